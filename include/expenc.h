@@ -1,0 +1,214 @@
+/*
+ * expenc.h -- C ABI of the MI355X (gfx950) expanded-encoding compressed-sensing
+ * reconstruction library (libexpenc.so).
+ *
+ * The library solves eq. 1 of Varela-Mattatall, Dubovan et al. ("High-resolution
+ * single-shot spiral diffusion-weighted imaging at 7T using expanded encoding
+ * with compressed sensing"):
+ *
+ *     x_hat = argmin_x ||A_exp x - y||_2^2 + lambda ||W x||_1
+ *
+ * where A_exp is the expanded encoding operator.  The paper describes A_exp
+ * (Introduction; Methods 2.1) as a signal model that includes a static B0 map,
+ * the dynamic field measured by field probes and expanded in spherical
+ * harmonics up to 2nd or 3rd order, and the coil sensitivities, for an
+ * arbitrary trajectory.  Written out, for coil c, sample t and pixel r:
+ *
+ *     A[(t,c), r] = S_c(r) * exp(i * phi(t,r)),
+ *     phi(t,r)    = sum_{l<L} k_l(t) * b_l(r) + dw0(r) * t.
+ *
+ * Conventions for every entry point:
+ *   - Array pointers are DEVICE pointers owned by the caller; the library
+ *     never allocates, frees or retains caller memory.  Scratch memory is a
+ *     caller-provided workspace whose size comes from expenc_workspace_size.
+ *   - Complex arrays are interleaved complex64 (re, im as two floats), the
+ *     layout of torch.complex64.  Field/geometry arrays are float64.
+ *   - Images are row-major [ny][nx] (x fastest); R = nx*ny.  k-space is
+ *     sample-major [T][C] (coils fastest); a batch of B problems that share
+ *     one operator is stacked in front: x [B][R], y [B][T][C].
+ *   - Every call is stream-ordered and asynchronous on `stream` (a
+ *     hipStream_t passed as void*; NULL is the default stream).  Argument
+ *     validation happens on the host before any HIP call and is reported
+ *     synchronously; launch failures are reported as EXPENC_EHIP.
+ *   - On a non-OK status, expenc_last_error() returns a thread-local message.
+ *   - Calls on distinct workspaces are independent; calls that share a
+ *     workspace must be ordered by the caller (same stream).
+ */
+#ifndef EXPENC_H
+#define EXPENC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  EXPENC_OK = 0,
+  EXPENC_EINVAL = -1,        /* bad argument (null pointer, size, enum)          */
+  EXPENC_EWORKSPACE = -2,    /* workspace missing or smaller than required       */
+  EXPENC_EHIP = -3,          /* a HIP runtime call or kernel launch failed       */
+  EXPENC_EUNSUPPORTED = -4,  /* valid but unsupported combination                */
+  EXPENC_ENONFINITE = -5     /* a solve produced NaN/Inf (reported after sync)   */
+};
+
+/* Arithmetic form of the encoding contraction. */
+enum {
+  EXPENC_FP32 = 0,        /* FP32 phase tile x FP32 operand on FP32 MFMA              */
+  EXPENC_BF16_SPLIT = 1,  /* both operands split hi+lo in bf16, 3 MFMA products      */
+  EXPENC_FP16_SPLIT = 2   /* both operands split hi+lo in fp16, 3 MFMA products      */
+};
+
+/* Wavelet families (periodised, orthonormal, separable 2D). */
+enum {
+  EXPENC_HAAR = 0,        /* h = [1, 1]/sqrt(2)                                    */
+  EXPENC_DB4 = 1          /* 8-tap Daubechies, 4 vanishing moments, extremal phase */
+};
+
+/* What a workspace query is for. */
+enum {
+  EXPENC_WS_FORWARD = 0,
+  EXPENC_WS_ADJOINT = 1,
+  EXPENC_WS_FISTA = 2,
+  EXPENC_WS_LIPSCHITZ = 3,
+  EXPENC_WS_CG = 4,
+  EXPENC_WS_FIELD_GRAD = 5
+};
+
+/*
+ * One expanded-encoding operator (the entry formula above).  B problems may
+ * share it (same field, same coils), in which case their coil data form the
+ * columns of one contraction.
+ */
+typedef struct expenc_op {
+  int32_t nx, ny;          /* image grid; R = nx*ny                                  */
+  int32_t ncoils;          /* C >= 1                                                  */
+  int32_t nbasis;          /* L in [0, 16]: number of field basis terms              */
+  int64_t nsamples;        /* T >= 1                                                  */
+  const double *basis;     /* [L][R] b_l(r) (basis units, e.g. m^degree); may be NULL if L == 0 */
+  const double *coef;      /* [T][L] k_l(t) in rad per basis unit; may be NULL if L == 0 */
+  const double *time;      /* [T] seconds from the first sample                      */
+  const double *dw0;       /* [R] off-resonance in rad/s, or NULL for none           */
+  const float *smaps;      /* [C][R] complex64 coil sensitivities S_c(r)             */
+} expenc_op;
+
+/*
+ * Real solid-harmonic field basis on the pixel grid (Introduction: field
+ * dynamics expanded in spherical harmonics up to 2nd or 3rd order).
+ * Writes basis[L][R] (float64): pixel centres x_i = (i - nx/2)*fov_x/nx,
+ * y_j = (j - ny/2)*fov_y/ny, slice at z = z0 (metres).  Term order:
+ * 1; x, y, z; xy, yz, 2z^2-x^2-y^2, xz, x^2-y^2; 3x^2y-y^3, xyz,
+ * y(4z^2-x^2-y^2), z(2z^2-3x^2-3y^2), x(4z^2-x^2-y^2), z(x^2-y^2), x^3-3xy^2.
+ * nbasis 9 = up to 2nd order, 16 = up to 3rd order.
+ */
+int expenc_sh_basis(int32_t nx, int32_t ny, double fov_x, double fov_y, double z0,
+                    int32_t nbasis, double *basis, void *stream);
+
+/* Bytes of workspace needed by the call `what` for this operator, batch and
+ * precision (for EXPENC_WS_FISTA also the wavelet grid nx_pad x ny_pad; pass
+ * 0 for the default).  Returns 0 on invalid arguments. */
+size_t expenc_workspace_size(const expenc_op *op, int32_t batch, int32_t precision,
+                             int32_t what, int32_t nx_pad, int32_t ny_pad);
+
+/*
+ * y = A_exp x (eq. 1's encoding operator).  x: [B][R] complex64,
+ * y: [B][T][C] complex64 (overwritten).  precision: EXPENC_FP32 or a split form.
+ */
+int expenc_forward(const expenc_op *op, int32_t batch, int32_t precision,
+                   const float *x, float *y, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * x = A_exp^H y, the adjoint (the paper's A^T in W A^T y, Methods 2.1):
+ * x[b][r] = sum_c conj(S_c(r)) sum_t exp(-i phi(t,r)) y[b][t][c].
+ * y: [B][T][C], x: [B][R] (overwritten).
+ */
+int expenc_adjoint(const expenc_op *op, int32_t batch, int32_t precision,
+                   const float *y, float *x, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Lipschitz constant of the gradient of ||A x - y||^2: L = 2 lambda_max(A^H A),
+ * by n_iter normalised power steps v <- A^H A v / ||A^H A v|| from the
+ * caller's start vector v0 [R] complex64, then the Rayleigh quotient
+ * (FP64 reductions).  Writes L to *lipschitz_out (a DEVICE float64 scalar).
+ */
+int expenc_lipschitz(const expenc_op *op, int32_t precision, int32_t n_iter, const float *v0,
+                     double *lipschitz_out, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Forward 2D wavelet transform W (eq. 1's sparsifying transform), periodised
+ * orthonormal separable, `levels` levels, Mallat layout (coarsest LL block at
+ * the top-left).  One level on a periodic length-n line v:
+ *   a[m] = sum_k h[k] v[(2m+k) mod n],  d[m] = sum_k g[k] v[(2m+k) mod n],
+ *   g[k] = (-1)^k h[M-1-k];  rows first, then columns, on the current LL block.
+ * x, w: [B][ny][nx] complex64; nx, ny multiples of 2^levels; w may equal x.
+ */
+int wavelet_fwd(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch,
+                const float *x, float *w, void *stream);
+
+/* Inverse (= adjoint) of wavelet_fwd; x may equal w. */
+int wavelet_inv(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch,
+                const float *w, float *x, void *stream);
+
+/*
+ * Proximal map of tau * sum_detail |w_i| (the l1 term of eq. 1 in the wavelet
+ * domain, complex modulus): every detail coefficient becomes
+ * w * max(0, 1 - tau/|w|); the coarsest LL block (ny>>levels x nx>>levels)
+ * passes through.  w_in, w_out: [B][ny][nx]; w_out may equal w_in.
+ */
+int soft_threshold(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w_in,
+                   float *w_out, float tau, void *stream);
+
+/* Options of fista_solve / cg_solve. */
+typedef struct expenc_fista_opts {
+  int32_t n_iter;          /* iterations K (Methods 2.1 uses 100)                    */
+  int32_t precision;       /* EXPENC_FP32 / EXPENC_BF16_SPLIT / EXPENC_FP16_SPLIT    */
+  int32_t wavelet;         /* EXPENC_HAAR / EXPENC_DB4                               */
+  int32_t levels;          /* J >= 1                                                 */
+  int32_t nx_pad, ny_pad;  /* wavelet grid (>= nx, ny, multiples of 2^J); 0 = round up */
+  int32_t ista;            /* 1: momentum off (t_k = 1), monotone ISTA               */
+  int32_t refine_every;    /* split forms: exact FP32 gradient every m iterations (0 = 10) */
+  int32_t n_power;         /* power steps when lipschitz <= 0                        */
+  int32_t reserved;
+  double lipschitz;        /* > 0: L to use; <= 0: estimate from power_v0            */
+  double lambda;           /* >= 0: lambda to use; < 0: lambda_factor * max|A^H y|   */
+  double lambda_factor;    /* used when lambda < 0 (e.g. 1e-3)                       */
+  const float *power_v0;   /* device [R] complex64 power-iteration start (lipschitz <= 0) */
+  double *objective;       /* device [B][n_iter] float64 objective trace, or NULL    */
+  double *scalars;         /* device [2 + 2B] float64: L, tau(b=0), lambda[B], ..., or NULL */
+} expenc_fista_opts;
+
+/*
+ * CS reconstruction: FISTA on eq. 1 exactly as written (no 1/2 on the data
+ * term), Methods 2.1.  With f(x) = ||A crop(x) - y||^2, L the Lipschitz
+ * constant of grad f and tau = lambda/L, from x_0 = z_1 = 0, t_1 = 1:
+ *   x_k     = W^H S_tau( W (z_k - grad f(z_k)/L) )
+ *   t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+ *   z_{k+1} = x_k + (t_k - 1)/t_{k+1} (x_k - x_{k-1})
+ * for exactly n_iter iterations.  The image lives on an nx_pad x ny_pad grid
+ * whose top-left nx x ny block is encoded.  y: [B][T][C]; x: [B][ny][nx]
+ * (crop of x_K, overwritten).  The iteration loop is captured once into a
+ * HIP graph and replayed on `stream`; L, lambda and tau stay on the device.
+ * Split precisions use an anchored gradient: an FP32 gradient at z_ref is
+ * refreshed every refine_every iterations and the split operators only
+ * apply A^H A to z_k - z_ref.
+ */
+int fista_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
+                const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Least-squares reconstruction by conjugate gradients on A^H A x = A^H y
+ * from x = 0, stopped after n_iter iterations (Methods 2.1: early stopping
+ * at 20 iterations as implicit regularisation).  Uses opts->n_iter and
+ * opts->precision only.  y: [B][T][C]; x: [B][R].
+ */
+int cg_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
+             const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/* Thread-local text of the last non-OK status of this thread. */
+const char *expenc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXPENC_H */

@@ -1,0 +1,519 @@
+// Expanded encoding operator A_exp and its adjoint on gfx950.
+//
+// The entry of A_exp (eq. 1; the Introduction and Methods 2.1 list its
+// ingredients: B0 map, spherical-harmonic field dynamics, coil maps, any
+// trajectory) is
+//     A[(t,c), r] = S_c(r) exp(i phi(t,r)),  phi = sum_l k_l(t) b_l(r) + dw0(r) t.
+// Both operators are evaluated as complex GEMMs whose phase tile E = exp(i phi)
+// is generated on the fly and never stored:
+//   forward  Y[t, col] = sum_r E(t,r) Z[r, col],        Z[r, b*C+c] = S_c(r) x_b(r)
+//   adjoint  X[r, col] = sum_t conj(E(t,r)) Y[t, col],  x_b(r) = sum_c conj(S_c(r)) X[r, b*C+c]
+// Phase in turns: kap[t][.] = (k_l(t)/2pi, t), bet[r][.] = (b_l(r), dw0(r)/2pi);
+// phi/2pi = sum_j kap[t][j] bet[r][j] is accumulated in FP64 (|phi| reaches
+// tens of turns, and the sine needs ~1e-8 turn accuracy), reduced to [0,1)
+// with v_fract_f64, and fed to the hardware v_sin/v_cos (argument in turns).
+//
+// FP32 form: v_mfma_f32_32x32x2_f32.  A wave owns 64 output rows (two 32-row
+// MFMA blocks) and walks the reduction index two at a time.  Every lane
+// evaluates two distinct phase entries (its own row, two reduction indices
+// shared by the whole wave, whose basis/field values arrive through scalar
+// loads); v_permlane32_swap then moves them into the A-operand layout
+// (lane l holds A[l%32][l/32]).  The B operand holds 16 columns x (re, im)
+// per 32-wide block: [Zr|Zi] against cos and [-Zi|Zr] against sin give
+// [Yr|Yi] in one accumulator.  The reduction index is split across
+// workgroups (split-K); partial sums are added in fixed order afterwards,
+// so results are bitwise reproducible.
+#include <cmath>
+#include <cstdio>
+
+#include "internal.h"
+
+namespace expenc {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+static constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
+
+// ---------------------------------------------------------------------------
+// Setup kernels
+// ---------------------------------------------------------------------------
+
+__global__ void k_prep_kap(const double *__restrict__ coef, const double *__restrict__ time,
+                           double *__restrict__ kap, int64_t T, int64_t Tp, int L, int NT) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Tp * NT) return;
+  int64_t t = i / NT;
+  int j = (int)(i % NT);
+  double v = 0.0;
+  if (t < T) {
+    if (j < L) v = coef[t * L + j] * kInv2Pi;
+    else if (j == L) v = time[t];
+  }
+  kap[i] = v;
+}
+
+__global__ void k_prep_bet(const double *__restrict__ basis, const double *__restrict__ dw0,
+                           double *__restrict__ bet, int R, int Rp, int L, int NT) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Rp * NT) return;
+  int r = (int)(i / NT);
+  int j = (int)(i % NT);
+  double v = 0.0;
+  if (r < R) {
+    if (j < L) v = basis[(int64_t)j * R + r];
+    else if (j == L && dw0) v = dw0[r] * kInv2Pi;
+  }
+  bet[i] = v;
+}
+
+// Z[r][col] = S_c(r) * x_b(r), col = b*C + c; zero for padded pixels/columns.
+__global__ void k_build_z_f32(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
+                              int64_t x_stride, int x_row_stride, int nx, int R, int Rp, int C,
+                              int NC, int NCP, float2 *__restrict__ z) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Rp * NCP) return;
+  int r = (int)(i / NCP);
+  int col = (int)(i % NCP);
+  float2 v = make_float2(0.f, 0.f);
+  if (r < R && col < NC) {
+    int b = col / C, c = col % C;
+    int yy = r / nx, xx = r % nx;
+    float2 s = smaps[(int64_t)c * R + r];
+    float2 u = x[b * x_stride + (int64_t)yy * x_row_stride + xx];
+    v = make_float2(s.x * u.x - s.y * u.y, s.x * u.y + s.y * u.x);
+  }
+  z[i] = v;
+}
+
+// Y operand [Tp][NCP] from y [B][T][C].
+__global__ void k_pack_y_f32(const float2 *__restrict__ y, int64_t T, int64_t Tp, int C, int NC,
+                             int NCP, float2 *__restrict__ yop) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Tp * NCP) return;
+  int64_t t = i / NCP;
+  int col = (int)(i % NCP);
+  float2 v = make_float2(0.f, 0.f);
+  if (t < T && col < NC) {
+    int b = col / C, c = col % C;
+    v = y[((int64_t)b * T + t) * C + c];
+  }
+  yop[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// FP32 contraction kernels
+// ---------------------------------------------------------------------------
+
+// Forward: rows = samples, reduction over pixels.
+template <int NT, int GW>
+__global__ __launch_bounds__(256) void k_fwd_f32(const double *__restrict__ kap,
+                                                 const double *__restrict__ bet,
+                                                 const float2 *__restrict__ zop,
+                                                 float *__restrict__ part, int64_t Tp, int Rp,
+                                                 int NCP, int chunk, int nsplit) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+
+  double kv[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) kv[j] = kap[(row0 + lane) * NT + j];
+
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+
+  const int r0 = split * chunk;
+  const int r1 = min(Rp, r0 + chunk);
+  const float2 *zl = zop + (int64_t)half * NCP + g0 * 16 + c16;
+#pragma unroll 2
+  for (int r = r0; r < r1; r += 2) {
+    const double *ba = bet + (int64_t)r * NT;
+    double pa = 0.0, pb = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      pa = fma(kv[j], ba[j], pa);
+      pb = fma(kv[j], ba[NT + j], pb);
+    }
+    const float fa = (float)__builtin_amdgcn_fract(pa);
+    const float fb = (float)__builtin_amdgcn_fract(pb);
+    const float ca = __builtin_amdgcn_cosf(fa), sa = __builtin_amdgcn_sinf(fa);
+    const float cb = __builtin_amdgcn_cosf(fb), sb = __builtin_amdgcn_sinf(fb);
+    const auto cc = __builtin_amdgcn_permlane32_swap(__float_as_uint(ca), __float_as_uint(cb), false, false);
+    const auto ss = __builtin_amdgcn_permlane32_swap(__float_as_uint(sa), __float_as_uint(sb), false, false);
+    const float c_lo = __uint_as_float(cc[0]), c_hi = __uint_as_float(cc[1]);
+    const float s_lo = __uint_as_float(ss[0]), s_hi = __uint_as_float(ss[1]);
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+      const float2 z = zl[(int64_t)r * NCP + g * 16];
+      const float b1 = im ? z.y : z.x;
+      const float b2 = im ? z.x : -z.y;
+      acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_lo, b1, acc[0][g], 0, 0, 0);
+      acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_hi, b1, acc[1][g], 0, 0, 0);
+      acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_lo, b2, acc[0][g], 0, 0, 0);
+      acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_hi, b2, acc[1][g], 0, 0, 0);
+    }
+  }
+
+  float *dst = part + (int64_t)split * Tp * NCP * 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        const int col = (g0 + g) * 16 + c16;
+        dst[(row * NCP + col) * 2 + im] = acc[a][g][v];
+      }
+}
+
+// Adjoint: rows = pixels, reduction over samples.
+template <int NT, int GW>
+__global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
+                                                 const double *__restrict__ bet,
+                                                 const float2 *__restrict__ yop,
+                                                 float *__restrict__ part, int Rp, int64_t Tp,
+                                                 int NCP, int chunk, int nsplit) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+
+  double bv[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) bv[j] = bet[(row0 + lane) * NT + j];
+
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+
+  const int64_t t0 = (int64_t)split * chunk;
+  const int64_t t1 = min(Tp, t0 + chunk);
+  const float2 *yl = yop + (int64_t)half * NCP + g0 * 16 + c16;
+#pragma unroll 2
+  for (int64_t t = t0; t < t1; t += 2) {
+    const double *ka = kap + t * NT;
+    double pa = 0.0, pb = 0.0;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+      pa = fma(ka[j], bv[j], pa);
+      pb = fma(ka[NT + j], bv[j], pb);
+    }
+    const float fa = (float)__builtin_amdgcn_fract(pa);
+    const float fb = (float)__builtin_amdgcn_fract(pb);
+    const float ca = __builtin_amdgcn_cosf(fa), sa = __builtin_amdgcn_sinf(fa);
+    const float cb = __builtin_amdgcn_cosf(fb), sb = __builtin_amdgcn_sinf(fb);
+    const auto cc = __builtin_amdgcn_permlane32_swap(__float_as_uint(ca), __float_as_uint(cb), false, false);
+    const auto ss = __builtin_amdgcn_permlane32_swap(__float_as_uint(sa), __float_as_uint(sb), false, false);
+    const float c_lo = __uint_as_float(cc[0]), c_hi = __uint_as_float(cc[1]);
+    const float s_lo = __uint_as_float(ss[0]), s_hi = __uint_as_float(ss[1]);
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+      const float2 y = yl[t * NCP + g * 16];
+      // conj(E) * Y = Er*[Yr|Yi] + Ei*[Yi|-Yr]
+      const float b1 = im ? y.y : y.x;
+      const float b2 = im ? -y.x : y.y;
+      acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_lo, b1, acc[0][g], 0, 0, 0);
+      acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_hi, b1, acc[1][g], 0, 0, 0);
+      acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_lo, b2, acc[0][g], 0, 0, 0);
+      acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_hi, b2, acc[1][g], 0, 0, 0);
+    }
+  }
+
+  float *dst = part + (int64_t)split * Rp * NCP * 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        const int col = (g0 + g) * 16 + c16;
+        dst[(row * NCP + col) * 2 + im] = acc[a][g][v];
+      }
+}
+
+// ---------------------------------------------------------------------------
+// Split-K reductions (fixed summation order)
+// ---------------------------------------------------------------------------
+
+__global__ void k_fwd_reduce_out(const float2 *__restrict__ part, int nsplit, int64_t T,
+                                 int64_t Tp, int C, int NC, int NCP, float2 *__restrict__ y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= T * NC) return;
+  int64_t t = i / NC;
+  int col = (int)(i % NC);
+  float2 s = make_float2(0.f, 0.f);
+  for (int k = 0; k < nsplit; ++k) {
+    float2 v = part[((int64_t)k * Tp + t) * NCP + col];
+    s.x += v.x;
+    s.y += v.y;
+  }
+  int b = col / C, c = col % C;
+  y[((int64_t)b * T + t) * C + c] = s;
+}
+
+// Residual into the adjoint operand: yop[t][col] = sum_split part - y_meas
+// (y_meas may be NULL: then yop = A z).  Padded rows/columns are zero.
+__global__ void k_fwd_residual(const float2 *__restrict__ part, int nsplit, int64_t T, int64_t Tp,
+                               int C, int NC, int NCP, const float2 *__restrict__ y_meas,
+                               float2 *__restrict__ yop) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Tp * NCP) return;
+  int64_t t = i / NCP;
+  int col = (int)(i % NCP);
+  float2 s = make_float2(0.f, 0.f);
+  if (t < T && col < NC) {
+    for (int k = 0; k < nsplit; ++k) {
+      float2 v = part[((int64_t)k * Tp + t) * NCP + col];
+      s.x += v.x;
+      s.y += v.y;
+    }
+    if (y_meas) {
+      const int b = col / C, c = col % C;
+      const float2 m = y_meas[((int64_t)b * T + t) * C + c];
+      s.x -= m.x;
+      s.y -= m.y;
+    }
+  }
+  yop[i] = s;
+}
+
+// x_b(r) = alpha * sum_c conj(S_c(r)) sum_split part[split][r][b*C+c].
+// Block: 8 pixels x 32 lanes; lanes stride over coils, then a shuffle sum.
+__global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict__ part, int nsplit,
+                                                        int R, int Rp, int nx, int C, int B, int NCP,
+                                                        const float2 *__restrict__ smaps,
+                                                        float2 *__restrict__ x, int64_t x_stride,
+                                                        int x_row_stride, const double *__restrict__ alpha_dev,
+                                                        const float2 *__restrict__ add) {
+  const int sub = threadIdx.x & 31;
+  const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
+  if (r >= R) return;  // uniform per 32-lane group
+  for (int b = 0; b < B; ++b) {
+    float sx = 0.f, sy = 0.f;
+    for (int c = sub; c < C; c += 32) {
+      const int col = b * C + c;
+      float2 u = make_float2(0.f, 0.f);
+      for (int k = 0; k < nsplit; ++k) {
+        float2 v = part[((int64_t)k * Rp + r) * NCP + col];
+        u.x += v.x;
+        u.y += v.y;
+      }
+      float2 s = smaps[(int64_t)c * R + r];
+      sx += s.x * u.x + s.y * u.y;  // conj(s) * u
+      sy += s.x * u.y - s.y * u.x;
+    }
+#pragma unroll
+    for (int o = 16; o > 0; o >>= 1) {
+      sx += __shfl_xor(sx, o, 32);
+      sy += __shfl_xor(sy, o, 32);
+    }
+    if (sub == 0) {
+      const int yy = r / nx, xx = r % nx;
+      const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
+      const float alpha = alpha_dev ? (float)*alpha_dev : 1.f;
+      float2 v = make_float2(alpha * sx, alpha * sy);
+      if (add) {
+        v.x += add[o].x;
+        v.y += add[o].y;
+      }
+      x[o] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static int phase_terms(int L) {
+  if (L + 1 <= 4) return 4;
+  if (L + 1 <= 10) return 10;
+  return 17;
+}
+
+static int target_workgroups() {
+  static int v = [] {
+    const char *e = getenv("EXPENC_TARGET_WG");
+    int t = e ? atoi(e) : 0;
+    return t > 0 ? t : 1024;
+  }();
+  return v;
+}
+
+int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p) {
+  if (!op) return fail(EXPENC_EINVAL, "operator descriptor is NULL");
+  if (op->nx < 1 || op->ny < 1) return fail(EXPENC_EINVAL, "image grid %dx%d is empty", op->nx, op->ny);
+  if ((int64_t)op->nx * op->ny > (1 << 26)) return fail(EXPENC_EINVAL, "image grid too large");
+  if (op->ncoils < 1) return fail(EXPENC_EINVAL, "ncoils must be >= 1 (got %d)", op->ncoils);
+  if (op->nbasis < 0 || op->nbasis > 16) return fail(EXPENC_EINVAL, "nbasis must be in [0,16] (got %d)", op->nbasis);
+  if (op->nsamples < 1 || op->nsamples > (int64_t(1) << 31)) return fail(EXPENC_EINVAL, "nsamples out of range");
+  if (op->nbasis > 0 && (!op->basis || !op->coef)) return fail(EXPENC_EINVAL, "basis/coef NULL with nbasis > 0");
+  if (!op->time) return fail(EXPENC_EINVAL, "time array is NULL");
+  if (!op->smaps) return fail(EXPENC_EINVAL, "smaps is NULL");
+  if (batch < 1) return fail(EXPENC_EINVAL, "batch must be >= 1 (got %d)", batch);
+  if (precision != EXPENC_FP32 && precision != EXPENC_BF16_SPLIT && precision != EXPENC_FP16_SPLIT)
+    return fail(EXPENC_EINVAL, "unknown precision %d", precision);
+  if ((int64_t)op->ncoils * batch > 4096) return fail(EXPENC_EUNSUPPORTED, "ncoils*batch > 4096");
+  EncPlan q;
+  q.nx = op->nx;
+  q.ny = op->ny;
+  q.R = op->nx * op->ny;
+  q.Rp = (int32_t)round_up(q.R, 256);
+  q.T = op->nsamples;
+  q.Tp = round_up(q.T, 256);
+  q.C = op->ncoils;
+  q.B = batch;
+  q.NC = q.C * q.B;
+  q.G = (int32_t)ceil_div(q.NC, 16);
+  q.GW = q.G >= 2 ? 2 : 1;
+  q.NGY = (int32_t)ceil_div(q.G, q.GW);
+  q.NCP = q.NGY * q.GW * 16;  // every wave's column groups exist (zero-filled past NC)
+  q.L = op->nbasis;
+  q.NT = phase_terms(q.L);
+  q.prec = precision;
+  q.has_dw0 = op->dw0 != nullptr;
+  if (precision != EXPENC_FP32) return fail(EXPENC_EUNSUPPORTED, "split precision not available in this build");
+  const int tgt = target_workgroups();
+  // forward: 256 sample rows per workgroup, split over pixels
+  {
+    int64_t nrb = q.Tp / 256;
+    int64_t want = ceil_div(tgt, nrb * q.NGY);
+    want = std::max<int64_t>(1, std::min<int64_t>(want, q.Rp / 16));
+    q.fwd_chunk = (int32_t)round_up(ceil_div(q.Rp, want), 16);
+    q.fwd_split = (int32_t)ceil_div(q.Rp, q.fwd_chunk);
+  }
+  // adjoint: 256 pixel rows per workgroup, split over samples
+  {
+    int64_t nrb = q.Rp / 256;
+    int64_t want = ceil_div(tgt, nrb * q.NGY);
+    want = std::max<int64_t>(1, std::min<int64_t>(want, q.Tp / 16));
+    q.adj_chunk = (int32_t)round_up(ceil_div(q.Tp, want), 16);
+    q.adj_split = (int32_t)ceil_div(q.Tp, q.adj_chunk);
+  }
+  *p = q;
+  return EXPENC_OK;
+}
+
+size_t enc_operand_bytes(const EncPlan &p) {
+  Arena a;
+  EncBuffers b;
+  carve_enc(p, a, &b);
+  return a.used + 256;
+}
+
+int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b) {
+  b->kap = a.take<double>((size_t)p.Tp * p.NT);
+  b->bet = a.take<double>((size_t)p.Rp * p.NT);
+  b->zop = a.take<float2>((size_t)p.Rp * p.NCP);
+  b->yop = a.take<float2>((size_t)p.Tp * p.NCP);
+  size_t pf = (size_t)p.fwd_split * p.Tp * p.NCP;
+  size_t pa = (size_t)p.adj_split * p.Rp * p.NCP;
+  b->part = a.take<float2>(std::max(pf, pa));
+  return a.ok() ? EXPENC_OK : EXPENC_EWORKSPACE;
+}
+
+static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)ceil_div(n, bs); }
+
+int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
+  k_prep_kap<<<blocks_for(p.Tp * p.NT, 256), 256, 0, s>>>(op->coef, op->time, b.kap, p.T, p.Tp, p.L, p.NT);
+  EX_LAUNCHED("prep_kap");
+  k_prep_bet<<<blocks_for((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L, p.NT);
+  EX_LAUNCHED("prep_bet");
+  return EXPENC_OK;
+}
+
+int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x_stride,
+                int32_t x_row_stride, const EncBuffers &b, hipStream_t s) {
+  k_build_z_f32<<<blocks_for((int64_t)p.Rp * p.NCP, 256), 256, 0, s>>>(
+      reinterpret_cast<const float2 *>(smaps), x, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC,
+      p.NCP, b.zop);
+  EX_LAUNCHED("build_z");
+  return EXPENC_OK;
+}
+
+int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s) {
+  k_pack_y_f32<<<blocks_for(p.Tp * p.NCP, 256), 256, 0, s>>>(y, p.T, p.Tp, p.C, p.NC, p.NCP, b.yop);
+  EX_LAUNCHED("pack_y");
+  return EXPENC_OK;
+}
+
+template <int NT>
+static void launch_fwd(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY);
+  float *part = reinterpret_cast<float *>(b.part);
+  if (p.GW == 2)
+    k_fwd_f32<NT, 2><<<grid, 256, 0, s>>>(b.kap, b.bet, b.zop, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk, p.fwd_split);
+  else
+    k_fwd_f32<NT, 1><<<grid, 256, 0, s>>>(b.kap, b.bet, b.zop, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk, p.fwd_split);
+}
+
+template <int NT>
+static void launch_adj(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY);
+  float *part = reinterpret_cast<float *>(b.part);
+  if (p.GW == 2)
+    k_adj_f32<NT, 2><<<grid, 256, 0, s>>>(b.kap, b.bet, b.yop, part, p.Rp, p.Tp, p.NCP, p.adj_chunk, p.adj_split);
+  else
+    k_adj_f32<NT, 1><<<grid, 256, 0, s>>>(b.kap, b.bet, b.yop, part, p.Rp, p.Tp, p.NCP, p.adj_chunk, p.adj_split);
+}
+
+int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  switch (p.NT) {
+    case 4: launch_fwd<4>(p, b, s); break;
+    case 10: launch_fwd<10>(p, b, s); break;
+    default: launch_fwd<17>(p, b, s); break;
+  }
+  EX_LAUNCHED("forward contraction");
+  return EXPENC_OK;
+}
+
+int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  switch (p.NT) {
+    case 4: launch_adj<4>(p, b, s); break;
+    case 10: launch_adj<10>(p, b, s); break;
+    default: launch_adj<17>(p, b, s); break;
+  }
+  EX_LAUNCHED("adjoint contraction");
+  return EXPENC_OK;
+}
+
+int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s) {
+  k_fwd_reduce_out<<<blocks_for(p.T * p.NC, 256), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC, p.NCP, y);
+  EX_LAUNCHED("forward reduce");
+  return EXPENC_OK;
+}
+
+int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s) {
+  k_fwd_residual<<<blocks_for(p.Tp * p.NCP, 256), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC,
+                                                                p.NCP, y_meas, b.yop);
+  EX_LAUNCHED("forward residual");
+  return EXPENC_OK;
+}
+
+int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
+                           int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
+                           const float2 *add, hipStream_t s) {
+  k_adj_reduce_out<<<blocks_for(p.R, 8), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
+                                                      reinterpret_cast<const float2 *>(smaps), x, x_stride,
+                                                      x_row_stride, alpha_dev, add);
+  EX_LAUNCHED("adjoint reduce");
+  return EXPENC_OK;
+}
+
+}  // namespace expenc

@@ -1,0 +1,108 @@
+// Internal helpers shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "expenc.h"
+
+namespace expenc {
+
+void set_error(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
+int fail(int status, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define EX_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return ::expenc::fail(EXPENC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+#define EX_LAUNCHED(name)                                                              \
+  do {                                                                                 \
+    hipError_t e_ = hipGetLastError();                                                 \
+    if (e_ != hipSuccess)                                                              \
+      return ::expenc::fail(EXPENC_EHIP, "launch of %s failed: %s", name, hipGetErrorString(e_)); \
+  } while (0)
+
+#define EX_TRY(expr)              \
+  do {                            \
+    int s_ = (expr);              \
+    if (s_ != EXPENC_OK) return s_; \
+  } while (0)
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+inline int64_t ceil_div(int64_t v, int64_t m) { return (v + m - 1) / m; }
+
+// Bump allocator over the caller's workspace (256-byte aligned slices).
+struct Arena {
+  char *base = nullptr;
+  size_t size = 0;
+  size_t used = 0;
+  template <class T>
+  T *take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return (base && used <= size) ? reinterpret_cast<T *>(base + off) : nullptr;
+  }
+  bool ok() const { return used <= size; }
+};
+
+// Geometry of one encoding contraction: a GEMM-shaped sum over pixels
+// (forward) or samples (adjoint) with B*C complex columns, padded so that
+// the kernels never test bounds inside their loops.
+struct EncPlan {
+  int32_t nx = 0, ny = 0, R = 0, Rp = 0;  // pixels, padded to a multiple of 256
+  int64_t T = 0, Tp = 0;                  // samples, padded to a multiple of 256
+  int32_t C = 0, B = 0, NC = 0;           // coils, batch, columns = B*C
+  int32_t G = 0, NCP = 0;                 // 16-column groups, padded columns = 16*GW*NGY
+  int32_t GW = 0, NGY = 0;                // groups per wave, grid y = ceil(G/GW)
+  int32_t L = 0, NT = 0;                  // basis terms, phase terms per entry (padded L+1)
+  int32_t prec = 0;
+  int32_t fwd_split = 1, fwd_chunk = 0;   // split-K over pixels
+  int32_t adj_split = 1, adj_chunk = 0;   // split-K over samples
+  bool has_dw0 = false;
+};
+
+int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p);
+
+// Device buffers of one operator application, carved from the workspace.
+struct EncBuffers {
+  double *kap = nullptr;   // [Tp][NT] field coefficients in turns (+ time)
+  double *bet = nullptr;   // [Rp][NT] basis values (+ dw0 in turns/s)
+  float2 *zop = nullptr;   // forward operand: FP32 [Rp][NCP] or packed split
+  float2 *yop = nullptr;   // adjoint operand: FP32 [Tp][NCP] or packed split
+  float2 *part = nullptr;  // split-K partial sums (max of forward and adjoint)
+};
+
+size_t enc_operand_bytes(const EncPlan &p);
+int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b);
+
+// Kernel launchers (stream-ordered, no synchronisation).
+int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s);
+// Z[r][b*C+c] = S_c(r) x_b(r) from x [B][R] (x_stride elements between problems);
+// for split precisions, pre-split and packed in the MFMA operand order.
+int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x_stride,
+                int32_t x_row_stride, const EncBuffers &b, hipStream_t s);
+int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+// y[b][t][c] = sum_split partials (ABI layout)
+int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s);
+// Y operand from y [B][T][C]
+int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s);
+int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+// x_b(r) = alpha * sum_c conj(S_c(r)) sum_split partials (+ add_b(r)),
+// written to x [B] with x_stride between problems and row stride
+// x_row_stride (pixels); alpha = *alpha_dev (device FP64) or 1 if NULL.
+int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
+                           int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
+                           const float2 *add, hipStream_t s);
+// Residual r = A z - y (y_meas [B][T][C], or NULL for r = A z) written
+// straight into the adjoint operand.
+int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s);
+
+// Daubechies / Haar analysis low-pass filter, derived on the host.
+int wavelet_filter(int32_t wavelet, double *h, int *taps);
+
+}  // namespace expenc

@@ -1,0 +1,363 @@
+// Wavelet transform W of eq. 1 and the soft-threshold proximal step.
+//
+// Periodised, orthonormal, separable 2D transform with the Mallat layout.
+// One level on a periodic line v of even length n:
+//   a[m] = sum_k h[k] v[(2m+k) mod n],  d[m] = sum_k g[k] v[(2m+k) mod n],
+//   g[k] = (-1)^k h[M-1-k];
+// rows first, then columns, on the current top-left low-pass block.  The
+// inverse is the transpose: v[m] = sum over taps k with k = m (mod 2) of
+// h[k] a[i] + g[k] d[i], i = ((m-k) mod n)/2.
+//
+// Each pass is one launch that stages whole lines in LDS and writes them back
+// in place, so a multi-level transform needs no scratch buffer.  Row passes
+// use one workgroup per image row (a coalesced line of n complex values);
+// column passes stage a strip of 16 columns x n rows (128-byte coalesced
+// row segments).  The column pass of the analysis can apply the
+// soft-threshold to every detail coefficient it produces, because a level's
+// detail bands are final once its column pass is done.  These are HBM /
+// launch-bound kernels: no MFMA.
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "internal.h"
+#include "wavelet_dev.h"
+
+namespace expenc {
+
+// ---------------------------------------------------------------------------
+// Filters (host): Haar, and Daubechies with p = 4 vanishing moments by
+// spectral factorisation of P(y) = sum_{k<p} C(p-1+k, k) y^k, where
+// |m0(w)|^2 = cos^{2p}(w/2) P(sin^2(w/2)) and y = (2 - z - 1/z)/4.  Each root
+// y_k of P gives z^2 - (2 - 4 y_k) z + 1 = 0; the root with |z| < 1 is kept,
+// so H(z) = sum h[n] z^-n has its non-trivial zeros inside the unit circle.
+// ---------------------------------------------------------------------------
+
+static std::vector<std::complex<double>> poly_roots(const std::vector<double> &asc) {
+  // Durand-Kerner iteration on the monic polynomial with ascending coefficients asc.
+  const int n = (int)asc.size() - 1;
+  std::vector<std::complex<double>> c(n + 1);
+  for (int i = 0; i <= n; ++i) c[i] = asc[i] / asc[n];
+  std::vector<std::complex<double>> z(n);
+  const std::complex<double> seed(0.4, 0.9);
+  for (int i = 0; i < n; ++i) z[i] = std::pow(seed, i);
+  for (int it = 0; it < 500; ++it) {
+    double delta = 0;
+    for (int i = 0; i < n; ++i) {
+      std::complex<double> num = c[n];
+      for (int k = n - 1; k >= 0; --k) num = num * z[i] + c[k];
+      std::complex<double> den = 1.0;
+      for (int j = 0; j < n; ++j)
+        if (j != i) den *= (z[i] - z[j]);
+      std::complex<double> step = num / den;
+      z[i] -= step;
+      delta = std::max(delta, std::abs(step));
+    }
+    if (delta < 1e-17) break;
+  }
+  return z;
+}
+
+int wavelet_filter(int32_t wavelet, double *h, int *taps) {
+  if (wavelet == EXPENC_HAAR) {
+    h[0] = h[1] = 1.0 / std::sqrt(2.0);
+    *taps = 2;
+    return EXPENC_OK;
+  }
+  if (wavelet != EXPENC_DB4) return fail(EXPENC_EINVAL, "unknown wavelet %d", wavelet);
+  const int p = 4;
+  std::vector<double> pasc(p);
+  for (int k = 0; k < p; ++k) {
+    double binom = 1;  // C(p-1+k, k)
+    for (int i = 1; i <= k; ++i) binom = binom * (p - 1 + i) / i;
+    pasc[k] = binom;
+  }
+  auto yr = poly_roots(pasc);
+  // descending-power polynomial (1+z)^p prod (z - z_k)
+  std::vector<std::complex<double>> poly{1.0};
+  auto mul = [&](std::complex<double> a0, std::complex<double> a1) {  // times (a0*z + a1)
+    std::vector<std::complex<double>> out(poly.size() + 1, 0.0);
+    for (size_t i = 0; i < poly.size(); ++i) {
+      out[i] += poly[i] * a0;
+      out[i + 1] += poly[i] * a1;
+    }
+    poly.swap(out);
+  };
+  for (int i = 0; i < p; ++i) mul(1.0, 1.0);
+  for (auto yk : yr) {
+    std::complex<double> b = 2.0 - 4.0 * yk;
+    std::complex<double> disc = std::sqrt(b * b - 4.0);
+    std::complex<double> z1 = (b + disc) / 2.0, z2 = (b - disc) / 2.0;
+    mul(1.0, -(std::abs(z1) < 1.0 ? z1 : z2));
+  }
+  double sum = 0;
+  for (auto &c : poly) sum += c.real();
+  for (int i = 0; i < 2 * p; ++i) h[i] = poly[i].real() / sum * std::sqrt(2.0);
+  *taps = 2 * p;
+  return EXPENC_OK;
+}
+
+int make_filter_set(int32_t wavelet, FilterSet *f) {
+  double h[16];
+  int taps = 0;
+  EX_TRY(wavelet_filter(wavelet, h, &taps));
+  f->taps = taps;
+  for (int k = 0; k < taps; ++k) {
+    f->h[k] = (float)h[k];
+    f->g[k] = (float)(((k & 1) ? -1.0 : 1.0) * h[taps - 1 - k]);
+  }
+  return EXPENC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Kernels
+// ---------------------------------------------------------------------------
+
+// Analysis along rows of the top-left my x mx block.  src/dst: [B][ny][nx]
+// with row stride nx (elements); src may equal dst (the line is staged in
+// LDS before any store).  One workgroup per (row, image).
+__global__ __launch_bounds__(256) void k_dwt_rows(const float2 *src, float2 *dst,
+                                                  int nx, int ny, int mx, FilterSet f) {
+  extern __shared__ float2 line[];
+  const int row = blockIdx.x, b = blockIdx.y;
+  const float2 *s = src + ((int64_t)b * ny + row) * nx;
+  float2 *d = dst + ((int64_t)b * ny + row) * nx;
+  for (int i = threadIdx.x; i < mx; i += blockDim.x) line[i] = s[i];
+  __syncthreads();
+  const int half = mx >> 1;
+  for (int m = threadIdx.x; m < half; m += blockDim.x) {
+    float2 a = make_float2(0.f, 0.f), dd = make_float2(0.f, 0.f);
+    for (int k = 0; k < f.taps; ++k) {
+      int j = 2 * m + k;
+      if (j >= mx) j -= mx;
+      if (j >= mx) j %= mx;
+      const float2 v = line[j];
+      a.x += f.h[k] * v.x;
+      a.y += f.h[k] * v.y;
+      dd.x += f.g[k] * v.x;
+      dd.y += f.g[k] * v.y;
+    }
+    d[m] = a;
+    d[half + m] = dd;
+  }
+}
+
+// Synthesis along rows (inverse of k_dwt_rows).  Optionally fused FISTA
+// momentum: out = x_k; z = x_k + beta*(x_k - x_prev).
+__global__ __launch_bounds__(256) void k_idwt_rows(const float2 *src, float2 *dst,
+                                                   int nx, int ny, int mx, FilterSet f,
+                                                   const float2 *__restrict__ xprev,
+                                                   float2 *__restrict__ zout, float beta) {
+  extern __shared__ float2 line[];
+  const int row = blockIdx.x, b = blockIdx.y;
+  const int64_t base = ((int64_t)b * ny + row) * nx;
+  for (int i = threadIdx.x; i < mx; i += blockDim.x) line[i] = src[base + i];
+  __syncthreads();
+  const int half = mx >> 1;
+  for (int m = threadIdx.x; m < mx; m += blockDim.x) {
+    float2 v = make_float2(0.f, 0.f);
+    for (int k = (m & 1); k < f.taps; k += 2) {
+      int q = m - k;
+      q %= mx;
+      if (q < 0) q += mx;
+      const int i = q >> 1;
+      const float2 a = line[i], d = line[half + i];
+      v.x += f.h[k] * a.x + f.g[k] * d.x;
+      v.y += f.h[k] * a.y + f.g[k] * d.y;
+    }
+    dst[base + m] = v;
+    if (zout) {
+      const float2 p = xprev[base + m];
+      zout[base + m] = make_float2(v.x + beta * (v.x - p.x), v.y + beta * (v.y - p.y));
+    }
+  }
+}
+
+// Analysis along columns of the top-left my x mx block, in place, 16
+// columns per workgroup.  If tau != nullptr, every detail coefficient of
+// this level (outputs outside the next LL block) is soft-thresholded with
+// tau[b], and if l1 != nullptr the sum of their moduli after thresholding is
+// added (FP64) into l1_part[b][blockIdx.x] (for the objective).
+__global__ __launch_bounds__(256) void k_dwt_cols(float2 *__restrict__ w, int nx, int ny, int mx, int my,
+                                                  FilterSet f, const double *__restrict__ tau,
+                                                  double *__restrict__ l1_part, int l1_stride) {
+  extern __shared__ float2 strip[];  // [my][16]
+  const int b = blockIdx.y;
+  const int x0 = blockIdx.x * 16;
+  const int cx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int ncols = min(16, mx - x0);
+  float2 *img = w + (int64_t)b * ny * nx;
+  for (int i = ty; i < my; i += 16)
+    if (cx < ncols) strip[i * 16 + cx] = img[(int64_t)i * nx + x0 + cx];
+  __syncthreads();
+  const int half = my >> 1;
+  const float t = tau ? (float)tau[b] : 0.f;
+  double l1 = 0.0;
+  if (cx < ncols) {
+    const bool detail_col = (x0 + cx) >= (mx >> 1);
+    for (int m = ty; m < half; m += 16) {
+      float2 a = make_float2(0.f, 0.f), dd = make_float2(0.f, 0.f);
+      for (int k = 0; k < f.taps; ++k) {
+        int j = 2 * m + k;
+        if (j >= my) j %= my;
+        const float2 v = strip[j * 16 + cx];
+        a.x += f.h[k] * v.x;
+        a.y += f.h[k] * v.y;
+        dd.x += f.g[k] * v.x;
+        dd.y += f.g[k] * v.y;
+      }
+      if (tau) {
+        if (detail_col) {
+          a = soft(a, t);
+          l1 += sqrt((double)a.x * a.x + (double)a.y * a.y);
+        }
+        dd = soft(dd, t);
+        l1 += sqrt((double)dd.x * dd.x + (double)dd.y * dd.y);
+      }
+      img[(int64_t)m * nx + x0 + cx] = a;
+      img[(int64_t)(half + m) * nx + x0 + cx] = dd;
+    }
+  }
+  if (l1_part) {
+    // block reduction in fixed order
+    __shared__ double red[256];
+    red[threadIdx.x] = l1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) l1_part[(int64_t)b * l1_stride + blockIdx.x] = red[0];
+  }
+}
+
+// Synthesis along columns, in place.
+__global__ __launch_bounds__(256) void k_idwt_cols(float2 *__restrict__ w, int nx, int ny, int mx, int my,
+                                                   FilterSet f) {
+  extern __shared__ float2 strip[];
+  const int b = blockIdx.y;
+  const int x0 = blockIdx.x * 16;
+  const int cx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int ncols = min(16, mx - x0);
+  float2 *img = w + (int64_t)b * ny * nx;
+  for (int i = ty; i < my; i += 16)
+    if (cx < ncols) strip[i * 16 + cx] = img[(int64_t)i * nx + x0 + cx];
+  __syncthreads();
+  const int half = my >> 1;
+  if (cx < ncols) {
+    for (int m = ty; m < my; m += 16) {
+      float2 v = make_float2(0.f, 0.f);
+      for (int k = (m & 1); k < f.taps; k += 2) {
+        int q = (m - k) % my;
+        if (q < 0) q += my;
+        const int i = q >> 1;
+        const float2 a = strip[i * 16 + cx], d = strip[(half + i) * 16 + cx];
+        v.x += f.h[k] * a.x + f.g[k] * d.x;
+        v.y += f.h[k] * a.y + f.g[k] * d.y;
+      }
+      img[(int64_t)m * nx + x0 + cx] = v;
+    }
+  }
+}
+
+__global__ void k_soft(const float2 *__restrict__ in, float2 *__restrict__ out, int nx, int ny, int llx,
+                       int lly, int64_t total, float tau) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t p = i % ((int64_t)nx * ny);
+  const int yy = (int)(p / nx), xx = (int)(p % nx);
+  float2 v = in[i];
+  if (!(yy < lly && xx < llx)) v = soft(v, tau);
+  out[i] = v;
+}
+
+__global__ void k_copy2(const float2 *__restrict__ in, float2 *__restrict__ out, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i];
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static int check_grid(int32_t nx, int32_t ny, int32_t levels, int32_t batch) {
+  if (nx < 2 || ny < 2 || levels < 1 || levels > 12 || batch < 1)
+    return fail(EXPENC_EINVAL, "bad wavelet grid %dx%d levels %d batch %d", nx, ny, levels, batch);
+  if ((nx % (1 << levels)) || (ny % (1 << levels)))
+    return fail(EXPENC_EINVAL, "grid %dx%d is not a multiple of 2^%d", nx, ny, levels);
+  if (nx > 4096 || ny > 512) return fail(EXPENC_EUNSUPPORTED, "wavelet grid larger than 4096 x 512");
+  return EXPENC_OK;
+}
+
+int dwt_forward_levels(const FilterSet &f, int nx, int ny, int levels, int batch, const float2 *src,
+                       float2 *w, const double *tau, double *l1_part, int l1_stride, hipStream_t s) {
+  for (int j = 0; j < levels; ++j) {
+    const int mx = nx >> j, my = ny >> j;
+    k_dwt_rows<<<dim3(my, batch), 256, mx * sizeof(float2), s>>>(j == 0 ? src : w, w, nx, ny, mx, f);
+    EX_LAUNCHED("dwt rows");
+    const int nb = (int)ceil_div(mx, 16);
+    double *lp = l1_part ? l1_part + (int64_t)j * batch * l1_stride : nullptr;
+    k_dwt_cols<<<dim3(nb, batch), 256, my * 16 * sizeof(float2), s>>>(w, nx, ny, mx, my, f, tau, lp, l1_stride);
+    EX_LAUNCHED("dwt cols");
+  }
+  return EXPENC_OK;
+}
+
+int dwt_inverse_levels(const FilterSet &f, int nx, int ny, int levels, int batch, float2 *w, float2 *dst,
+                       const float2 *xprev, float2 *zout, float beta, hipStream_t s) {
+  for (int j = levels - 1; j >= 0; --j) {
+    const int mx = nx >> j, my = ny >> j;
+    const int nb = (int)ceil_div(mx, 16);
+    k_idwt_cols<<<dim3(nb, batch), 256, my * 16 * sizeof(float2), s>>>(w, nx, ny, mx, my, f);
+    EX_LAUNCHED("idwt cols");
+    const bool last = (j == 0);
+    k_idwt_rows<<<dim3(my, batch), 256, mx * sizeof(float2), s>>>(w, last ? dst : w, nx, ny, mx, f,
+                                                                   last ? xprev : nullptr,
+                                                                   last ? zout : nullptr, beta);
+    EX_LAUNCHED("idwt rows");
+  }
+  return EXPENC_OK;
+}
+
+}  // namespace expenc
+
+using namespace expenc;
+
+extern "C" int wavelet_fwd(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch,
+                           const float *x, float *w, void *stream) {
+  EX_TRY(check_grid(nx, ny, levels, batch));
+  if (!x || !w) return fail(EXPENC_EINVAL, "NULL array");
+  FilterSet f;
+  EX_TRY(make_filter_set(wavelet, &f));
+  return dwt_forward_levels(f, nx, ny, levels, batch, reinterpret_cast<const float2 *>(x),
+                            reinterpret_cast<float2 *>(w), nullptr, nullptr, 0, (hipStream_t)stream);
+}
+
+extern "C" int wavelet_inv(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch,
+                           const float *w, float *x, void *stream) {
+  EX_TRY(check_grid(nx, ny, levels, batch));
+  if (!x || !w) return fail(EXPENC_EINVAL, "NULL array");
+  FilterSet f;
+  EX_TRY(make_filter_set(wavelet, &f));
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t n = (int64_t)nx * ny * batch;
+  if (x != w) {
+    k_copy2<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(reinterpret_cast<const float2 *>(w),
+                                                      reinterpret_cast<float2 *>(x), n);
+    EX_LAUNCHED("copy");
+  }
+  float2 *xx = reinterpret_cast<float2 *>(x);
+  return dwt_inverse_levels(f, nx, ny, levels, batch, xx, xx, nullptr, nullptr, 0.f, s);
+}
+
+extern "C" int soft_threshold(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w_in,
+                              float *w_out, float tau, void *stream) {
+  if (nx < 1 || ny < 1 || levels < 0 || batch < 1 || !w_in || !w_out || !(tau >= 0.f))
+    return fail(EXPENC_EINVAL, "bad soft_threshold arguments");
+  const int64_t total = (int64_t)nx * ny * batch;
+  k_soft<<<(unsigned)ceil_div(total, 256), 256, 0, (hipStream_t)stream>>>(
+      reinterpret_cast<const float2 *>(w_in), reinterpret_cast<float2 *>(w_out), nx, ny, nx >> levels,
+      ny >> levels, total, tau);
+  EX_LAUNCHED("soft_threshold");
+  return EXPENC_OK;
+}

@@ -1,0 +1,37 @@
+// Device-side wavelet/prox helpers and the pass launchers used by the solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace expenc {
+
+// Analysis filters in FP32 (low-pass h, high-pass g[k] = (-1)^k h[M-1-k]).
+struct FilterSet {
+  int taps;
+  float h[8];
+  float g[8];
+};
+
+// Soft-threshold of one complex coefficient: w * max(0, 1 - tau/|w|).
+__device__ inline float2 soft(float2 v, float t) {
+  const float m = sqrtf(v.x * v.x + v.y * v.y);
+  const float sc = m > t ? 1.f - t / m : 0.f;
+  return make_float2(v.x * sc, v.y * sc);
+}
+
+int make_filter_set(int32_t wavelet, FilterSet *f);
+
+// Multi-level analysis of src into w ([B][ny][nx]); w may equal src.  When
+// tau (device, [B]) is given the detail coefficients are soft-thresholded as
+// they are produced, and when l1_part is given the per-block sums of the
+// thresholded detail moduli go to l1_part[level][b][block] (l1_stride blocks).
+int dwt_forward_levels(const FilterSet &f, int nx, int ny, int levels, int batch, const float2 *src,
+                       float2 *w, const double *tau, double *l1_part, int l1_stride, hipStream_t s);
+// Multi-level synthesis, in place on w except the last row pass, which writes
+// dst; if zout is given it also writes zout = dst + beta*(dst - xprev).
+int dwt_inverse_levels(const FilterSet &f, int nx, int ny, int levels, int batch, float2 *w, float2 *dst,
+                       const float2 *xprev, float2 *zout, float beta, hipStream_t s);
+
+}  // namespace expenc

@@ -1,0 +1,238 @@
+"""Python binding of the expanded-encoding CS library (torch tensors in,
+torch tensors out).  Each function marshals device pointers, sizes and the
+current HIP stream into one C-ABI call of libexpenc.so; all arithmetic runs
+in the library's HIP kernels.  Tensors must live on a ROCm device.
+
+Layouts (see include/expenc.h): images [B][ny][nx] (or [B][R]) complex64,
+k-space [B][T][C] complex64, field arrays float64.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import torch
+
+from . import _binding as _b
+from ._binding import FP32, BF16_SPLIT, FP16_SPLIT, HAAR, DB4, check
+
+PRECISIONS = {"fp32": FP32, "bf16": BF16_SPLIT, "bf16_split": BF16_SPLIT, "fp16": FP16_SPLIT,
+              "fp16_split": FP16_SPLIT}
+WAVELETS = {"haar": HAAR, "db4": DB4}
+
+
+def _prec(p) -> int:
+    return PRECISIONS[p] if isinstance(p, str) else int(p)
+
+
+def _wav(w) -> int:
+    return WAVELETS[w] if isinstance(w, str) else int(w)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _need(t: torch.Tensor, dtype, name: str, device):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU (got {t.device})")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+class Operator:
+    """One expanded-encoding operator: A[(t,c), r] = S_c(r) exp(i phi(t, r)),
+    phi = sum_l coef[t, l] basis[l, r] + dw0[r] time[t].
+
+    basis [L][R] f64, coef [T][L] f64 (rad per basis unit), time [T] f64 (s),
+    dw0 [R] f64 (rad/s) or None, smaps [C][R] complex64; image nx x ny."""
+
+    def __init__(self, nx: int, ny: int, smaps, coef, time, basis, dw0=None):
+        dev = smaps.device
+        self.device = dev
+        self.smaps = _need(smaps, torch.complex64, "smaps", dev)
+        self.time = _need(time, torch.float64, "time", dev)
+        self.nx, self.ny = int(nx), int(ny)
+        self.ncoils = smaps.shape[0]
+        self.nsamples = time.shape[0]
+        if basis is None or basis.numel() == 0:
+            self.nbasis = 0
+            self.basis = self.coef = None
+        else:
+            self.basis = _need(basis, torch.float64, "basis", dev)
+            self.coef = _need(coef, torch.float64, "coef", dev)
+            self.nbasis = basis.shape[0]
+            if coef.shape != (self.nsamples, self.nbasis):
+                raise ValueError(f"coef must be [T][L] = [{self.nsamples}][{self.nbasis}]")
+            if basis.shape[1] != self.nx * self.ny:
+                raise ValueError("basis must be [L][nx*ny]")
+        self.dw0 = None if dw0 is None else _need(dw0, torch.float64, "dw0", dev)
+        if smaps.shape[1] != self.nx * self.ny:
+            raise ValueError("smaps must be [C][nx*ny]")
+        self._c = _b.ExpencOp(self.nx, self.ny, self.ncoils, self.nbasis, self.nsamples,
+                              None if self.basis is None else self.basis.data_ptr(),
+                              None if self.coef is None else self.coef.data_ptr(),
+                              self.time.data_ptr(),
+                              None if self.dw0 is None else self.dw0.data_ptr(),
+                              self.smaps.data_ptr())
+        self._ws = {}
+
+    @property
+    def npix(self) -> int:
+        return self.nx * self.ny
+
+    def workspace(self, what: int, batch: int = 1, precision=FP32, nx_pad: int = 0, ny_pad: int = 0):
+        n = _b.lib().expenc_workspace_size(ctypes.byref(self._c), batch, _prec(precision), what, nx_pad, ny_pad)
+        if n == 0:
+            raise _b.ExpencError(_b.EXPENC_EINVAL, "expenc_workspace_size")
+        key = (what, batch, _prec(precision), nx_pad, ny_pad)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < n:
+            ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+
+def sh_basis(nx: int, ny: int, fov_x: float, fov_y: float, z0: float, nbasis: int, device="cuda") -> torch.Tensor:
+    """Real solid-harmonic field basis [L][R] (float64) on the pixel grid."""
+    out = torch.empty((nbasis, nx * ny), dtype=torch.float64, device=device)
+    check(_b.lib().expenc_sh_basis(nx, ny, fov_x, fov_y, z0, nbasis, _ptr(out) if nbasis else None,
+                                   _stream(out.device)), "expenc_sh_basis")
+    return out
+
+
+def forward(x: torch.Tensor, op: Operator, precision="fp32", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """y = A x.  x: [R] or [B][R] (or [B][ny][nx]) complex64 -> y [B][T][C]."""
+    single = x.dim() == 1
+    xb = x.reshape(1 if single else x.shape[0], op.npix)
+    _need(xb, torch.complex64, "x", op.device)
+    batch = xb.shape[0]
+    y = out if out is not None else torch.empty((batch, op.nsamples, op.ncoils), dtype=torch.complex64,
+                                                device=op.device)
+    _need(y, torch.complex64, "y", op.device)
+    ws = op.workspace(_b.WS_FORWARD, batch, precision)
+    check(_b.lib().expenc_forward(ctypes.byref(op._c), batch, _prec(precision), _ptr(xb), _ptr(y), _ptr(ws),
+                                  ws.numel(), _stream(op.device)), "expenc_forward")
+    return y[0] if single else y
+
+
+def adjoint(y: torch.Tensor, op: Operator, precision="fp32", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x = A^H y.  y: [T][C] or [B][T][C] complex64 -> x [B][R]."""
+    single = y.dim() == 2
+    yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
+    _need(yb, torch.complex64, "y", op.device)
+    batch = yb.shape[0]
+    x = out if out is not None else torch.empty((batch, op.npix), dtype=torch.complex64, device=op.device)
+    _need(x, torch.complex64, "x", op.device)
+    ws = op.workspace(_b.WS_ADJOINT, batch, precision)
+    check(_b.lib().expenc_adjoint(ctypes.byref(op._c), batch, _prec(precision), _ptr(yb), _ptr(x), _ptr(ws),
+                                  ws.numel(), _stream(op.device)), "expenc_adjoint")
+    return x[0] if single else x
+
+
+def lipschitz(op: Operator, v0: torch.Tensor, n_iter: int, precision="fp32") -> torch.Tensor:
+    """L = 2 lambda_max(A^H A) by power iteration from v0 [R]; a device float64 scalar."""
+    _need(v0, torch.complex64, "v0", op.device)
+    out = torch.empty(1, dtype=torch.float64, device=op.device)
+    ws = op.workspace(_b.WS_LIPSCHITZ, 1, precision)
+    check(_b.lib().expenc_lipschitz(ctypes.byref(op._c), _prec(precision), n_iter, _ptr(v0), _ptr(out), _ptr(ws),
+                                    ws.numel(), _stream(op.device)), "expenc_lipschitz")
+    return out
+
+
+def wavelet_fwd(x: torch.Tensor, levels: int, wavelet="db4", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """W x for x [ny][nx] or [B][ny][nx] complex64 (Mallat layout)."""
+    xb = x.reshape((-1,) + tuple(x.shape[-2:]))
+    _need(xb, torch.complex64, "x", None)
+    w = out if out is not None else torch.empty_like(xb)
+    check(_b.lib().wavelet_fwd(xb.shape[2], xb.shape[1], levels, _wav(wavelet), xb.shape[0], _ptr(xb), _ptr(w),
+                               _stream(x.device)), "wavelet_fwd")
+    return w.reshape(x.shape)
+
+
+def wavelet_inv(w: torch.Tensor, levels: int, wavelet="db4", out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    wb = w.reshape((-1,) + tuple(w.shape[-2:]))
+    _need(wb, torch.complex64, "w", None)
+    x = out if out is not None else torch.empty_like(wb)
+    check(_b.lib().wavelet_inv(wb.shape[2], wb.shape[1], levels, _wav(wavelet), wb.shape[0], _ptr(wb), _ptr(x),
+                               _stream(w.device)), "wavelet_inv")
+    return x.reshape(w.shape)
+
+
+def soft_threshold(w: torch.Tensor, tau: float, levels: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    wb = w.reshape((-1,) + tuple(w.shape[-2:]))
+    _need(wb, torch.complex64, "w", None)
+    o = out if out is not None else torch.empty_like(wb)
+    check(_b.lib().soft_threshold(wb.shape[2], wb.shape[1], levels, wb.shape[0], _ptr(wb), _ptr(o), float(tau),
+                                  _stream(w.device)), "soft_threshold")
+    return o.reshape(w.shape)
+
+
+@dataclasses.dataclass
+class FistaResult:
+    x: torch.Tensor                      # [B][ny][nx]
+    lipschitz: float
+    lam: list
+    tau: list
+    objective: Optional[torch.Tensor]    # [B][n_iter] float64
+
+
+def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4", precision="fp32",
+          lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3, power_v0=None,
+          n_power: int = 30, nx_pad: int = 0, ny_pad: int = 0, ista: bool = False, refine_every: int = 0,
+          trace: bool = False, sync_scalars: bool = True):
+    """FISTA on eq. 1 (see fista_solve in include/expenc.h).  Returns a FistaResult."""
+    single = y.dim() == 2
+    yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
+    _need(yb, torch.complex64, "y", op.device)
+    batch = yb.shape[0]
+    m = 1 << levels
+    nxp = nx_pad or -(-op.nx // m) * m
+    nyp = ny_pad or -(-op.ny // m) * m
+    x = torch.empty((batch, op.ny, op.nx), dtype=torch.complex64, device=op.device)
+    obj = torch.empty((batch, max(n_iter, 1)), dtype=torch.float64, device=op.device) if trace else None
+    sc = torch.zeros(2 + 2 * batch, dtype=torch.float64, device=op.device)
+    if lipschitz <= 0 and power_v0 is None:
+        raise ValueError("lipschitz <= 0 needs power_v0 (the seeded start vector)")
+    opts = _b.FistaOpts(n_iter, _prec(precision), _wav(wavelet), levels, nxp, nyp, int(ista), refine_every,
+                        n_power, 0, float(lipschitz), float(lam), float(lambda_factor),
+                        None if power_v0 is None else _need(power_v0, torch.complex64, "power_v0",
+                                                            op.device).data_ptr(),
+                        None if obj is None else obj.data_ptr(), sc.data_ptr())
+    ws = op.workspace(_b.WS_FISTA, batch, precision, nxp, nyp)
+    check(_b.lib().fista_solve(ctypes.byref(op._c), batch, _ptr(yb), _ptr(x), ctypes.byref(opts), _ptr(ws),
+                               ws.numel(), _stream(op.device)), "fista_solve")
+    if sync_scalars:
+        s = sc.cpu().tolist()
+        res = FistaResult(x[0] if single else x, s[0], s[2:2 + batch], s[2 + batch:2 + 2 * batch], obj)
+    else:
+        res = FistaResult(x[0] if single else x, float("nan"), [], [], obj)
+    return res
+
+
+def cg(y: torch.Tensor, op: Operator, n_iter: int, precision="fp32") -> torch.Tensor:
+    """Least squares by CG on A^H A x = A^H y from 0, n_iter iterations -> x [B][R]."""
+    single = y.dim() == 2
+    yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
+    _need(yb, torch.complex64, "y", op.device)
+    batch = yb.shape[0]
+    x = torch.empty((batch, op.npix), dtype=torch.complex64, device=op.device)
+    opts = _b.FistaOpts()
+    opts.n_iter = n_iter
+    opts.precision = _prec(precision)
+    ws = op.workspace(_b.WS_CG, batch, precision)
+    check(_b.lib().cg_solve(ctypes.byref(op._c), batch, _ptr(yb), _ptr(x), ctypes.byref(opts), _ptr(ws),
+                            ws.numel(), _stream(op.device)), "cg_solve")
+    return x[0] if single else x

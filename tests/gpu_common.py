@@ -1,0 +1,56 @@
+"""Shared helpers of the GPU parity tests: seeded inputs as torch device
+tensors (for the HIP path) and as rounded numpy arrays (for the oracle)."""
+from __future__ import annotations
+
+import numpy as np
+
+import synth
+
+
+def c64(a: np.ndarray) -> np.ndarray:
+    """Round to complex64 and back, so both sides see identical inputs."""
+    return np.asarray(a).astype(np.complex64).astype(np.complex128)
+
+
+def rel(a, b) -> float:
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+class Case:
+    """One problem: numpy inputs for the oracle, device tensors for the GPU."""
+
+    def __init__(self, w: synth.Workload, z0: float | None = None, ncoils: int | None = None,
+                 with_dw0: bool = True, nbasis: int | None = None):
+        import torch
+        from oracle import encoding
+        import paper_2211_07532_amd as ee
+
+        self.w = w
+        p = synth.make_problem(w)
+        nb = w.nbasis if nbasis is None else nbasis
+        self.z0 = w.z0 if z0 is None else z0
+        self.smaps = c64(p.smaps if ncoils is None else synth.coil_maps(w, ncoils))
+        self.coef = p.coef[:, :nb].copy()
+        self.time = p.time
+        self.dw0 = p.dw0 if with_dw0 else None
+        self.x_true = c64(p.x_true)
+        self.x_noisy = c64(p.x_noisy)
+        self.basis_np = encoding.sh_basis(w.n, w.fov, self.z0, nb)
+        dev = torch.device("cuda")
+        self.dev = dev
+        self.t_smaps = torch.from_numpy(self.smaps.astype(np.complex64)).to(dev)
+        self.t_coef = torch.from_numpy(self.coef).to(dev)
+        self.t_time = torch.from_numpy(self.time).to(dev)
+        self.t_dw0 = None if self.dw0 is None else torch.from_numpy(self.dw0).to(dev)
+        # the GPU evaluates its own basis from the grid geometry
+        self.t_basis = ee.sh_basis(w.n, w.n, w.fov, w.fov, self.z0, nb, device=dev)
+        self.op = ee.Operator(w.n, w.n, self.t_smaps, self.t_coef, self.t_time, self.t_basis, self.t_dw0)
+
+    def oracle_args(self):
+        return (self.smaps, self.coef, self.time, self.basis_np, self.dw0)
+
+    def to_dev(self, a: np.ndarray):
+        import torch
+        return torch.from_numpy(np.ascontiguousarray(a).astype(np.complex64)).to(self.dev)
