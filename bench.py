@@ -1,0 +1,160 @@
+"""Benchmark of the expanded-encoding CS hot path on one MI355X.
+
+One step = one complete CS reconstruction of the 1.5 mm workload (148 x 148
+image, 32 coils, 16384-sample single-shot spiral, 3rd-order field terms +
+dB0): field setup, power-iteration Lipschitz estimate, lambda from A^H y and
+50 FISTA iterations with a 3-level Daubechies-4 wavelet, all inside
+libexpenc (the iteration loop replays a captured HIP graph).  Inputs are
+seeded synthetic stand-ins for the paper's scanner data and sit in HBM
+before the timed region.
+
+Prints ONE JSON line.  `value` is the A_exp + A_exp^H throughput of the whole
+step in GCMAC/s (T*R*C complex multiply-accumulates per operator
+application, counted once per application whatever the arithmetic form).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6}
+N_POWER = 20
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=10)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, prob, basis):
+    """The FP64 oracle on the host: one forward and one adjoint application
+    of the full-size operator (the bounded sample), in GCMAC/s."""
+    from oracle import encoding
+    t0 = time.perf_counter()
+    y = encoding.forward(prob.x_noisy, prob.smaps, prob.coef, prob.time, basis, prob.dw0)
+    encoding.adjoint(y, prob.smaps, prob.coef, prob.time, basis, prob.dw0)
+    dt = time.perf_counter() - t0
+    cmac = w.nsamples * w.npix * w.ncoils
+    return {"value": round(2 * cmac / dt / 1e9, 4), "unit": "GCMAC/s",
+            "cores": int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1)), "kind": "oracle",
+            "sample": f"one A_exp and one A_exp^H application of the {w.name} operator "
+                      f"({2 * cmac:.3e} CMAC, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only: this build has no multi-GPU path (got --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2211_07532_amd as ee
+    from paper_2211_07532_amd import _binding as B
+
+    w = synth.MM15
+    dev = torch.device("cuda:0")
+    prob = synth.make_problem(w)
+    smaps = torch.from_numpy(prob.smaps.astype(np.complex64)).to(dev)
+    coef = torch.from_numpy(prob.coef).to(dev)
+    tm = torch.from_numpy(prob.time).to(dev)
+    dw0 = torch.from_numpy(prob.dw0).to(dev)
+    basis = ee.sh_basis(w.n, w.n, w.fov, w.fov, w.z0, w.nbasis, device=dev)
+    op = ee.Operator(w.n, w.n, smaps, coef, tm, basis, dw0)
+    x_noisy = torch.from_numpy(prob.x_noisy.astype(np.complex64)).to(dev)
+    y = ee.forward(x_noisy, op)                      # synthetic k-space of the noisy object
+    v0 = torch.from_numpy(synth.power_start(w.npix, 7).astype(np.complex64)).to(dev)
+    prec = args.precision
+
+    def step():
+        return ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
+                        n_power=N_POWER, lam=-1.0, lambda_factor=1e-3, sync_scalars=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    cmac = w.nsamples * w.npix * w.ncoils
+    apps = 2 * w.n_iter + (2 * N_POWER + 1) + 1
+    value = apps * cmac / dt / 1e9
+
+    # FISTA loop alone (L and lambda given): iterations per second
+    sc = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
+                  n_power=N_POWER)
+    L, lam = sc.lipschitz, sc.lam[0]
+    ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    reps = max(2, args.steps)
+    for _ in range(reps):
+        ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+    torch.cuda.synchronize()
+    it_s = w.n_iter * reps / (time.perf_counter() - t1)
+
+    # Roofline of the contraction kernels: HIP events around each eager launch
+    lib = B.lib()
+    out = (ctypes.c_double * 4)()
+    B.check(lib.expenc_kernel_timing(1, out), "timing on")
+    for _ in range(args.kernel_reps):
+        yk = ee.forward(x_noisy, op, precision=prec)
+        ee.adjoint(yk, op, precision=prec)
+    torch.cuda.synchronize()
+    B.check(lib.expenc_kernel_timing(2, out), "timing read")
+    B.check(lib.expenc_kernel_timing(0, out), "timing off")
+    fwd_ms = out[0] / max(out[1], 1)
+    adj_ms = out[2] / max(out[3], 1)
+    dom_ms = max(fwd_ms, adj_ms)
+    dom = "forward" if fwd_ms >= adj_ms else "adjoint"
+    flops = 8.0 * cmac                                  # algorithmic: 4 real MAC per CMAC
+    achieved = flops / (dom_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[prec]
+
+    line = {
+        "metric": "A_exp+A_exp^H GCMAC/s & CS-FISTA iter/s, BF16-split vs FP32 at <=1e-4 NRMSE",
+        "value": round(value, 2),
+        "unit": "GCMAC/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "bf16": "bf16-split", "fp16": "f16-split"}[prec],
+        "data": "synthetic",
+        "config": {"workload": w.name, "image": f"{w.n}x{w.n}", "coils": w.ncoils, "samples": w.nsamples,
+                   "field_terms": w.nbasis, "fista_iters": w.n_iter, "wavelet": f"{w.wavelet} J={w.levels}",
+                   "power_iters": N_POWER, "operator_applications_per_step": apps},
+        "fista_iter_per_s": round(it_s, 2),
+        "kernel_ms": {"forward_contraction": round(fwd_ms, 4), "adjoint_contraction": round(adj_ms, 4)},
+        "roofline": {"bound": "mfma", "kernel": f"{dom} contraction", "achieved": round(achieved, 2),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import encoding
+        line["cpu_baseline"] = cpu_baseline(w, prob, encoding.sh_basis(w.n, w.fov, w.z0, w.nbasis))
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -205,6 +205,16 @@ int fista_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
 int cg_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
              const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Profiling aid (not part of the method): per-kernel timing of the two
+ * contraction kernels with HIP events recorded on their launch stream around
+ * every eager launch (launches captured into a graph are not timed).
+ * mode 0: off and clear; 1: on and clear; 2: wait for the recorded events
+ * and write out[0] = total forward-contraction ms, out[1] = forward launches,
+ * out[2] = total adjoint-contraction ms, out[3] = adjoint launches (host array).
+ */
+int expenc_kernel_timing(int32_t mode, double *out);
+
 /* Thread-local text of the last non-OK status of this thread. */
 const char *expenc_last_error(void);
 

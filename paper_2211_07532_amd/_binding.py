@@ -67,6 +67,7 @@ SIGNATURES = {
                                 ctypes.c_size_t, _vp]),
     "expenc_field_grad": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _vp, _vp, _vp, _vp, _vp,
                                          ctypes.c_size_t, _vp]),
+    "expenc_kernel_timing": (ctypes.c_int, [_c_int, ctypes.POINTER(ctypes.c_double)]),
     "expenc_last_error": (ctypes.c_char_p, []),
 }
 

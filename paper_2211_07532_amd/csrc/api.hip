@@ -328,3 +328,5 @@ extern "C" int expenc_lipschitz(const expenc_op *op, int32_t precision, int32_t 
   EX_TRY(enc_prepare(p1, op, eb, s));
   return lipschitz_run(p1, op, eb, n_iter, v0, vec, tmp, dpart, dpart + kRedBlocks, lipschitz_out, s);
 }
+
+extern "C" int expenc_kernel_timing(int32_t mode, double *out) { return kernel_timing(mode, out); }

@@ -25,6 +25,9 @@
 // so results are bitwise reproducible.
 #include <cmath>
 #include <cstdio>
+#include <mutex>
+#include <utility>
+#include <vector>
 
 #include "internal.h"
 
@@ -453,6 +456,89 @@ int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream
   return EXPENC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Opt-in per-kernel timing of the two contraction kernels with HIP events
+// recorded on the launch stream (eager launches only; skipped while the
+// stream is being captured into a graph).
+// ---------------------------------------------------------------------------
+namespace {
+struct KernelTimer {
+  std::mutex mu;
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[2];
+  std::vector<hipEvent_t> pool;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    hipEventCreate(&e);
+    return e;
+  }
+  void clear() {
+    for (auto &v : ev)
+      for (auto &pr : v) {
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+    ev[0].clear();
+    ev[1].clear();
+  }
+};
+KernelTimer g_timer;
+
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &st) != hipSuccess) return true;
+  return st != hipStreamCaptureStatusNone;
+}
+
+template <class F>
+void timed(int kind, hipStream_t s, F launch) {
+  hipEvent_t a = nullptr, b = nullptr;
+  bool t = false;
+  {
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    t = g_timer.on && !capturing(s);
+    if (t) {
+      a = g_timer.get();
+      b = g_timer.get();
+    }
+  }
+  if (t) hipEventRecord(a, s);
+  launch();
+  if (t) {
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> lk(g_timer.mu);
+    g_timer.ev[kind].push_back({a, b});
+  }
+}
+}  // namespace
+
+int kernel_timing(int32_t mode, double *out) {
+  std::lock_guard<std::mutex> lk(g_timer.mu);
+  if (mode == 0 || mode == 1) {
+    g_timer.clear();
+    g_timer.on = (mode == 1);
+    return EXPENC_OK;
+  }
+  if (mode != 2 || !out) return fail(EXPENC_EINVAL, "bad timing mode");
+  for (int k = 0; k < 2; ++k) {
+    double tot = 0;
+    for (auto &pr : g_timer.ev[k]) {
+      EX_HIP(hipEventSynchronize(pr.second));
+      float ms = 0;
+      EX_HIP(hipEventElapsedTime(&ms, pr.first, pr.second));
+      tot += ms;
+    }
+    out[2 * k] = tot;
+    out[2 * k + 1] = (double)g_timer.ev[k].size();
+  }
+  return EXPENC_OK;
+}
+
 template <int NT>
 static void launch_fwd(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY);
@@ -474,21 +560,25 @@ static void launch_adj(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 }
 
 int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  switch (p.NT) {
-    case 4: launch_fwd<4>(p, b, s); break;
-    case 10: launch_fwd<10>(p, b, s); break;
-    default: launch_fwd<17>(p, b, s); break;
-  }
+  timed(0, s, [&] {
+    switch (p.NT) {
+      case 4: launch_fwd<4>(p, b, s); break;
+      case 10: launch_fwd<10>(p, b, s); break;
+      default: launch_fwd<17>(p, b, s); break;
+    }
+  });
   EX_LAUNCHED("forward contraction");
   return EXPENC_OK;
 }
 
 int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  switch (p.NT) {
-    case 4: launch_adj<4>(p, b, s); break;
-    case 10: launch_adj<10>(p, b, s); break;
-    default: launch_adj<17>(p, b, s); break;
-  }
+  timed(1, s, [&] {
+    switch (p.NT) {
+      case 4: launch_adj<4>(p, b, s); break;
+      case 10: launch_adj<10>(p, b, s); break;
+      default: launch_adj<17>(p, b, s); break;
+    }
+  });
   EX_LAUNCHED("adjoint contraction");
   return EXPENC_OK;
 }

@@ -102,6 +102,9 @@ int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *s
 // straight into the adjoint operand.
 int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s);
 
+// Per-kernel event timing of the contraction kernels (mode 0 off, 1 on, 2 read).
+int kernel_timing(int32_t mode, double *out);
+
 // Daubechies / Haar analysis low-pass filter, derived on the host.
 int wavelet_filter(int32_t wavelet, double *h, int *taps);
 
