@@ -303,7 +303,8 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
                                                         const float2 *__restrict__ smaps,
                                                         float2 *__restrict__ x, int64_t x_stride,
                                                         int x_row_stride, const double *__restrict__ alpha_dev,
-                                                        const float2 *__restrict__ add) {
+                                                        const float2 *__restrict__ add,
+                                                        const float2 *__restrict__ base) {
   const int sub = threadIdx.x & 31;
   const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
   if (r >= R) return;  // uniform per 32-lane group
@@ -330,6 +331,10 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
       const int yy = r / nx, xx = r % nx;
       const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
       const float alpha = alpha_dev ? (float)*alpha_dev : 1.f;
+      if (base) {
+        sx += base[o].x;
+        sy += base[o].y;
+      }
       float2 v = make_float2(alpha * sx, alpha * sy);
       if (add) {
         v.x += add[o].x;
@@ -391,7 +396,6 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p)
   q.NT = phase_terms(q.L);
   q.prec = precision;
   q.has_dw0 = op->dw0 != nullptr;
-  if (precision != EXPENC_FP32) return fail(EXPENC_EUNSUPPORTED, "split precision not available in this build");
   const int tgt = target_workgroups();
   // forward: 256 sample rows per workgroup, split over pixels
   {
@@ -420,14 +424,24 @@ size_t enc_operand_bytes(const EncPlan &p) {
   return a.used + 256;
 }
 
-int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b) {
+size_t enc_part_elems(const EncPlan &p) {
+  const size_t pf = (size_t)p.fwd_split * p.Tp * p.NCP;
+  const size_t pa = (size_t)p.adj_split * p.Rp * p.NCP;
+  return std::max(pf, pa);
+}
+
+int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
   b->kap = a.take<double>((size_t)p.Tp * p.NT);
   b->bet = a.take<double>((size_t)p.Rp * p.NT);
   b->zop = a.take<float2>((size_t)p.Rp * p.NCP);
   b->yop = a.take<float2>((size_t)p.Tp * p.NCP);
-  size_t pf = (size_t)p.fwd_split * p.Tp * p.NCP;
-  size_t pa = (size_t)p.adj_split * p.Rp * p.NCP;
-  b->part = a.take<float2>(std::max(pf, pa));
+  b->part = a.take<float2>(std::max(enc_part_elems(p), min_part));
+  if (p.prec != EXPENC_FP32) {
+    b->zs = a.take<char>((size_t)p.Rp * (p.NCP / 16) * 256);
+    b->ys = a.take<char>((size_t)p.Tp * (p.NCP / 16) * 256);
+    b->dbet = a.take<float>((size_t)p.Rp * p.NT);
+    b->dkap = a.take<float>((size_t)p.Tp * p.NT);
+  }
   return a.ok() ? EXPENC_OK : EXPENC_EWORKSPACE;
 }
 
@@ -438,11 +452,14 @@ int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipS
   EX_LAUNCHED("prep_kap");
   k_prep_bet<<<blocks_for((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L, p.NT);
   EX_LAUNCHED("prep_bet");
+  if (p.prec != EXPENC_FP32) return split_prepare(p, b, s);
   return EXPENC_OK;
 }
 
 int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x_stride,
-                int32_t x_row_stride, const EncBuffers &b, hipStream_t s) {
+                int32_t x_row_stride, const EncBuffers &b, hipStream_t s, const float2 *xsub) {
+  if (p.prec != EXPENC_FP32) return split_build_z(p, smaps, x, xsub, x_stride, x_row_stride, b, s);
+  if (xsub) return fail(EXPENC_EUNSUPPORTED, "operand difference is only built for split forms");
   k_build_z_f32<<<blocks_for((int64_t)p.Rp * p.NCP, 256), 256, 0, s>>>(
       reinterpret_cast<const float2 *>(smaps), x, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC,
       p.NCP, b.zop);
@@ -451,6 +468,7 @@ int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x
 }
 
 int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s) {
+  if (p.prec != EXPENC_FP32) return split_pack_y(p, y, false, nullptr, b, s);
   k_pack_y_f32<<<blocks_for(p.Tp * p.NCP, 256), 256, 0, s>>>(y, p.T, p.Tp, p.C, p.NC, p.NCP, b.yop);
   EX_LAUNCHED("pack_y");
   return EXPENC_OK;
@@ -561,6 +579,10 @@ static void launch_adj(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   timed(0, s, [&] {
+    if (p.prec != EXPENC_FP32) {
+      split_forward_launch(p, b, s);
+      return;
+    }
     switch (p.NT) {
       case 4: launch_fwd<4>(p, b, s); break;
       case 10: launch_fwd<10>(p, b, s); break;
@@ -573,6 +595,10 @@ int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   timed(1, s, [&] {
+    if (p.prec != EXPENC_FP32) {
+      split_adjoint_launch(p, b, s);
+      return;
+    }
     switch (p.NT) {
       case 4: launch_adj<4>(p, b, s); break;
       case 10: launch_adj<10>(p, b, s); break;
@@ -590,6 +616,7 @@ int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hip
 }
 
 int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s) {
+  if (p.prec != EXPENC_FP32) return split_pack_y(p, nullptr, true, y_meas, b, s);
   k_fwd_residual<<<blocks_for(p.Tp * p.NCP, 256), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC,
                                                                 p.NCP, y_meas, b.yop);
   EX_LAUNCHED("forward residual");
@@ -598,10 +625,10 @@ int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_
 
 int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
                            int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
-                           const float2 *add, hipStream_t s) {
+                           const float2 *add, hipStream_t s, const float2 *base) {
   k_adj_reduce_out<<<blocks_for(p.R, 8), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
                                                       reinterpret_cast<const float2 *>(smaps), x, x_stride,
-                                                      x_row_stride, alpha_dev, add);
+                                                      x_row_stride, alpha_dev, add, base);
   EX_LAUNCHED("adjoint reduce");
   return EXPENC_OK;
 }

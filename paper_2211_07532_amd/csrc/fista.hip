@@ -135,6 +135,22 @@ __global__ void k_cg_dir(float2 *__restrict__ p, const float2 *__restrict__ r, i
   p[o] = make_float2(rv.x + be * pv.x, rv.y + be * pv.y);
 }
 
+// v = z + alpha * g on the nx x ny crop of each nxp x nyp image, v = z elsewhere
+__global__ void k_grad_step(float2 *__restrict__ v, const float2 *__restrict__ z, const float2 *__restrict__ g,
+                            const double *__restrict__ alpha_dev, int nxp, int nyp, int nx, int ny, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t p = i % ((int64_t)nxp * nyp);
+  const int yy = (int)(p / nxp), xx = (int)(p % nxp);
+  float2 o = z[i];
+  if (yy < ny && xx < nx) {
+    const float a = (float)*alpha_dev;
+    o.x += a * g[i].x;
+    o.y += a * g[i].y;
+  }
+  v[i] = o;
+}
+
 __global__ void k_copy_d(const double *in, double *out, int n) {
   const int i = threadIdx.x;
   if (i < n) out[i] = in[i];
@@ -228,10 +244,11 @@ static int run_graph(uint64_t key, hipStream_t s, Body body) {
 // ---------------------------------------------------------------------------
 
 struct FistaLayout {
-  EncPlan p, p1;
+  EncPlan p, p1, pf;  // p: iteration precision (batch B); p1: FP32 batch 1; pf: FP32 batch B
   int nxp = 0, nyp = 0;
   EncBuffers eb;
   float2 *z = nullptr, *v = nullptr, *w = nullptr, *x0 = nullptr, *x1 = nullptr;
+  float2 *zref = nullptr, *gref = nullptr;   // split forms: anchor z_ref and A^H(A z_ref - y)
   float2 *pvec = nullptr, *ptmp = nullptr;
   double *dpart = nullptr;   // [B * kRedBlocks]
   double *sc = nullptr;      // [2 + 2B + 8]
@@ -251,23 +268,24 @@ static int resolve_pad(int n, int given, int levels, int *out) {
 static int layout_fista(const expenc_op *op, int32_t batch, int32_t precision, int levels, int nx_pad, int ny_pad,
                         bool objective, Arena &a, FistaLayout *L) {
   EX_TRY(make_plan(op, batch, precision, &L->p));
-  EX_TRY(make_plan(op, 1, precision, &L->p1));
+  EX_TRY(make_plan(op, 1, EXPENC_FP32, &L->p1));
+  EX_TRY(make_plan(op, batch, EXPENC_FP32, &L->pf));
   if (levels < 1 || levels > 12) return fail(EXPENC_EINVAL, "levels must be in [1, 12]");
   EX_TRY(resolve_pad(op->nx, nx_pad, levels, &L->nxp));
   EX_TRY(resolve_pad(op->ny, ny_pad, levels, &L->nyp));
-  // operand buffers sized for the larger of the batch-B and batch-1 plans
-  Arena probe_b, probe_1;
-  EncBuffers tmp;
-  carve_enc(L->p, probe_b, &tmp);
-  carve_enc(L->p1, probe_1, &tmp);
-  const EncPlan &big = probe_b.used >= probe_1.used ? L->p : L->p1;
-  carve_enc(big, a, &L->eb);
+  // p's buffers hold the FP32 operands of pf as well; the partial-sum buffer
+  // is shared by all three plans (identical padded geometry)
+  carve_enc(L->p, a, &L->eb, std::max(enc_part_elems(L->p1), enc_part_elems(L->pf)));
   const size_t img = (size_t)batch * L->nxp * L->nyp;
   L->z = a.take<float2>(img);
   L->v = a.take<float2>(img);
   L->w = a.take<float2>(img);
   L->x0 = a.take<float2>(img);
   L->x1 = a.take<float2>(img);
+  if (precision != EXPENC_FP32) {
+    L->zref = a.take<float2>(img);
+    L->gref = a.take<float2>(img);
+  }
   L->pvec = a.take<float2>((size_t)L->p.R);
   L->ptmp = a.take<float2>((size_t)L->p.R);
   L->dpart = a.take<double>((size_t)batch * kRedBlocks);
@@ -349,10 +367,11 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
     k_fill_d<<<1, 256, 0, s>>>(L.sc + 2, B, opts->lambda);
     EX_LAUNCHED("fill");
   } else {
-    EX_TRY(enc_pack_y(p, y2, L.eb, s));
-    EX_TRY(enc_adjoint_partials(p, L.eb, s));
-    EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, p.R, p.nx, nullptr, nullptr, s));
-    EX_TRY(reduce_maxabs(L.v, p.R, p.R, B, opts->lambda_factor, L.dpart, L.sc + 2, s));
+    const EncPlan &pf = L.pf;
+    EX_TRY(enc_pack_y(pf, y2, L.eb, s));
+    EX_TRY(enc_adjoint_partials(pf, L.eb, s));
+    EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.v, pf.R, pf.nx, nullptr, nullptr, s));
+    EX_TRY(reduce_maxabs(L.v, pf.R, pf.R, B, opts->lambda_factor, L.dpart, L.sc + 2, s));
   }
   k_fista_scalars<<<1, 256, 0, s>>>(L.sc, B);
   EX_LAUNCHED("scalars");
@@ -372,25 +391,50 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
     }
   }
   const bool padded = (nxp != p.nx) || (nyp != p.ny);
+  const bool split = opts->precision != EXPENC_FP32;
   const bool with_obj = opts->objective != nullptr;
   auto body = [&](hipStream_t cs) -> int {
     for (int k = 0; k < K; ++k) {
       float2 *xk = (k % 2 == 0) ? L.x1 : L.x0;
       float2 *xprev = (k % 2 == 0) ? L.x0 : L.x1;
-      EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs));
-      EX_TRY(enc_forward_partials(p, L.eb, cs));
-      EX_TRY(enc_forward_residual(p, L.eb, y2, cs));
-      EX_TRY(enc_adjoint_partials(p, L.eb, cs));
-      if (padded) EX_TRY(copy_f2(L.z, L.v, img * B, cs));
-      EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, L.sc + 1, L.z, cs));
+      if (!split) {
+        // v = z - (2/L) A^H (A z - y)
+        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs));
+        EX_TRY(enc_forward_partials(p, L.eb, cs));
+        EX_TRY(enc_forward_residual(p, L.eb, y2, cs));
+        EX_TRY(enc_adjoint_partials(p, L.eb, cs));
+        if (padded) EX_TRY(copy_f2(L.z, L.v, img * B, cs));
+        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, L.sc + 1, L.z, cs));
+      } else if (k % refine == 0 || k == K - 1) {
+        // anchor: exact FP32 gradient at z_ref = z
+        const EncPlan &pf = L.pf;
+        EX_TRY(enc_build_z(pf, op->smaps, L.z, img, nxp, L.eb, cs));
+        EX_TRY(enc_forward_partials(pf, L.eb, cs));
+        EX_TRY(enc_forward_residual(pf, L.eb, y2, cs));
+        EX_TRY(enc_adjoint_partials(pf, L.eb, cs));
+        EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.gref, img, nxp, nullptr, nullptr, cs));
+        k_grad_step<<<(unsigned)ceil_div(img * B, 256), 256, 0, cs>>>(L.v, L.z, L.gref, L.sc + 1, nxp, nyp, p.nx,
+                                                                       p.ny, (int64_t)B * img);
+        EX_LAUNCHED("gradient step");
+        EX_TRY(copy_f2(L.z, L.zref, img * B, cs));
+      } else {
+        // split operators on the difference: g = g_ref + A~^H A~ (z - z_ref)
+        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs, L.zref));
+        EX_TRY(enc_forward_partials(p, L.eb, cs));
+        EX_TRY(enc_forward_residual(p, L.eb, nullptr, cs));
+        EX_TRY(enc_adjoint_partials(p, L.eb, cs));
+        if (padded) EX_TRY(copy_f2(L.z, L.v, img * B, cs));
+        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, L.sc + 1, L.z, cs, L.gref));
+      }
       EX_TRY(dwt_forward_levels(f, nxp, nyp, opts->levels, B, L.v, L.w, L.sc + 2 + B, with_obj ? L.l1 : nullptr,
                                 L.l1_blocks, cs));
       EX_TRY(dwt_inverse_levels(f, nxp, nyp, opts->levels, B, L.w, xk, xprev, L.z, beta[k], cs));
       if (with_obj) {
-        EX_TRY(enc_build_z(p, op->smaps, xk, img, nxp, L.eb, cs));
-        EX_TRY(enc_forward_partials(p, L.eb, cs));
-        EX_TRY(enc_forward_residual(p, L.eb, y2, cs));
-        k_resid_norm_part<<<dim3(kRedBlocks, B), 256, 0, cs>>>(L.eb.yop, p.Tp, p.NCP, p.C, L.dpart);
+        const EncPlan &pf = L.pf;
+        EX_TRY(enc_build_z(pf, op->smaps, xk, img, nxp, L.eb, cs));
+        EX_TRY(enc_forward_partials(pf, L.eb, cs));
+        EX_TRY(enc_forward_residual(pf, L.eb, y2, cs));
+        k_resid_norm_part<<<dim3(kRedBlocks, B), 256, 0, cs>>>(L.eb.yop, pf.Tp, pf.NCP, pf.C, L.dpart);
         EX_LAUNCHED("residual norm");
         EX_TRY(reduce_sum_parts(L.dpart, kRedBlocks, B, 1.0, L.data, cs));
         k_objective<<<B, 256, 0, cs>>>(L.data, L.l1, opts->levels, B, L.l1_blocks, nxp, L.sc + 2,

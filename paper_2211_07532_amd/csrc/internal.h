@@ -75,17 +75,25 @@ struct EncBuffers {
   float2 *zop = nullptr;   // forward operand: FP32 [Rp][NCP] or packed split
   float2 *yop = nullptr;   // adjoint operand: FP32 [Tp][NCP] or packed split
   float2 *part = nullptr;  // split-K partial sums (max of forward and adjoint)
+  void *zs = nullptr;      // split forms: packed hi/lo forward operand [Rp/16][NCP/16][4][64] x 16 B
+  void *ys = nullptr;      // split forms: packed hi/lo adjoint operand [Tp/16][NCP/16][4][64] x 16 B
+  float *dbet = nullptr;   // split forms: [Rp][NT] bet minus its 16-row tile centre (FP32)
+  float *dkap = nullptr;   // split forms: [Tp][NT] kap minus its 16-row tile centre (FP32)
 };
 
 size_t enc_operand_bytes(const EncPlan &p);
-int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b);
+// Split-K partial-sum elements (float2) a plan needs.
+size_t enc_part_elems(const EncPlan &p);
+// Carves the buffers of plan p; the partial-sum buffer gets at least
+// min_part float2 elements (so a second plan can share it).
+int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part = 0);
 
 // Kernel launchers (stream-ordered, no synchronisation).
 int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s);
 // Z[r][b*C+c] = S_c(r) x_b(r) from x [B][R] (x_stride elements between problems);
 // for split precisions, pre-split and packed in the MFMA operand order.
 int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x_stride,
-                int32_t x_row_stride, const EncBuffers &b, hipStream_t s);
+                int32_t x_row_stride, const EncBuffers &b, hipStream_t s, const float2 *xsub = nullptr);
 int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // y[b][t][c] = sum_split partials (ABI layout)
 int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s);
@@ -95,12 +103,23 @@ int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // x_b(r) = alpha * sum_c conj(S_c(r)) sum_split partials (+ add_b(r)),
 // written to x [B] with x_stride between problems and row stride
 // x_row_stride (pixels); alpha = *alpha_dev (device FP64) or 1 if NULL.
+// If base is given (same layout as x) it is added to the sum before scaling:
+// x = add + alpha * (base + sum).
 int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
                            int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
-                           const float2 *add, hipStream_t s);
+                           const float2 *add, hipStream_t s, const float2 *base = nullptr);
 // Residual r = A z - y (y_meas [B][T][C], or NULL for r = A z) written
 // straight into the adjoint operand.
 int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s);
+
+// Split-precision kernels (split.hip).
+int split_prepare(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
+                  int32_t x_row_stride, const EncBuffers &b, hipStream_t s);
+int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, const float2 *y_meas,
+                 const EncBuffers &b, hipStream_t s);
 
 // Per-kernel event timing of the contraction kernels (mode 0 off, 1 on, 2 read).
 int kernel_timing(int32_t mode, double *out);

@@ -1,0 +1,451 @@
+// Split-precision (bf16 or fp16 hi+lo) forms of the encoding contractions.
+//
+// Every operand value v (FP32) is written as hi + lo with hi = rnd(v) and
+// lo = rnd(v - hi) in the 16-bit format; a product a*b is taken as
+// a_hi*b_hi + a_hi*b_lo + a_lo*b_hi on v_mfma_f32_32x32x16_{bf16,f16} with FP32
+// accumulation (the lo*lo term, ~2^-2p relative, is dropped).  This runs the
+// contraction at the 16-bit MFMA rate with an error of about 3*2^-16 per
+// product (bf16) or 3*2^-22 (fp16) instead of 2^-8 / 2^-11 for a plain
+// 16-bit product.
+//
+// Layout of one MFMA step (K = 16 reduction indices): lane l holds 8
+// consecutive reduction indices 8*(l/32) .. 8*(l/32)+7 of row l%32 for the A
+// operand and of column l%32 for the B operand.  As in the FP32 kernels, each
+// lane first evaluates the phase tile for ITS OWN row against all 16
+// reduction indices (which are wave-uniform, so their field/basis values
+// come through scalar loads), splits and packs pairs into 32-bit words, and
+// v_permlane32_swap exchanges the half-waves so that the two 32-row MFMA
+// blocks receive their operands.  The B operand is pre-split and packed in
+// exactly the per-lane order (four 16-byte records per lane and step: b1 hi,
+// b1 lo, b2 hi, b2 lo), so the inner loop loads it with dwordx4 loads.
+#include "internal.h"
+
+namespace expenc {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Split two FP32 values into packed (hi, lo) 16-bit pairs.
+template <bool BF>
+__device__ inline void split_pair(float a, float b, uint32_t &hi, uint32_t &lo) {
+  if constexpr (BF) {
+    const bf16x2 h = {(__bf16)a, (__bf16)b};
+    hi = __builtin_bit_cast(uint32_t, h);
+    const float ah = __uint_as_float(hi << 16), bh = __uint_as_float(hi & 0xffff0000u);
+    const bf16x2 l = {(__bf16)(a - ah), (__bf16)(b - bh)};
+    lo = __builtin_bit_cast(uint32_t, l);
+  } else {
+    const f16x2 h = {(_Float16)a, (_Float16)b};
+    hi = __builtin_bit_cast(uint32_t, h);
+    const f16x2 l = {(_Float16)(a - (float)h[0]), (_Float16)(b - (float)h[1])};
+    lo = __builtin_bit_cast(uint32_t, l);
+  }
+}
+
+template <bool BF>
+__device__ inline f32x16 mfma16(u32x4 a, u32x4 b, f32x16 c) {
+  if constexpr (BF)
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                  0, 0, 0);
+}
+
+__device__ inline uint32_t swap_lo(uint32_t a, uint32_t b, uint32_t &hi_out) {
+  const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+  hi_out = r[1];
+  return r[0];
+}
+
+// Phase tile of one lane against 16 wave-uniform reduction indices, split,
+// packed and redistributed.
+//
+// The phase of the tile's centre index (index 8) is accumulated in FP64 and
+// reduced to [0,1) turns (anchor a).  The other 15 follow as
+//   phi_j = a + sum_k pf[k] * dq[j][k]          (FP32)
+// where pf is this lane's phase terms rounded to FP32 and dq[j] the
+// wave-uniform differences (index j minus index 8) of the other factor,
+// precomputed per tile in FP64 and rounded once.  Within a tile the
+// increments stay small (a few turns for 16 pixels along a row, under one
+// turn for 16 samples), so the FP32 rounding error of the increment is
+// about 1e-6 turn, well inside the split forms' error budget.  The uniform
+// differences (NT floats per index) are scalar-loaded one index ahead.
+//
+//   pv: this lane's FP64 terms; qc: the centre index's NT uniform FP64
+//   terms; dq: 16 x NT uniform FP32 differences.  On return A[blk][kind]
+//   (blk 0: rows 0..31, 1: rows 32..63; kind 0 c_hi, 1 c_lo, 2 s_hi, 3 s_lo)
+//   are the A operands of this step.
+template <int NT, bool BF>
+__device__ inline void phase_tile16(const double (&pv)[NT], const float (&pf)[NT], const double *__restrict__ qc,
+                                    const float *__restrict__ dq, u32x4 (&A)[2][4]) {
+  double pa = 0.0;
+#pragma unroll
+  for (int j = 0; j < NT; ++j) pa = fma(pv[j], qc[j], pa);
+  const float a = (float)__builtin_amdgcn_fract(pa);
+  __builtin_amdgcn_sched_barrier(0);
+  float c[16], sn[16];
+  float buf[2][NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) buf[0][j] = dq[j];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    if (i + 1 < 16) {
+      // An opaque (empty) redefinition of the uniform offset: the scalar
+      // loads of index i+1 cannot be merged with, or hoisted above, those of
+      // earlier indices, so only two indices' terms are live at a time.
+      int off = (i + 1) * NT;
+      __asm__ volatile("" : "+s"(off));
+#pragma unroll
+      for (int j = 0; j < NT; ++j) buf[(i + 1) & 1][j] = dq[off + j];
+    }
+    float ph = a;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) ph = fmaf(pf[j], buf[i & 1][j], ph);
+    const float f = __builtin_amdgcn_fractf(ph);
+    c[i] = __builtin_amdgcn_cosf(f);
+    sn[i] = __builtin_amdgcn_sinf(f);
+  }
+  uint32_t w[4][2][4];  // [kind][half of the 16 indices][word]
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int hf = m >> 2, wd = m & 3;
+    split_pair<BF>(c[2 * m], c[2 * m + 1], w[0][hf][wd], w[1][hf][wd]);
+    split_pair<BF>(sn[2 * m], sn[2 * m + 1], w[2][hf][wd], w[3][hf][wd]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t hi0, hi1, hi2, hi3;
+    const uint32_t lo0 = swap_lo(w[k][0][0], w[k][1][0], hi0);
+    const uint32_t lo1 = swap_lo(w[k][0][1], w[k][1][1], hi1);
+    const uint32_t lo2 = swap_lo(w[k][0][2], w[k][1][2], hi2);
+    const uint32_t lo3 = swap_lo(w[k][0][3], w[k][1][3], hi3);
+    A[0][k] = u32x4{lo0, lo1, lo2, lo3};
+    A[1][k] = u32x4{hi0, hi1, hi2, hi3};
+  }
+}
+
+// 6 MFMAs of one step for one 32-row block and one 32-column group:
+// cos against b1, sin against b2, each as hi*hi + hi*lo + lo*hi.
+template <bool BF>
+__device__ inline f32x16 step6(const u32x4 (&A)[4], const u32x4 *b, f32x16 acc) {
+  acc = mfma16<BF>(A[0], b[0], acc);
+  acc = mfma16<BF>(A[0], b[1], acc);
+  acc = mfma16<BF>(A[1], b[0], acc);
+  acc = mfma16<BF>(A[2], b[2], acc);
+  acc = mfma16<BF>(A[2], b[3], acc);
+  acc = mfma16<BF>(A[3], b[2], acc);
+  return acc;
+}
+
+template <int GW>
+__device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0, int lane, f32x16 (&acc)[2][GW]) {
+  const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        const int col = (g0 + g) * 16 + c16;
+        dst[(row * NCP + col) * 2 + im] = acc[a][g][v];
+      }
+}
+
+// Forward, split form: rows = samples, reduction over pixels (16 per step).
+template <int NT, int GW, bool BF>
+__global__ __launch_bounds__(256) void k_fwd_split(const double *__restrict__ kap, const double *__restrict__ bet,
+                                                   const float *__restrict__ dbet, const u32x4 *__restrict__ zs,
+                                                   float *__restrict__ part, int64_t Tp, int Rp, int NCP, int chunk,
+                                                   int nsplit) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int NGP = NCP / 16;
+  double kv[NT];
+  float kf[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    kv[j] = kap[(row0 + lane) * NT + j];
+    kf[j] = (float)kv[j];
+  }
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+  const int r0 = split * chunk;
+  const int r1 = min(Rp, r0 + chunk);
+  for (int r = r0; r < r1; r += 16) {
+    u32x4 A[2][4];
+    phase_tile16<NT, BF>(kv, kf, bet + (int64_t)(r + 8) * NT, dbet + (int64_t)r * NT, A);
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+      const u32x4 *zq = zs + ((int64_t)(r >> 4) * NGP + (g0 + g)) * 256 + lane;
+      const u32x4 b[4] = {zq[0], zq[64], zq[128], zq[192]};
+      acc[0][g] = step6<BF>(A[0], b, acc[0][g]);
+      acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
+    }
+  }
+  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc);
+}
+
+// Adjoint, split form: rows = pixels, reduction over samples (16 per step).
+// The A operand is exp(+i phi); the conjugation lives in the packed B operand.
+template <int NT, int GW, bool BF>
+__global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ kap, const double *__restrict__ bet,
+                                                   const float *__restrict__ dkap, const u32x4 *__restrict__ ys,
+                                                   float *__restrict__ part, int Rp, int64_t Tp, int NCP, int chunk,
+                                                   int nsplit) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int NGP = NCP / 16;
+  double bv[NT];
+  float bf[NT];
+#pragma unroll
+  for (int j = 0; j < NT; ++j) {
+    bv[j] = bet[(row0 + lane) * NT + j];
+    bf[j] = (float)bv[j];
+  }
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+  const int64_t t0 = (int64_t)split * chunk;
+  const int64_t t1 = min(Tp, t0 + chunk);
+  for (int64_t t = t0; t < t1; t += 16) {
+    u32x4 A[2][4];
+    phase_tile16<NT, BF>(bv, bf, kap + (t + 8) * NT, dkap + t * NT, A);
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+      const u32x4 *yq = ys + ((t >> 4) * NGP + (g0 + g)) * 256 + lane;
+      const u32x4 b[4] = {yq[0], yq[64], yq[128], yq[192]};
+      acc[0][g] = step6<BF>(A[0], b, acc[0][g]);
+      acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
+    }
+  }
+  store_partials<GW>(part + (int64_t)split * Rp * NCP * 2, row0, NCP, g0, lane, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Operand packing.  Record (step q, group g, lane l): 8 reduction indices
+// 16q + 8*(l/32) + i, column col = 16g + l%16, part = (l/16)&1.
+//   forward:  b1 = part ? Zi : Zr,   b2 = part ? Zr : -Zi
+//   adjoint:  b1 = part ? Yi : Yr,   b2 = part ? -Yr : Yi
+// ---------------------------------------------------------------------------
+
+template <bool BF>
+__device__ inline void write_record(u32x4 *out, int64_t q, int g, int NGP, int lane, const float (&b1)[8],
+                                    const float (&b2)[8]) {
+  uint32_t h1[4], l1[4], h2[4], l2[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    split_pair<BF>(b1[2 * m], b1[2 * m + 1], h1[m], l1[m]);
+    split_pair<BF>(b2[2 * m], b2[2 * m + 1], h2[m], l2[m]);
+  }
+  u32x4 *o = out + (q * NGP + g) * 256 + lane;
+  o[0] = u32x4{h1[0], h1[1], h1[2], h1[3]};
+  o[64] = u32x4{l1[0], l1[1], l1[2], l1[3]};
+  o[128] = u32x4{h2[0], h2[1], h2[2], h2[3]};
+  o[192] = u32x4{l2[0], l2[1], l2[2], l2[3]};
+}
+
+template <bool BF>
+__global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
+                                const float2 *__restrict__ xsub, int64_t x_stride, int x_row_stride, int nx, int R,
+                                int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs) {
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (int64_t)(Rp / 16) * NGP * 64) return;
+  const int lane = (int)(id & 63);
+  const int g = (int)((id >> 6) % NGP);
+  const int64_t q = (id >> 6) / NGP;
+  const int col = 16 * g + (lane & 15);
+  const int im = (lane >> 4) & 1;
+  float b1[8], b2[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int r = (int)(16 * q + 8 * (lane >> 5) + i);
+    float2 z = make_float2(0.f, 0.f);
+    if (r < R && col < NC) {
+      const int b = col / C, c = col % C;
+      const int64_t o = b * x_stride + (int64_t)(r / nx) * x_row_stride + (r % nx);
+      float2 u = x[o];
+      if (xsub) {
+        const float2 w = xsub[o];
+        u.x -= w.x;
+        u.y -= w.y;
+      }
+      const float2 s = smaps[(int64_t)c * R + r];
+      z = make_float2(s.x * u.x - s.y * u.y, s.x * u.y + s.y * u.x);
+    }
+    b1[i] = im ? z.y : z.x;
+    b2[i] = im ? z.x : -z.y;
+  }
+  write_record<BF>(zs, q, g, NGP, lane, b1, b2);
+}
+
+// Adjoint operand from y [B][T][C] (src_abi) or from forward partials minus
+// y_meas (src_part, nsplit partial arrays in [Tp][NCP] layout).
+template <bool BF>
+__global__ void k_pack_y_split(const float2 *__restrict__ src_abi, const float2 *__restrict__ src_part, int nsplit,
+                               const float2 *__restrict__ y_meas, int64_t T, int64_t Tp, int C, int NC, int NCP,
+                               u32x4 *__restrict__ ys) {
+  const int NGP = NCP / 16;
+  const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (id >= (Tp / 16) * NGP * 64) return;
+  const int lane = (int)(id & 63);
+  const int g = (int)((id >> 6) % NGP);
+  const int64_t q = (id >> 6) / NGP;
+  const int col = 16 * g + (lane & 15);
+  const int im = (lane >> 4) & 1;
+  float b1[8], b2[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const int64_t t = 16 * q + 8 * (lane >> 5) + i;
+    float2 y = make_float2(0.f, 0.f);
+    if (t < T && col < NC) {
+      const int b = col / C, c = col % C;
+      if (src_abi) {
+        y = src_abi[((int64_t)b * T + t) * C + c];
+      } else {
+        for (int k = 0; k < nsplit; ++k) {
+          const float2 v = src_part[((int64_t)k * Tp + t) * NCP + col];
+          y.x += v.x;
+          y.y += v.y;
+        }
+        if (y_meas) {
+          const float2 m = y_meas[((int64_t)b * T + t) * C + c];
+          y.x -= m.x;
+          y.y -= m.y;
+        }
+      }
+    }
+    b1[i] = im ? y.y : y.x;
+    b2[i] = im ? -y.x : y.y;
+  }
+  write_record<BF>(ys, q, g, NGP, lane, b1, b2);
+}
+
+// Per-tile differences d[16q + j][k] = (float)(src[16q + j][k] - src[16q + 8][k]).
+__global__ void k_tile_diff(const double *__restrict__ src, float *__restrict__ d, int64_t rows, int NT) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * NT) return;
+  const int64_t r = i / NT;
+  const int k = (int)(i % NT);
+  const int64_t centre = (r & ~int64_t(15)) + 8;
+  d[i] = (float)(src[r * NT + k] - src[centre * NT + k]);
+}
+
+int split_prepare(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  k_tile_diff<<<(unsigned)ceil_div((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(b.bet, b.dbet, p.Rp, p.NT);
+  EX_LAUNCHED("tile differences (pixels)");
+  k_tile_diff<<<(unsigned)ceil_div(p.Tp * p.NT, 256), 256, 0, s>>>(b.kap, b.dkap, p.Tp, p.NT);
+  EX_LAUNCHED("tile differences (samples)");
+  return EXPENC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <int NT, bool BF>
+static void launch_fwd_split(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY);
+  float *part = reinterpret_cast<float *>(b.part);
+  const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
+  if (p.GW == 2)
+    k_fwd_split<NT, 2, BF><<<grid, 256, 0, s>>>(b.kap, b.bet, b.dbet, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
+                                                p.fwd_split);
+  else
+    k_fwd_split<NT, 1, BF><<<grid, 256, 0, s>>>(b.kap, b.bet, b.dbet, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
+                                                p.fwd_split);
+}
+
+template <int NT, bool BF>
+static void launch_adj_split(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY);
+  float *part = reinterpret_cast<float *>(b.part);
+  const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
+  if (p.GW == 2)
+    k_adj_split<NT, 2, BF><<<grid, 256, 0, s>>>(b.kap, b.bet, b.dkap, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
+                                                p.adj_split);
+  else
+    k_adj_split<NT, 1, BF><<<grid, 256, 0, s>>>(b.kap, b.bet, b.dkap, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
+                                                p.adj_split);
+}
+
+template <bool BF>
+static void fwd_split_nt(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  switch (p.NT) {
+    case 4: launch_fwd_split<4, BF>(p, b, s); break;
+    case 10: launch_fwd_split<10, BF>(p, b, s); break;
+    default: launch_fwd_split<17, BF>(p, b, s); break;
+  }
+}
+
+template <bool BF>
+static void adj_split_nt(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  switch (p.NT) {
+    case 4: launch_adj_split<4, BF>(p, b, s); break;
+    case 10: launch_adj_split<10, BF>(p, b, s); break;
+    default: launch_adj_split<17, BF>(p, b, s); break;
+  }
+}
+
+void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  if (p.prec == EXPENC_BF16_SPLIT) fwd_split_nt<true>(p, b, s);
+  else fwd_split_nt<false>(p, b, s);
+}
+
+void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  if (p.prec == EXPENC_BF16_SPLIT) adj_split_nt<true>(p, b, s);
+  else adj_split_nt<false>(p, b, s);
+}
+
+int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
+                  int32_t x_row_stride, const EncBuffers &b, hipStream_t s) {
+  const int NGP = p.NCP / 16;
+  const int64_t n = (int64_t)(p.Rp / 16) * NGP * 64;
+  const unsigned nb = (unsigned)ceil_div(n, 256);
+  const float2 *sm = reinterpret_cast<const float2 *>(smaps);
+  u32x4 *zs = reinterpret_cast<u32x4 *>(b.zs);
+  if (p.prec == EXPENC_BF16_SPLIT)
+    k_build_z_split<true><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC, NGP, zs);
+  else
+    k_build_z_split<false><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC, NGP,
+                                              zs);
+  EX_LAUNCHED("build_z split");
+  return EXPENC_OK;
+}
+
+int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, const float2 *y_meas,
+                 const EncBuffers &b, hipStream_t s) {
+  const int NGP = p.NCP / 16;
+  const int64_t n = (p.Tp / 16) * NGP * 64;
+  const unsigned nb = (unsigned)ceil_div(n, 256);
+  u32x4 *ys = reinterpret_cast<u32x4 *>(b.ys);
+  const float2 *part = from_partials ? b.part : nullptr;
+  if (p.prec == EXPENC_BF16_SPLIT)
+    k_pack_y_split<true><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys);
+  else
+    k_pack_y_split<false><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys);
+  EX_LAUNCHED("pack_y split");
+  return EXPENC_OK;
+}
+
+}  // namespace expenc

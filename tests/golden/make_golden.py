@@ -1,0 +1,43 @@
+"""Writes the FP64 oracle's reference reconstruction of the 1.5 mm workload
+(148 x 148, 32 coils, T = 16384, 3rd-order field + dB0; 50 FISTA iterations
+with a 3-level db4 wavelet; L from 20 power steps from the seeded start
+vector; lambda = 1e-3 max|A^H y|) to mm15_fista.npz.  Calls only the oracle
+and the seeded input generator.  Takes several minutes on 8 cores.
+
+    python tests/golden/make_golden.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import synth  # noqa: E402
+from oracle import encoding, solve  # noqa: E402
+
+
+def c64(a):
+    return np.asarray(a).astype(np.complex64).astype(np.complex128)
+
+
+def main():
+    w = synth.MM15
+    p = synth.make_problem(w)
+    basis = encoding.sh_basis(w.n, w.fov, w.z0, w.nbasis)
+    op = solve.Operator(c64(p.smaps), p.coef, p.time, basis, p.dw0, w.n)
+    t0 = time.time()
+    y = c64(op.A(c64(p.x_noisy)))
+    v0 = c64(synth.power_start(w.npix, 7))
+    L = solve.power_lipschitz(op, v0, 20)
+    lam = solve.lambda_rule(op, y)
+    x = solve.fista(op, y, L, lam, w.n_iter, w.levels, w.wavelet, w.n_pad)
+    np.savez_compressed(os.path.join(HERE, "mm15_fista.npz"), x_hat=x.astype(np.complex128), lipschitz=L,
+                        lam=lam, n_iter=w.n_iter, n_power=20, power_seed=7)
+    print(f"wrote mm15_fista.npz: L={L:.6e} lambda={lam:.6e} ({time.time() - t0:.0f} s)")
+
+
+if __name__ == "__main__":
+    main()

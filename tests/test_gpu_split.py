@@ -1,0 +1,104 @@
+"""GPU parity of the split-precision (bf16 / fp16 hi+lo) operator forms and of
+the anchored-refinement FISTA against the FP64 oracle.
+
+Bars: relative l2 error of A / A^H <= 1e-3 in split form (the target for the
+split operators before refinement), and no worse than 5x the error level
+the RNE split emulation predicts for the same arithmetic; image NRMSE after
+a split-form solve with FP32 anchors <= 1e-4."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import encoding, solve, splitemu
+from tests.gpu_common import Case, c64, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _ee():
+    import paper_2211_07532_amd as ee
+    return ee
+
+
+def _emulated_forward_error(case, x, kind):
+    """Relative error of the 3-product split forward predicted by RNE
+    emulation, with the phase tile rounded to FP32 first (tiny sizes)."""
+    ph = encoding.phase(case.coef, case.time, case.basis_np, case.dw0)
+    e = np.exp(1j * ph).astype(np.complex64).astype(np.complex128)
+    z = (case.smaps * x[None, :]).T.astype(np.complex64).astype(np.complex128)
+    ref = np.exp(1j * ph) @ (case.smaps * x[None, :]).T
+    return rel(splitemu.split_cmatmul(e, z, kind), ref)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("name", ["tiny", "ragged"])
+def test_split_operators(prec, name):
+    ee = _ee()
+    if name == "tiny":
+        w = synth.TINY
+        case = Case(w)
+        batch = 2
+    else:
+        w = synth.Workload("ragged", 13, 0.1, 5, 333, 3e-6, 2.0, 16, 120.0, 20.0, 5, "haar", 1, 21)
+        case = Case(w, z0=0.004)
+        batch = 3
+    print(f"[case] split {prec} {name}", flush=True)
+    x = c64(synth.random_complex((batch, w.npix), 61))
+    x[0] = case.x_noisy
+    y_ref = encoding.forward(x, *case.oracle_args())
+    y = ee.forward(case.to_dev(x), case.op, precision=prec).cpu().numpy()
+    e_fwd = rel(y, y_ref)
+    g = c64(synth.random_complex(y_ref.shape, 62))
+    x_ref = encoding.adjoint(g, *case.oracle_args())
+    e_adj = rel(ee.adjoint(case.to_dev(g), case.op, precision=prec).cpu().numpy(), x_ref)
+    emu = _emulated_forward_error(case, case.x_noisy, prec)
+    print(f"split {prec} {name}: forward {e_fwd:.2e} adjoint {e_adj:.2e} emulated {emu:.2e}", flush=True)
+    assert e_fwd <= 1e-3 and e_adj <= 1e-3
+    assert e_fwd <= 5 * emu + 2e-6
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_split_full_size_sampled(prec):
+    ee = _ee()
+    wl = synth.MM15
+    case = Case(wl)
+    x = case.x_noisy
+    y = ee.forward(case.to_dev(x), case.op, precision=prec).cpu().numpy()
+    rng = np.random.default_rng(6)
+    ts = np.concatenate([[0, wl.nsamples - 1], rng.integers(0, wl.nsamples, 10)])
+    got = np.stack([y[t] for t in ts])
+    ref = np.stack([encoding.forward_one(x, *case.oracle_args(), int(t)) for t in ts])
+    e = rel(got, ref)
+    xa = ee.adjoint(case.to_dev(y), case.op, precision=prec).cpu().numpy()
+    rs = np.concatenate([[0, wl.npix - 1], rng.integers(0, wl.npix, 8)])
+    got = np.array([xa[r] for r in rs])
+    ref = np.array([encoding.adjoint_one(y.astype(np.complex128), *case.oracle_args(), int(r)) for r in rs])
+    e2 = rel(got, ref)
+    print(f"split {prec} full: forward {e:.2e} adjoint {e2:.2e}", flush=True)
+    assert e <= 1e-3 and e2 <= 1e-3
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("variant", ["tiny", "padded-db4"])
+def test_split_fista_with_anchors(prec, variant):
+    ee = _ee()
+    if variant == "tiny":
+        w = synth.TINY
+    else:
+        w = synth.Workload("pad", 20, 0.2, 6, 900, 3e-6, 2.0, 16, 80.0, 20.0, 30, "db4", 3, 51)
+    case = Case(w)
+    op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
+    y = c64(op.A(case.x_noisy))
+    L = solve.power_lipschitz(op, c64(synth.power_start(w.npix, 4)), 30)
+    lam = solve.lambda_rule(op, y)
+    ref = solve.fista(op, y, L, lam, w.n_iter, w.levels, w.wavelet, w.n_pad)
+    res = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam,
+                   refine_every=10)
+    e = solve.nrmse(res.x.cpu().numpy().reshape(-1), ref)
+    # without intermediate anchors (only the first and the last iteration are exact)
+    res0 = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam,
+                    refine_every=10 ** 6)
+    e0 = solve.nrmse(res0.x.cpu().numpy().reshape(-1), ref)
+    print(f"split FISTA {prec} {variant}: NRMSE {e:.2e} (anchored every 10), {e0:.2e} (no intermediate anchor)",
+          flush=True)
+    assert e <= 1e-4
