@@ -75,8 +75,9 @@ def main():
     coef = torch.from_numpy(prob.coef).to(dev)
     tm = torch.from_numpy(prob.time).to(dev)
     dw0 = torch.from_numpy(prob.dw0).to(dev)
-    basis = ee.sh_basis(w.n, w.n, w.fov, w.fov, w.z0, w.nbasis, device=dev)
-    op = ee.Operator(w.n, w.n, smaps, coef, tm, basis, dw0)
+    # the field basis is the solid-harmonic set on the image grid: declared by
+    # geometry, the library evaluates it (and uses its polynomial form)
+    op = ee.Operator(w.n, w.n, smaps, coef, tm, None, dw0, sh_grid=(w.fov, w.fov, w.z0))
     x_noisy = torch.from_numpy(prob.x_noisy.astype(np.complex64)).to(dev)
     y = ee.forward(x_noisy, op)                      # synthetic k-space of the noisy object
     v0 = torch.from_numpy(synth.power_start(w.npix, 7).astype(np.complex64)).to(dev)

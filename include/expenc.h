@@ -76,6 +76,15 @@ enum {
   EXPENC_WS_FIELD_GRAD = 5
 };
 
+/* How the field basis b_l(r) is given. */
+enum {
+  EXPENC_BASIS_MAPS = 0,  /* `basis` holds b_l(r) for every pixel (any basis)            */
+  EXPENC_BASIS_SH = 1     /* b_l are the real solid harmonics of expenc_sh_basis on the
+                             grid (fov_x, fov_y, z0); `basis` is ignored and may be NULL.
+                             The split forms then evaluate the phase as a cubic
+                             polynomial in (x, y) (same values, fewer operations).      */
+};
+
 /*
  * One expanded-encoding operator (the entry formula above).  B problems may
  * share it (same field, same coils), in which case their coil data form the
@@ -91,6 +100,9 @@ typedef struct expenc_op {
   const double *time;      /* [T] seconds from the first sample                      */
   const double *dw0;       /* [R] off-resonance in rad/s, or NULL for none           */
   const float *smaps;      /* [C][R] complex64 coil sensitivities S_c(r)             */
+  int32_t basis_kind;      /* EXPENC_BASIS_MAPS or EXPENC_BASIS_SH                   */
+  int32_t reserved;        /* must be 0                                              */
+  double fov_x, fov_y, z0; /* EXPENC_BASIS_SH: grid geometry in metres (as expenc_sh_basis) */
 } expenc_op;
 
 /*

@@ -20,6 +20,7 @@ EXPENC_ENONFINITE = -5
 
 FP32, BF16_SPLIT, FP16_SPLIT = 0, 1, 2
 HAAR, DB4 = 0, 1
+BASIS_MAPS, BASIS_SH = 0, 1
 WS_FORWARD, WS_ADJOINT, WS_FISTA, WS_LIPSCHITZ, WS_CG, WS_FIELD_GRAD = range(6)
 
 _c_int = ctypes.c_int32
@@ -33,6 +34,8 @@ class ExpencOp(ctypes.Structure):
         ("ncoils", ctypes.c_int32), ("nbasis", ctypes.c_int32),
         ("nsamples", ctypes.c_int64),
         ("basis", _vp), ("coef", _vp), ("time", _vp), ("dw0", _vp), ("smaps", _vp),
+        ("basis_kind", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("fov_x", ctypes.c_double), ("fov_y", ctypes.c_double), ("z0", ctypes.c_double),
     ]
 
 

@@ -37,6 +37,28 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 static constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
 
+// Real solid harmonics up to 3rd order at (x, y, z), in the basis order of
+// expenc_sh_basis.
+__device__ inline void sh_eval(double x, double y, double z, double (&v)[16]) {
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  v[0] = 1.0;
+  v[1] = x;
+  v[2] = y;
+  v[3] = z;
+  v[4] = x * y;
+  v[5] = y * z;
+  v[6] = 2.0 * z2 - x2 - y2;
+  v[7] = x * z;
+  v[8] = x2 - y2;
+  v[9] = y * (3.0 * x2 - y2);
+  v[10] = x * y * z;
+  v[11] = y * (4.0 * z2 - x2 - y2);
+  v[12] = z * (2.0 * z2 - 3.0 * x2 - 3.0 * y2);
+  v[13] = x * (4.0 * z2 - x2 - y2);
+  v[14] = z * (x2 - y2);
+  v[15] = x * (x2 - 3.0 * y2);
+}
+
 // ---------------------------------------------------------------------------
 // Setup kernels
 // ---------------------------------------------------------------------------
@@ -53,6 +75,26 @@ __global__ void k_prep_kap(const double *__restrict__ coef, const double *__rest
     else if (j == L) v = time[t];
   }
   kap[i] = v;
+}
+
+// bet for EXPENC_BASIS_SH: the solid harmonics evaluated at the pixel centres.
+__global__ void k_prep_bet_sh(const double *__restrict__ dw0, double *__restrict__ bet, int nx, int ny, int Rp, int L,
+                              int NT, double dx, double dy, double z) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Rp * NT) return;
+  const int r = (int)(i / NT);
+  const int j = (int)(i % NT);
+  double v = 0.0;
+  if (r < nx * ny) {
+    if (j < L) {
+      double b[16];
+      sh_eval((r % nx - 0.5 * nx) * dx, (r / nx - 0.5 * ny) * dy, z, b);
+      v = b[j];
+    } else if (j == L && dw0) {
+      v = dw0[r] * kInv2Pi;
+    }
+  }
+  bet[i] = v;
 }
 
 __global__ void k_prep_bet(const double *__restrict__ basis, const double *__restrict__ dw0,
@@ -304,17 +346,18 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
                                                         float2 *__restrict__ x, int64_t x_stride,
                                                         int x_row_stride, const double *__restrict__ alpha_dev,
                                                         const float2 *__restrict__ add,
-                                                        const float2 *__restrict__ base) {
+                                                        const float2 *__restrict__ base, int nxq) {
   const int sub = threadIdx.x & 31;
   const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
   if (r >= R) return;  // uniform per 32-lane group
+  const int64_t rq = (int64_t)(r / nx) * nxq + (r % nx);  // row of the partial sums
   for (int b = 0; b < B; ++b) {
     float sx = 0.f, sy = 0.f;
     for (int c = sub; c < C; c += 32) {
       const int col = b * C + c;
       float2 u = make_float2(0.f, 0.f);
       for (int k = 0; k < nsplit; ++k) {
-        float2 v = part[((int64_t)k * Rp + r) * NCP + col];
+        float2 v = part[((int64_t)k * Rp + rq) * NCP + col];
         u.x += v.x;
         u.y += v.y;
       }
@@ -371,7 +414,14 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p)
   if (op->ncoils < 1) return fail(EXPENC_EINVAL, "ncoils must be >= 1 (got %d)", op->ncoils);
   if (op->nbasis < 0 || op->nbasis > 16) return fail(EXPENC_EINVAL, "nbasis must be in [0,16] (got %d)", op->nbasis);
   if (op->nsamples < 1 || op->nsamples > (int64_t(1) << 31)) return fail(EXPENC_EINVAL, "nsamples out of range");
-  if (op->nbasis > 0 && (!op->basis || !op->coef)) return fail(EXPENC_EINVAL, "basis/coef NULL with nbasis > 0");
+  if (op->basis_kind != EXPENC_BASIS_MAPS && op->basis_kind != EXPENC_BASIS_SH)
+    return fail(EXPENC_EINVAL, "unknown basis_kind %d", op->basis_kind);
+  if (op->reserved != 0) return fail(EXPENC_EINVAL, "reserved field must be 0");
+  if (op->basis_kind == EXPENC_BASIS_SH && !(op->fov_x > 0 && op->fov_y > 0))
+    return fail(EXPENC_EINVAL, "EXPENC_BASIS_SH needs fov_x, fov_y > 0");
+  if (op->nbasis > 0 && !op->coef) return fail(EXPENC_EINVAL, "coef NULL with nbasis > 0");
+  if (op->nbasis > 0 && op->basis_kind == EXPENC_BASIS_MAPS && !op->basis)
+    return fail(EXPENC_EINVAL, "basis NULL with nbasis > 0 and EXPENC_BASIS_MAPS");
   if (!op->time) return fail(EXPENC_EINVAL, "time array is NULL");
   if (!op->smaps) return fail(EXPENC_EINVAL, "smaps is NULL");
   if (batch < 1) return fail(EXPENC_EINVAL, "batch must be >= 1 (got %d)", batch);
@@ -382,7 +432,12 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p)
   q.nx = op->nx;
   q.ny = op->ny;
   q.R = op->nx * op->ny;
-  q.Rp = (int32_t)round_up(q.R, 256);
+  q.sh = op->basis_kind == EXPENC_BASIS_SH;
+  q.nxq = (q.sh && precision != EXPENC_FP32) ? (int32_t)round_up(op->nx, 16) : op->nx;
+  q.dx = q.sh ? op->fov_x / op->nx : 0.0;
+  q.dy = q.sh ? op->fov_y / op->ny : 0.0;
+  q.z0 = q.sh ? op->z0 : 0.0;
+  q.Rp = (int32_t)round_up((int64_t)q.nxq * op->ny, 256);
   q.T = op->nsamples;
   q.Tp = round_up(q.T, 256);
   q.C = op->ncoils;
@@ -439,8 +494,15 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
   if (p.prec != EXPENC_FP32) {
     b->zs = a.take<char>((size_t)p.Rp * (p.NCP / 16) * 256);
     b->ys = a.take<char>((size_t)p.Tp * (p.NCP / 16) * 256);
-    b->dbet = a.take<float>((size_t)p.Rp * p.NT);
-    b->dkap = a.take<float>((size_t)p.Tp * p.NT);
+    if (p.sh) {
+      b->pmono = a.take<double>((size_t)p.Tp * 12);
+      b->dpmono = a.take<float>((size_t)p.Tp * 12);
+      b->dwq = a.take<double>((size_t)p.Rp);
+      b->ddw = a.take<float>((size_t)p.Rp);
+    } else {
+      b->dbet = a.take<float>((size_t)p.Rp * p.NT);
+      b->dkap = a.take<float>((size_t)p.Tp * p.NT);
+    }
   }
   return a.ok() ? EXPENC_OK : EXPENC_EWORKSPACE;
 }
@@ -450,9 +512,17 @@ static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)ceil_div
 int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
   k_prep_kap<<<blocks_for(p.Tp * p.NT, 256), 256, 0, s>>>(op->coef, op->time, b.kap, p.T, p.Tp, p.L, p.NT);
   EX_LAUNCHED("prep_kap");
-  k_prep_bet<<<blocks_for((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L, p.NT);
-  EX_LAUNCHED("prep_bet");
-  if (p.prec != EXPENC_FP32) return split_prepare(p, b, s);
+  const bool split = p.prec != EXPENC_FP32;
+  if (!(split && p.sh)) {  // the polynomial split kernels do not read bet
+    if (p.sh)
+      k_prep_bet_sh<<<blocks_for((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(op->dw0, b.bet, p.nx, p.ny, p.Rp, p.L,
+                                                                          p.NT, p.dx, p.dy, p.z0);
+    else
+      k_prep_bet<<<blocks_for((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L,
+                                                                       p.NT);
+    EX_LAUNCHED("prep_bet");
+  }
+  if (split) return split_prepare(p, op, b, s);
   return EXPENC_OK;
 }
 
@@ -628,7 +698,7 @@ int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *s
                            const float2 *add, hipStream_t s, const float2 *base) {
   k_adj_reduce_out<<<blocks_for(p.R, 8), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
                                                       reinterpret_cast<const float2 *>(smaps), x, x_stride,
-                                                      x_row_stride, alpha_dev, add, base);
+                                                      x_row_stride, alpha_dev, add, base, p.nxq);
   EX_LAUNCHED("adjoint reduce");
   return EXPENC_OK;
 }

@@ -355,7 +355,9 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
   const float2 *y2 = reinterpret_cast<const float2 *>(y);
 
   // ---- prologue (eager, stream-ordered) ----
-  EX_TRY(enc_prepare(p, op, L.eb, s));
+  // FP32 tables first (the FP32 plan's pixel layout), then the split tables
+  EX_TRY(enc_prepare(L.pf, op, L.eb, s));
+  if (opts->precision != EXPENC_FP32) EX_TRY(enc_prepare(p, op, L.eb, s));
   if (opts->lipschitz > 0) {
     k_fill_d<<<1, 64, 0, s>>>(L.sc, 1, opts->lipschitz);
     EX_LAUNCHED("fill");

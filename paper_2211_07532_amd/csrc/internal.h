@@ -64,6 +64,12 @@ struct EncPlan {
   int32_t fwd_split = 1, fwd_chunk = 0;   // split-K over pixels
   int32_t adj_split = 1, adj_chunk = 0;   // split-K over samples
   bool has_dw0 = false;
+  // Solid-harmonic basis given by grid geometry (EXPENC_BASIS_SH).  Split
+  // forms with it lay pixels out row-padded: r' = y*nxq + x, nxq = nx rounded
+  // up to 16, so that every 16-pixel step lies inside one image row.
+  bool sh = false;
+  int32_t nxq = 0;                        // padded row length of the pixel index
+  double dx = 0, dy = 0, z0 = 0;          // pixel pitch and slice position (metres)
 };
 
 int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p);
@@ -79,6 +85,10 @@ struct EncBuffers {
   void *ys = nullptr;      // split forms: packed hi/lo adjoint operand [Tp/16][NCP/16][4][64] x 16 B
   float *dbet = nullptr;   // split forms: [Rp][NT] bet minus its 16-row tile centre (FP32)
   float *dkap = nullptr;   // split forms: [Tp][NT] kap minus its 16-row tile centre (FP32)
+  double *pmono = nullptr; // split + SH: [Tp][12] cubic-monomial phase coefficients (turns) and t
+  float *dpmono = nullptr; // split + SH: [Tp][12] pmono minus its 16-row tile centre (FP32)
+  double *dwq = nullptr;   // split + SH: [Rp] dw0/2pi in the row-padded pixel layout
+  float *ddw = nullptr;    // split + SH: [Rp] dwq minus its 16-pixel tile centre (FP32)
 };
 
 size_t enc_operand_bytes(const EncPlan &p);
@@ -113,7 +123,7 @@ int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *s
 int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s);
 
 // Split-precision kernels (split.hip).
-int split_prepare(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s);
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,

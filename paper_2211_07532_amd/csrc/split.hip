@@ -62,6 +62,31 @@ __device__ inline uint32_t swap_lo(uint32_t a, uint32_t b, uint32_t &hi_out) {
   return r[0];
 }
 
+// Split the 16 (cos, sin) values of one lane into hi/lo 16-bit pairs, pack
+// them into 32-bit words and exchange half-waves so that
+//   A[blk][kind] (blk 0: rows 0..31, 1: rows 32..63; kind 0 c_hi, 1 c_lo, 2 s_hi, 3 s_lo)
+// are the A operands of this step.
+template <bool BF>
+__device__ inline void pack_tile16(const float (&c)[16], const float (&sn)[16], u32x4 (&A)[2][4]) {
+  uint32_t w[4][2][4];  // [kind][half of the 16 indices][word]
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const int hf = m >> 2, wd = m & 3;
+    split_pair<BF>(c[2 * m], c[2 * m + 1], w[0][hf][wd], w[1][hf][wd]);
+    split_pair<BF>(sn[2 * m], sn[2 * m + 1], w[2][hf][wd], w[3][hf][wd]);
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    uint32_t hi0, hi1, hi2, hi3;
+    const uint32_t lo0 = swap_lo(w[k][0][0], w[k][1][0], hi0);
+    const uint32_t lo1 = swap_lo(w[k][0][1], w[k][1][1], hi1);
+    const uint32_t lo2 = swap_lo(w[k][0][2], w[k][1][2], hi2);
+    const uint32_t lo3 = swap_lo(w[k][0][3], w[k][1][3], hi3);
+    A[0][k] = u32x4{lo0, lo1, lo2, lo3};
+    A[1][k] = u32x4{hi0, hi1, hi2, hi3};
+  }
+}
+
 // Phase tile of one lane against 16 wave-uniform reduction indices, split,
 // packed and redistributed.
 //
@@ -110,23 +135,7 @@ __device__ inline void phase_tile16(const double (&pv)[NT], const float (&pf)[NT
     c[i] = __builtin_amdgcn_cosf(f);
     sn[i] = __builtin_amdgcn_sinf(f);
   }
-  uint32_t w[4][2][4];  // [kind][half of the 16 indices][word]
-#pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const int hf = m >> 2, wd = m & 3;
-    split_pair<BF>(c[2 * m], c[2 * m + 1], w[0][hf][wd], w[1][hf][wd]);
-    split_pair<BF>(sn[2 * m], sn[2 * m + 1], w[2][hf][wd], w[3][hf][wd]);
-  }
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    uint32_t hi0, hi1, hi2, hi3;
-    const uint32_t lo0 = swap_lo(w[k][0][0], w[k][1][0], hi0);
-    const uint32_t lo1 = swap_lo(w[k][0][1], w[k][1][1], hi1);
-    const uint32_t lo2 = swap_lo(w[k][0][2], w[k][1][2], hi2);
-    const uint32_t lo3 = swap_lo(w[k][0][3], w[k][1][3], hi3);
-    A[0][k] = u32x4{lo0, lo1, lo2, lo3};
-    A[1][k] = u32x4{hi0, hi1, hi2, hi3};
-  }
+  pack_tile16<BF>(c, sn, A);
 }
 
 // 6 MFMAs of one step for one 32-row block and one 32-column group:
@@ -242,6 +251,164 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
   store_partials<GW>(part + (int64_t)split * Rp * NCP * 2, row0, NCP, g0, lane, acc);
 }
 
+
+// ---------------------------------------------------------------------------
+// Split forms with the solid-harmonic basis in polynomial form.  With z
+// fixed, sum_l k_l(t) b_l(x, y) is a cubic polynomial in (x, y) whose ten
+// monomial coefficients P_m(t) (turns) are formed once per sample.
+//
+// Forward (lane = sample t, 16 pixels of one image row per step): along the
+// row the phase is a cubic in x.  Each lane expands it around the tile
+// centre x_c in FP64: the anchor phi(x_c) reduced to [0,1), and the scaled
+// Taylor coefficients d1 = phi_x dx, d2 = phi_xx dx^2 / 2, d3 = phi_xxx dx^3 / 6.
+// Pixel x_c + k dx (k = -8..7, a literal) then costs three FP32 FMAs, plus
+// one for the off-resonance difference t (dw0(r) - dw0(r_c)) / 2pi.
+//
+// Adjoint (lane = pixel, 16 samples per step): the FP64 anchor at the tile's
+// centre sample, then FP32 increments sum_m (P_m(t_j) - P_m(t_c)) mono_m(r)
+// + (t_j - t_c) dw0(r)/2pi over the ten monomials (one of which is 1).
+// ---------------------------------------------------------------------------
+
+template <int GW, bool BF>
+__global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__ pmono, const double *__restrict__ dwq,
+                                                      const float *__restrict__ ddw, const u32x4 *__restrict__ zs,
+                                                      float *__restrict__ part, int64_t Tp, int Rp, int NCP, int chunk,
+                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int NGP = NCP / 16;
+  double P[10];
+#pragma unroll
+  for (int m = 0; m < 10; ++m) P[m] = pmono[(row0 + lane) * 12 + m];
+  const double tt = pmono[(row0 + lane) * 12 + 10];
+  const float tf = (float)tt;
+  const double dx2 = dx * dx, dx3 = dx2 * dx;
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+  const int r0 = split * chunk;
+  const int r1 = min(Rp, r0 + chunk);
+  for (int r = r0; r < r1; r += 16) {
+    const int yi = r / nxq, xi = r % nxq + 8;
+    const double ym = (yi - 0.5 * ny) * dy, xc = (xi - 0.5 * nx) * dx;
+    const double a0 = P[0] + ym * (P[2] + ym * (P[5] + ym * P[9]));
+    const double a1 = P[1] + ym * (P[4] + ym * P[8]);
+    const double a2 = P[3] + ym * P[7];
+    const double a3 = P[6];
+    const double phc = fma(tt, dwq[r + 8], a0 + xc * (a1 + xc * (a2 + xc * a3)));
+    const float an = (float)__builtin_amdgcn_fract(phc);
+    const float d1 = (float)((a1 + xc * (2.0 * a2 + 3.0 * a3 * xc)) * dx);
+    const float d2 = (float)((a2 + 3.0 * a3 * xc) * dx2);
+    const float d3 = (float)(a3 * dx3);
+    float c[16], sn[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const float k = (float)(j - 8);
+      float ph = fmaf(fmaf(fmaf(d3, k, d2), k, d1), k, an);
+      ph = fmaf(tf, ddw[r + j], ph);
+      const float f = __builtin_amdgcn_fractf(ph);
+      c[j] = __builtin_amdgcn_cosf(f);
+      sn[j] = __builtin_amdgcn_sinf(f);
+    }
+    u32x4 A[2][4];
+    pack_tile16<BF>(c, sn, A);
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+      const u32x4 *zq = zs + ((int64_t)(r >> 4) * NGP + (g0 + g)) * 256 + lane;
+      const u32x4 b[4] = {zq[0], zq[64], zq[128], zq[192]};
+      acc[0][g] = step6<BF>(A[0], b, acc[0][g]);
+      acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
+    }
+  }
+  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc);
+}
+
+template <int GW, bool BF>
+__global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__ pmono, const float *__restrict__ dpmono,
+                                                      const double *__restrict__ dwq, const u32x4 *__restrict__ ys,
+                                                      float *__restrict__ part, int Rp, int64_t Tp, int NCP, int chunk,
+                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int split = blockIdx.x % nsplit;
+  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int NGP = NCP / 16;
+  const int rq = (int)(row0 + lane);
+  const double xm = (rq % nxq - 0.5 * nx) * dx, ym = (rq / nxq - 0.5 * ny) * dy;
+  double mono[11];
+  mono[0] = 1.0;
+  mono[1] = xm;
+  mono[2] = ym;
+  mono[3] = xm * xm;
+  mono[4] = xm * ym;
+  mono[5] = ym * ym;
+  mono[6] = xm * xm * xm;
+  mono[7] = xm * xm * ym;
+  mono[8] = xm * ym * ym;
+  mono[9] = ym * ym * ym;
+  mono[10] = dwq[rq];
+  float mf[11];
+#pragma unroll
+  for (int m = 0; m < 11; ++m) mf[m] = (float)mono[m];
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+  const int64_t t0 = (int64_t)split * chunk;
+  const int64_t t1 = min(Tp, t0 + chunk);
+  for (int64_t t = t0; t < t1; t += 16) {
+    const double *pc = pmono + (t + 8) * 12;
+    double pa = 0.0;
+#pragma unroll
+    for (int m = 0; m < 11; ++m) pa = fma(pc[m], mono[m], pa);
+    const float an = (float)__builtin_amdgcn_fract(pa);
+    __builtin_amdgcn_sched_barrier(0);
+    const float *dq = dpmono + t * 12;
+    float c[16], sn[16];
+    float buf[2][11];
+#pragma unroll
+    for (int m = 0; m < 11; ++m) buf[0][m] = dq[m];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      if (i + 1 < 16) {
+        // opaque offset: keeps the next sample's scalar loads from being
+        // merged with, or hoisted above, the current ones
+        int off = (i + 1) * 12;
+        __asm__ volatile("" : "+s"(off));
+#pragma unroll
+        for (int m = 0; m < 11; ++m) buf[(i + 1) & 1][m] = dq[off + m];
+      }
+      float ph = an + buf[i & 1][0];
+#pragma unroll
+      for (int m = 1; m < 11; ++m) ph = fmaf(buf[i & 1][m], mf[m], ph);
+      const float f = __builtin_amdgcn_fractf(ph);
+      c[i] = __builtin_amdgcn_cosf(f);
+      sn[i] = __builtin_amdgcn_sinf(f);
+    }
+    u32x4 A[2][4];
+    pack_tile16<BF>(c, sn, A);
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+      const u32x4 *yq = ys + ((t >> 4) * NGP + (g0 + g)) * 256 + lane;
+      const u32x4 b[4] = {yq[0], yq[64], yq[128], yq[192]};
+      acc[0][g] = step6<BF>(A[0], b, acc[0][g]);
+      acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
+    }
+  }
+  store_partials<GW>(part + (int64_t)split * Rp * NCP * 2, row0, NCP, g0, lane, acc);
+}
+
 // ---------------------------------------------------------------------------
 // Operand packing.  Record (step q, group g, lane l): 8 reduction indices
 // 16q + 8*(l/32) + i, column col = 16g + l%16, part = (l/16)&1.
@@ -267,8 +434,9 @@ __device__ inline void write_record(u32x4 *out, int64_t q, int g, int NGP, int l
 
 template <bool BF>
 __global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
-                                const float2 *__restrict__ xsub, int64_t x_stride, int x_row_stride, int nx, int R,
-                                int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs) {
+                                const float2 *__restrict__ xsub, int64_t x_stride, int x_row_stride, int nx, int ny,
+                                int nxq, int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs) {
+  const int R = nx * ny;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)(Rp / 16) * NGP * 64) return;
   const int lane = (int)(id & 63);
@@ -279,11 +447,13 @@ __global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *
   float b1[8], b2[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int r = (int)(16 * q + 8 * (lane >> 5) + i);
+    const int rq = (int)(16 * q + 8 * (lane >> 5) + i);
+    const int yy = rq / nxq, xx = rq % nxq;
     float2 z = make_float2(0.f, 0.f);
-    if (r < R && col < NC) {
+    if (yy < ny && xx < nx && col < NC) {
       const int b = col / C, c = col % C;
-      const int64_t o = b * x_stride + (int64_t)(r / nx) * x_row_stride + (r % nx);
+      const int r = yy * nx + xx;
+      const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
       float2 u = x[o];
       if (xsub) {
         const float2 w = xsub[o];
@@ -351,7 +521,71 @@ __global__ void k_tile_diff(const double *__restrict__ src, float *__restrict__ 
   d[i] = (float)(src[r * NT + k] - src[centre * NT + k]);
 }
 
-int split_prepare(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+// Monomial coefficients of the solid harmonics at fixed z (rows l, columns
+// m over 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3).
+struct MonoMatrix {
+  double m[16][10];
+};
+
+static MonoMatrix mono_matrix(double z) {
+  MonoMatrix M{};
+  auto &m = M.m;
+  m[0][0] = 1;
+  m[1][1] = 1;
+  m[2][2] = 1;
+  m[3][0] = z;
+  m[4][4] = 1;
+  m[5][2] = z;
+  m[6][0] = 2 * z * z, m[6][3] = -1, m[6][5] = -1;
+  m[7][1] = z;
+  m[8][3] = 1, m[8][5] = -1;
+  m[9][7] = 3, m[9][9] = -1;
+  m[10][4] = z;
+  m[11][2] = 4 * z * z, m[11][7] = -1, m[11][9] = -1;
+  m[12][0] = 2 * z * z * z, m[12][3] = -3 * z, m[12][5] = -3 * z;
+  m[13][1] = 4 * z * z, m[13][6] = -1, m[13][8] = -1;
+  m[14][3] = z, m[14][5] = -z;
+  m[15][6] = 1, m[15][8] = -3;
+  return M;
+}
+
+// pmono[t][m] = sum_l kap[t][l] M[l][m] (m < 10), pmono[t][10] = t.
+__global__ void k_prep_pmono(const double *__restrict__ kap, int NT, int L, int64_t Tp, MonoMatrix M,
+                             double *__restrict__ pmono) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Tp) return;
+  double out[12];
+  for (int m = 0; m < 12; ++m) out[m] = 0.0;
+  for (int l = 0; l < L; ++l) {
+    const double k = kap[t * NT + l];
+    for (int m = 0; m < 10; ++m) out[m] = fma(k, M.m[l][m], out[m]);
+  }
+  out[10] = kap[t * NT + L];
+  for (int m = 0; m < 12; ++m) pmono[t * 12 + m] = out[m];
+}
+
+// dwq[r'] = dw0(r)/2pi in the row-padded pixel layout.
+__global__ void k_prep_dwq(const double *__restrict__ dw0, int nx, int ny, int nxq, int Rp, double *__restrict__ dwq) {
+  const int rq = blockIdx.x * blockDim.x + threadIdx.x;
+  if (rq >= Rp) return;
+  const int yy = rq / nxq, xx = rq % nxq;
+  double v = 0.0;
+  if (dw0 && yy < ny && xx < nx) v = dw0[yy * nx + xx] * 0.15915494309189533576888376337251436;
+  dwq[rq] = v;
+}
+
+int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
+  if (p.sh) {
+    k_prep_pmono<<<(unsigned)ceil_div(p.Tp, 256), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), b.pmono);
+    EX_LAUNCHED("monomial coefficients");
+    k_tile_diff<<<(unsigned)ceil_div(p.Tp * 12, 256), 256, 0, s>>>(b.pmono, b.dpmono, p.Tp, 12);
+    EX_LAUNCHED("tile differences (samples)");
+    k_prep_dwq<<<(unsigned)ceil_div(p.Rp, 256), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);
+    EX_LAUNCHED("off-resonance layout");
+    k_tile_diff<<<(unsigned)ceil_div(p.Rp, 256), 256, 0, s>>>(b.dwq, b.ddw, p.Rp, 1);
+    EX_LAUNCHED("tile differences (pixels)");
+    return EXPENC_OK;
+  }
   k_tile_diff<<<(unsigned)ceil_div((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(b.bet, b.dbet, p.Rp, p.NT);
   EX_LAUNCHED("tile differences (pixels)");
   k_tile_diff<<<(unsigned)ceil_div(p.Tp * p.NT, 256), 256, 0, s>>>(b.kap, b.dkap, p.Tp, p.NT);
@@ -407,14 +641,52 @@ static void adj_split_nt(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   }
 }
 
+template <bool BF>
+static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY);
+  float *part = reinterpret_cast<float *>(b.part);
+  const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
+  if (p.GW == 2)
+    k_fwd_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.ddw, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
+                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+  else
+    k_fwd_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.ddw, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
+                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+}
+
+template <bool BF>
+static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY);
+  float *part = reinterpret_cast<float *>(b.part);
+  const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
+  if (p.GW == 2)
+    k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpmono, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
+                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+  else
+    k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpmono, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
+                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+}
+
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  if (p.prec == EXPENC_BF16_SPLIT) fwd_split_nt<true>(p, b, s);
-  else fwd_split_nt<false>(p, b, s);
+  const bool bf = p.prec == EXPENC_BF16_SPLIT;
+  if (p.sh) {
+    if (bf) fwd_split_sh<true>(p, b, s);
+    else fwd_split_sh<false>(p, b, s);
+  } else {
+    if (bf) fwd_split_nt<true>(p, b, s);
+    else fwd_split_nt<false>(p, b, s);
+  }
 }
 
 void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  if (p.prec == EXPENC_BF16_SPLIT) adj_split_nt<true>(p, b, s);
-  else adj_split_nt<false>(p, b, s);
+  const bool bf = p.prec == EXPENC_BF16_SPLIT;
+  if (p.sh) {
+    if (bf) adj_split_sh<true>(p, b, s);
+    else adj_split_sh<false>(p, b, s);
+  } else {
+    if (bf) adj_split_nt<true>(p, b, s);
+    else adj_split_nt<false>(p, b, s);
+  }
 }
 
 int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
@@ -425,10 +697,11 @@ int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const f
   const float2 *sm = reinterpret_cast<const float2 *>(smaps);
   u32x4 *zs = reinterpret_cast<u32x4 *>(b.zs);
   if (p.prec == EXPENC_BF16_SPLIT)
-    k_build_z_split<true><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC, NGP, zs);
+    k_build_z_split<true><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
+                                             p.NC, NGP, zs);
   else
-    k_build_z_split<false><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC, NGP,
-                                              zs);
+    k_build_z_split<false><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
+                                              p.NC, NGP, zs);
   EX_LAUNCHED("build_z split");
   return EXPENC_OK;
 }

@@ -57,9 +57,12 @@ class Operator:
     phi = sum_l coef[t, l] basis[l, r] + dw0[r] time[t].
 
     basis [L][R] f64, coef [T][L] f64 (rad per basis unit), time [T] f64 (s),
-    dw0 [R] f64 (rad/s) or None, smaps [C][R] complex64; image nx x ny."""
+    dw0 [R] f64 (rad/s) or None, smaps [C][R] complex64; image nx x ny.
+    With sh_grid=(fov_x, fov_y, z0) the basis is declared to be the real
+    solid harmonics on that grid (basis may then be None); the library can
+    then evaluate the phase in polynomial form."""
 
-    def __init__(self, nx: int, ny: int, smaps, coef, time, basis, dw0=None):
+    def __init__(self, nx: int, ny: int, smaps, coef, time, basis, dw0=None, sh_grid=None, nbasis=None):
         dev = smaps.device
         self.device = dev
         self.smaps = _need(smaps, torch.complex64, "smaps", dev)
@@ -67,7 +70,14 @@ class Operator:
         self.nx, self.ny = int(nx), int(ny)
         self.ncoils = smaps.shape[0]
         self.nsamples = time.shape[0]
-        if basis is None or basis.numel() == 0:
+        self.sh_grid = sh_grid
+        if sh_grid is not None and basis is None and coef is not None and coef.numel() > 0:
+            self.basis = None
+            self.coef = _need(coef, torch.float64, "coef", dev)
+            self.nbasis = coef.shape[1] if nbasis is None else int(nbasis)
+            if coef.shape != (self.nsamples, self.nbasis):
+                raise ValueError(f"coef must be [T][L] = [{self.nsamples}][{self.nbasis}]")
+        elif basis is None or basis.numel() == 0:
             self.nbasis = 0
             self.basis = self.coef = None
         else:
@@ -86,7 +96,9 @@ class Operator:
                               None if self.coef is None else self.coef.data_ptr(),
                               self.time.data_ptr(),
                               None if self.dw0 is None else self.dw0.data_ptr(),
-                              self.smaps.data_ptr())
+                              self.smaps.data_ptr(),
+                              _b.BASIS_SH if sh_grid is not None else _b.BASIS_MAPS, 0,
+                              *(tuple(float(v) for v in sh_grid) if sh_grid is not None else (0.0, 0.0, 0.0)))
         self._ws = {}
 
     @property

@@ -22,7 +22,7 @@ class Case:
     """One problem: numpy inputs for the oracle, device tensors for the GPU."""
 
     def __init__(self, w: synth.Workload, z0: float | None = None, ncoils: int | None = None,
-                 with_dw0: bool = True, nbasis: int | None = None):
+                 with_dw0: bool = True, nbasis: int | None = None, sh: bool = False):
         import torch
         from oracle import encoding
         import paper_2211_07532_amd as ee
@@ -46,7 +46,12 @@ class Case:
         self.t_dw0 = None if self.dw0 is None else torch.from_numpy(self.dw0).to(dev)
         # the GPU evaluates its own basis from the grid geometry
         self.t_basis = ee.sh_basis(w.n, w.n, w.fov, w.fov, self.z0, nb, device=dev)
-        self.op = ee.Operator(w.n, w.n, self.t_smaps, self.t_coef, self.t_time, self.t_basis, self.t_dw0)
+        if sh and nb > 0:
+            # the basis declared as solid harmonics on the grid: the library evaluates it itself
+            self.op = ee.Operator(w.n, w.n, self.t_smaps, self.t_coef, self.t_time, None, self.t_dw0,
+                                  sh_grid=(w.fov, w.fov, self.z0))
+        else:
+            self.op = ee.Operator(w.n, w.n, self.t_smaps, self.t_coef, self.t_time, self.t_basis, self.t_dw0)
 
     def oracle_args(self):
         return (self.smaps, self.coef, self.time, self.basis_np, self.dw0)

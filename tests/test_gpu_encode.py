@@ -27,25 +27,26 @@ def test_sh_basis_matches_oracle():
         assert np.max(np.abs(b - ref)) <= 1e-15 * np.max(np.abs(ref)) + 1e-300
 
 
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 @pytest.mark.parametrize("name", ["tiny", "ragged", "onecoil-nofield", "40coils"])
-def test_forward_adjoint_whole_output(name):
+def test_forward_adjoint_whole_output(name, sh):
     import torch
     ee = _ee()
     if name == "tiny":
         w = synth.TINY
-        case = Case(w)
+        case = Case(w, sh=sh)
         batch = 2
     elif name == "ragged":
         w = synth.Workload("ragged", 13, 0.1, 5, 333, 3e-6, 2.0, 16, 120.0, 20.0, 5, "haar", 1, 21)
-        case = Case(w, z0=0.004)
+        case = Case(w, z0=0.004, sh=sh)
         batch = 3
     elif name == "onecoil-nofield":
         w = synth.Workload("c1", 24, 0.2, 1, 600, 2e-6, 2.0, 3, 0.0, 20.0, 5, "haar", 1, 22)
-        case = Case(w, with_dw0=False, nbasis=0)
+        case = Case(w, with_dw0=False, nbasis=0, sh=sh)
         batch = 1
     else:
         w = synth.Workload("c40", 20, 0.2, 40, 700, 2e-6, 2.0, 9, 80.0, 20.0, 5, "haar", 1, 23)
-        case = Case(w)
+        case = Case(w, sh=sh)
         batch = 1
     print(f"[case] {name} n={w.n} T={w.nsamples} C={case.smaps.shape[0]} L={case.coef.shape[1]} B={batch}",
           flush=True)
@@ -80,13 +81,14 @@ def test_bitwise_determinism():
     assert np.array_equal(a1.view(np.uint32), a2.view(np.uint32))
 
 
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 @pytest.mark.parametrize("wl", [synth.MM15, synth.MM11])
-def test_full_size_sampled_outputs(wl):
+def test_full_size_sampled_outputs(wl, sh):
     """Full-size operators in the benchmark's launch configuration: sampled
     samples/pixels against the oracle's one-output direct sums."""
     ee = _ee()
-    print(f"[case] full {wl.name}", flush=True)
-    case = Case(wl)
+    print(f"[case] full {wl.name} sh={sh}", flush=True)
+    case = Case(wl, sh=sh)
     x = case.x_noisy
     y = ee.forward(case.to_dev(x), case.op).cpu().numpy()
     rng = np.random.default_rng(5)

@@ -30,19 +30,24 @@ def _emulated_forward_error(case, x, kind):
     return rel(splitemu.split_cmatmul(e, z, kind), ref)
 
 
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-@pytest.mark.parametrize("name", ["tiny", "ragged"])
-def test_split_operators(prec, name):
+@pytest.mark.parametrize("name", ["tiny", "ragged", "40coils-nodw0"])
+def test_split_operators(prec, name, sh):
     ee = _ee()
     if name == "tiny":
         w = synth.TINY
-        case = Case(w)
+        case = Case(w, sh=sh)
         batch = 2
-    else:
+    elif name == "ragged":
         w = synth.Workload("ragged", 13, 0.1, 5, 333, 3e-6, 2.0, 16, 120.0, 20.0, 5, "haar", 1, 21)
-        case = Case(w, z0=0.004)
+        case = Case(w, z0=0.004, sh=sh)
         batch = 3
-    print(f"[case] split {prec} {name}", flush=True)
+    else:
+        w = synth.Workload("c40", 20, 0.2, 40, 700, 2e-6, 2.0, 9, 80.0, 20.0, 5, "haar", 1, 23)
+        case = Case(w, with_dw0=False, sh=sh)
+        batch = 1
+    print(f"[case] split {prec} {name} sh={sh}", flush=True)
     x = c64(synth.random_complex((batch, w.npix), 61))
     x[0] = case.x_noisy
     y_ref = encoding.forward(x, *case.oracle_args())
@@ -52,16 +57,17 @@ def test_split_operators(prec, name):
     x_ref = encoding.adjoint(g, *case.oracle_args())
     e_adj = rel(ee.adjoint(case.to_dev(g), case.op, precision=prec).cpu().numpy(), x_ref)
     emu = _emulated_forward_error(case, case.x_noisy, prec)
-    print(f"split {prec} {name}: forward {e_fwd:.2e} adjoint {e_adj:.2e} emulated {emu:.2e}", flush=True)
+    print(f"split {prec} {name} sh={sh}: forward {e_fwd:.2e} adjoint {e_adj:.2e} emulated {emu:.2e}", flush=True)
     assert e_fwd <= 1e-3 and e_adj <= 1e-3
     assert e_fwd <= 5 * emu + 2e-6
 
 
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-def test_split_full_size_sampled(prec):
+def test_split_full_size_sampled(prec, sh):
     ee = _ee()
     wl = synth.MM15
-    case = Case(wl)
+    case = Case(wl, sh=sh)
     x = case.x_noisy
     y = ee.forward(case.to_dev(x), case.op, precision=prec).cpu().numpy()
     rng = np.random.default_rng(6)
@@ -74,19 +80,20 @@ def test_split_full_size_sampled(prec):
     got = np.array([xa[r] for r in rs])
     ref = np.array([encoding.adjoint_one(y.astype(np.complex128), *case.oracle_args(), int(r)) for r in rs])
     e2 = rel(got, ref)
-    print(f"split {prec} full: forward {e:.2e} adjoint {e2:.2e}", flush=True)
+    print(f"split {prec} full sh={sh}: forward {e:.2e} adjoint {e2:.2e}", flush=True)
     assert e <= 1e-3 and e2 <= 1e-3
 
 
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("variant", ["tiny", "padded-db4"])
-def test_split_fista_with_anchors(prec, variant):
+def test_split_fista_with_anchors(prec, variant, sh):
     ee = _ee()
     if variant == "tiny":
         w = synth.TINY
     else:
         w = synth.Workload("pad", 20, 0.2, 6, 900, 3e-6, 2.0, 16, 80.0, 20.0, 30, "db4", 3, 51)
-    case = Case(w)
+    case = Case(w, sh=sh)
     op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
     y = c64(op.A(case.x_noisy))
     L = solve.power_lipschitz(op, c64(synth.power_start(w.npix, 4)), 30)
@@ -99,6 +106,6 @@ def test_split_fista_with_anchors(prec, variant):
     res0 = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam,
                     refine_every=10 ** 6)
     e0 = solve.nrmse(res0.x.cpu().numpy().reshape(-1), ref)
-    print(f"split FISTA {prec} {variant}: NRMSE {e:.2e} (anchored every 10), {e0:.2e} (no intermediate anchor)",
+    print(f"split FISTA {prec} {variant} sh={sh}: NRMSE {e:.2e} (anchored every 10), {e0:.2e} (no intermediate anchor)",
           flush=True)
     assert e <= 1e-4
