@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp16"])
+    ap.add_argument("--precision", default="all", choices=["all", "fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
     return ap.parse_args()
@@ -56,6 +56,10 @@ def cpu_baseline(w, prob, basis):
             "cores": int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1)), "kind": "oracle",
             "sample": f"one A_exp and one A_exp^H application of the {w.name} operator "
                       f"({2 * cmac:.3e} CMAC, {dt:.1f} s)"}
+
+
+FORMS = {"fp32": "f32", "bf16": "bf16-split", "fp16": "f16-split"}
+GOLDEN = os.path.join(ROOT, "tests", "golden", "mm15_fista.npz")
 
 
 def main():
@@ -81,76 +85,90 @@ def main():
     x_noisy = torch.from_numpy(prob.x_noisy.astype(np.complex64)).to(dev)
     y = ee.forward(x_noisy, op)                      # synthetic k-space of the noisy object
     v0 = torch.from_numpy(synth.power_start(w.npix, 7).astype(np.complex64)).to(dev)
-    prec = args.precision
-
-    def step():
-        return ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
-                        n_power=N_POWER, lam=-1.0, lambda_factor=1e-3, sync_scalars=False)
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
+    golden = np.load(GOLDEN)["x_hat"] if os.path.exists(GOLDEN) else None
     cmac = w.nsamples * w.npix * w.ncoils
     apps = 2 * w.n_iter + (2 * N_POWER + 1) + 1
-    value = apps * cmac / dt / 1e9
-
-    # FISTA loop alone (L and lambda given): iterations per second
-    sc = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
-                  n_power=N_POWER)
-    L, lam = sc.lipschitz, sc.lam[0]
-    ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    reps = max(2, args.steps)
-    for _ in range(reps):
-        ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
-    torch.cuda.synchronize()
-    it_s = w.n_iter * reps / (time.perf_counter() - t1)
-
-    # Roofline of the contraction kernels: HIP events around each eager launch
     lib = B.lib()
-    out = (ctypes.c_double * 4)()
-    B.check(lib.expenc_kernel_timing(1, out), "timing on")
-    for _ in range(args.kernel_reps):
-        yk = ee.forward(x_noisy, op, precision=prec)
-        ee.adjoint(yk, op, precision=prec)
-    torch.cuda.synchronize()
-    B.check(lib.expenc_kernel_timing(2, out), "timing read")
-    B.check(lib.expenc_kernel_timing(0, out), "timing off")
-    fwd_ms = out[0] / max(out[1], 1)
-    adj_ms = out[2] / max(out[3], 1)
-    dom_ms = max(fwd_ms, adj_ms)
-    dom = "forward" if fwd_ms >= adj_ms else "adjoint"
-    flops = 8.0 * cmac                                  # algorithmic: 4 real MAC per CMAC
-    achieved = flops / (dom_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[prec]
+    forms = [args.precision] if args.precision != "all" else list(FORMS)
+    out = {}
+    for prec in forms:
+        def step():
+            return ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
+                            n_power=N_POWER, lam=-1.0, lambda_factor=1e-3, sync_scalars=False)
 
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res = step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        nrmse = None
+        if golden is not None:
+            xr = res.x.cpu().numpy().reshape(-1).astype(np.complex128)
+            nrmse = float(np.linalg.norm(xr - golden.reshape(-1)) / np.linalg.norm(golden))
+        # FISTA loop alone (L and lambda given): iterations per second
+        sc = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
+                      n_power=N_POWER)
+        L, lam = sc.lipschitz, sc.lam[0]
+        ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = max(2, args.steps)
+        for _ in range(reps):
+            ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+        torch.cuda.synchronize()
+        it_s = w.n_iter * reps / (time.perf_counter() - t1)
+        # contraction kernels: HIP events around each eager launch on its stream
+        ev = (ctypes.c_double * 4)()
+        B.check(lib.expenc_kernel_timing(1, ev), "timing on")
+        for _ in range(args.kernel_reps):
+            yk = ee.forward(x_noisy, op, precision=prec)
+            ee.adjoint(yk, op, precision=prec)
+        torch.cuda.synchronize()
+        B.check(lib.expenc_kernel_timing(2, ev), "timing read")
+        B.check(lib.expenc_kernel_timing(0, ev), "timing off")
+        fwd_ms = ev[0] / max(ev[1], 1)
+        adj_ms = ev[2] / max(ev[3], 1)
+        dom_ms = max(fwd_ms, adj_ms)
+        achieved = 8.0 * cmac / (dom_ms * 1e-3) / 1e12     # algorithmic: 4 real MAC per CMAC
+        out[prec] = {
+            "gcmac_per_s": round(apps * cmac / dt / 1e9, 2), "ms_per_step": round(dt * 1e3, 3),
+            "fista_iter_per_s": round(it_s, 2), "nrmse_vs_fp64": None if nrmse is None else float(f"{nrmse:.3e}"),
+            "kernel_ms": {"forward_contraction": round(fwd_ms, 4), "adjoint_contraction": round(adj_ms, 4)},
+            "roofline": {"bound": "mfma", "kernel": ("forward" if fwd_ms >= adj_ms else "adjoint") + " contraction",
+                         "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+                         "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": None},
+        }
+
+    # headline: the fastest form whose solve meets NRMSE <= 1e-4 against the FP64 oracle
+    ok = [p for p in forms if out[p]["nrmse_vs_fp64"] is None or out[p]["nrmse_vs_fp64"] <= 1e-4]
+    head = max(ok or forms, key=lambda p: out[p]["gcmac_per_s"])
+    h = out[head]
     line = {
         "metric": "A_exp+A_exp^H GCMAC/s & CS-FISTA iter/s, BF16-split vs FP32 at <=1e-4 NRMSE",
-        "value": round(value, 2),
+        "value": h["gcmac_per_s"],
         "unit": "GCMAC/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt * 1e3, 3),
+        "ms_per_step": h["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16": "bf16-split", "fp16": "f16-split"}[prec],
+        "dtype": FORMS[head],
         "data": "synthetic",
         "config": {"workload": w.name, "image": f"{w.n}x{w.n}", "coils": w.ncoils, "samples": w.nsamples,
                    "field_terms": w.nbasis, "fista_iters": w.n_iter, "wavelet": f"{w.wavelet} J={w.levels}",
                    "power_iters": N_POWER, "operator_applications_per_step": apps},
-        "fista_iter_per_s": round(it_s, 2),
-        "kernel_ms": {"forward_contraction": round(fwd_ms, 4), "adjoint_contraction": round(adj_ms, 4)},
-        "roofline": {"bound": "mfma", "kernel": f"{dom} contraction", "achieved": round(achieved, 2),
-                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None},
+        "fista_iter_per_s": h["fista_iter_per_s"],
+        "nrmse_vs_fp64": h["nrmse_vs_fp64"],
+        "roofline": h["roofline"],
+        "forms": out,
     }
+    if "fp32" in out and head != "fp32":
+        line["split_vs_fp32_fista_iter_ratio"] = round(h["fista_iter_per_s"] / out["fp32"]["fista_iter_per_s"], 3)
     if not args.no_cpu_baseline:
         from oracle import encoding
         line["cpu_baseline"] = cpu_baseline(w, prob, encoding.sh_basis(w.n, w.fov, w.z0, w.nbasis))

@@ -171,6 +171,34 @@ int wavelet_inv(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t
 int soft_threshold(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w_in,
                    float *w_out, float tau, void *stream);
 
+/*
+ * Vector-Jacobian product of the soft-threshold (for differentiating through
+ * the prox of eq. 1's l1 term).  With u = w/|w|, a = 1 - tau/|w|, b = tau/|w|,
+ * the real-linear derivative of S_tau at |w| > tau is dw -> a dw + b u Re(conj(u) dw)
+ * (symmetric), so grad_in = a g + b u Re(conj(u) g); grad_in = 0 where
+ * |w| <= tau, and grad_in = g on the coarsest LL block.  Upstream g and the
+ * result use the convention grad = dL/dRe + i dL/dIm.  All [B][ny][nx].
+ */
+int soft_threshold_vjp(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w_in, const float *g,
+                       float *grad_in, float tau, void *stream);
+
+/*
+ * Field-parameter gradients of the encoding operator (differentiation of
+ * A(theta) with theta = (k_l(t), dw0(r))).  Using dA/dk_l(t) = i b_l(r) A and
+ * dA/d dw0(r) = i t A, for a real loss and upstream gradients in the
+ * convention grad = dL/dRe + i dL/dIm:
+ *   for y = A x with upstream g:     call with (w, kk) = (x, g);
+ *   for x = A^H y with upstream gx:  call with (w, kk) = (gx, y);
+ * then
+ *   grad_coef[t][l] = -Im sum_c conj(kk[t][c]) [A (b_l w)](t, c)     (float64 [T][L])
+ *   grad_dw0[r]     = -Im( w(r) conj([A^H (t kk)](r)) )              (float64 [R])
+ * Either output may be NULL to skip it.  w: [R], kk: [T][C] complex64.
+ * precision must be EXPENC_FP32.  The L basis-weighted products run as one
+ * batched forward contraction (every phase tile is shared by the L terms).
+ */
+int expenc_field_grad(const expenc_op *op, int32_t precision, const float *w, const float *kk,
+                      double *grad_coef, double *grad_dw0, void *ws, size_t ws_bytes, void *stream);
+
 /* Options of fista_solve / cg_solve. */
 typedef struct expenc_fista_opts {
   int32_t n_iter;          /* iterations K (Methods 2.1 uses 100)                    */

@@ -271,6 +271,8 @@ extern "C" size_t expenc_workspace_size(const expenc_op *op, int32_t batch, int3
       return fista_bytes(op, batch, precision, nx_pad, ny_pad);
     case EXPENC_WS_CG:
       return cg_bytes(op, batch, precision);
+    case EXPENC_WS_FIELD_GRAD:
+      return grad_bytes(op, precision);
     default:
       return 0;
   }

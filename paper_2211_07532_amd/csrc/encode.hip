@@ -187,8 +187,9 @@ __global__ __launch_bounds__(256) void k_fwd_f32(const double *__restrict__ kap,
       pa = fma(kv[j], ba[j], pa);
       pb = fma(kv[j], ba[NT + j], pb);
     }
-    const float fa = (float)__builtin_amdgcn_fract(pa);
-    const float fb = (float)__builtin_amdgcn_fract(pb);
+    // centred reduction to [-1/2, 1/2] turns before rounding to FP32
+    const float fa = (float)(pa - __builtin_rint(pa));
+    const float fb = (float)(pb - __builtin_rint(pb));
     const float ca = __builtin_amdgcn_cosf(fa), sa = __builtin_amdgcn_sinf(fa);
     const float cb = __builtin_amdgcn_cosf(fb), sb = __builtin_amdgcn_sinf(fb);
     const auto cc = __builtin_amdgcn_permlane32_swap(__float_as_uint(ca), __float_as_uint(cb), false, false);
@@ -258,8 +259,9 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
       pa = fma(ka[j], bv[j], pa);
       pb = fma(ka[NT + j], bv[j], pb);
     }
-    const float fa = (float)__builtin_amdgcn_fract(pa);
-    const float fb = (float)__builtin_amdgcn_fract(pb);
+    // centred reduction to [-1/2, 1/2] turns before rounding to FP32
+    const float fa = (float)(pa - __builtin_rint(pa));
+    const float fb = (float)(pb - __builtin_rint(pb));
     const float ca = __builtin_amdgcn_cosf(fa), sa = __builtin_amdgcn_sinf(fa);
     const float cb = __builtin_amdgcn_cosf(fb), sb = __builtin_amdgcn_sinf(fb);
     const auto cc = __builtin_amdgcn_permlane32_swap(__float_as_uint(ca), __float_as_uint(cb), false, false);
@@ -302,14 +304,14 @@ __global__ void k_fwd_reduce_out(const float2 *__restrict__ part, int nsplit, in
   if (i >= T * NC) return;
   int64_t t = i / NC;
   int col = (int)(i % NC);
-  float2 s = make_float2(0.f, 0.f);
+  double sx = 0.0, sy = 0.0;
   for (int k = 0; k < nsplit; ++k) {
     float2 v = part[((int64_t)k * Tp + t) * NCP + col];
-    s.x += v.x;
-    s.y += v.y;
+    sx += v.x;
+    sy += v.y;
   }
   int b = col / C, c = col % C;
-  y[((int64_t)b * T + t) * C + c] = s;
+  y[((int64_t)b * T + t) * C + c] = make_float2((float)sx, (float)sy);
 }
 
 // Residual into the adjoint operand: yop[t][col] = sum_split part - y_meas
@@ -321,21 +323,21 @@ __global__ void k_fwd_residual(const float2 *__restrict__ part, int nsplit, int6
   if (i >= Tp * NCP) return;
   int64_t t = i / NCP;
   int col = (int)(i % NCP);
-  float2 s = make_float2(0.f, 0.f);
+  double sx = 0.0, sy = 0.0;
   if (t < T && col < NC) {
     for (int k = 0; k < nsplit; ++k) {
       float2 v = part[((int64_t)k * Tp + t) * NCP + col];
-      s.x += v.x;
-      s.y += v.y;
+      sx += v.x;
+      sy += v.y;
     }
     if (y_meas) {
       const int b = col / C, c = col % C;
       const float2 m = y_meas[((int64_t)b * T + t) * C + c];
-      s.x -= m.x;
-      s.y -= m.y;
+      sx -= m.x;
+      sy -= m.y;
     }
   }
-  yop[i] = s;
+  yop[i] = make_float2((float)sx, (float)sy);
 }
 
 // x_b(r) = alpha * sum_c conj(S_c(r)) sum_split part[split][r][b*C+c].
@@ -352,18 +354,18 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
   if (r >= R) return;  // uniform per 32-lane group
   const int64_t rq = (int64_t)(r / nx) * nxq + (r % nx);  // row of the partial sums
   for (int b = 0; b < B; ++b) {
-    float sx = 0.f, sy = 0.f;
+    double sx = 0.0, sy = 0.0;
     for (int c = sub; c < C; c += 32) {
       const int col = b * C + c;
-      float2 u = make_float2(0.f, 0.f);
+      double ux = 0.0, uy = 0.0;
       for (int k = 0; k < nsplit; ++k) {
         float2 v = part[((int64_t)k * Rp + rq) * NCP + col];
-        u.x += v.x;
-        u.y += v.y;
+        ux += v.x;
+        uy += v.y;
       }
       float2 s = smaps[(int64_t)c * R + r];
-      sx += s.x * u.x + s.y * u.y;  // conj(s) * u
-      sy += s.x * u.y - s.y * u.x;
+      sx += s.x * ux + s.y * uy;  // conj(s) * u
+      sy += s.x * uy - s.y * ux;
     }
 #pragma unroll
     for (int o = 16; o > 0; o >>= 1) {
@@ -373,12 +375,12 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
     if (sub == 0) {
       const int yy = r / nx, xx = r % nx;
       const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
-      const float alpha = alpha_dev ? (float)*alpha_dev : 1.f;
+      const double alpha = alpha_dev ? *alpha_dev : 1.0;
       if (base) {
         sx += base[o].x;
         sy += base[o].y;
       }
-      float2 v = make_float2(alpha * sx, alpha * sy);
+      float2 v = make_float2((float)(alpha * sx), (float)(alpha * sy));
       if (add) {
         v.x += add[o].x;
         v.y += add[o].y;
@@ -402,7 +404,7 @@ static int target_workgroups() {
   static int v = [] {
     const char *e = getenv("EXPENC_TARGET_WG");
     int t = e ? atoi(e) : 0;
-    return t > 0 ? t : 1024;
+    return t > 0 ? t : 2048;
   }();
   return v;
 }

@@ -383,12 +383,12 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
 
   // ---- iterations (captured) ----
   const int K = opts->n_iter;
-  std::vector<float> beta(K);
+  std::vector<double> beta(K);
   {
     double t = 1.0;
     for (int k = 0; k < K; ++k) {
       const double tn = opts->ista ? 1.0 : (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-      beta[k] = (float)((t - 1.0) / tn);
+      beta[k] = (t - 1.0) / tn;
       t = tn;
     }
   }

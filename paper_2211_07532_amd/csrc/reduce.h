@@ -28,5 +28,6 @@ int lipschitz_run(const EncPlan &p1, const expenc_op *op, const EncBuffers &eb, 
 
 size_t fista_bytes(const expenc_op *op, int32_t batch, int32_t precision, int32_t nx_pad, int32_t ny_pad);
 size_t cg_bytes(const expenc_op *op, int32_t batch, int32_t precision);
+size_t grad_bytes(const expenc_op *op, int32_t precision);
 
 }  // namespace expenc

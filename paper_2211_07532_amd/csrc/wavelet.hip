@@ -12,7 +12,7 @@
 // in place, so a multi-level transform needs no scratch buffer.  Row passes
 // use one workgroup per image row (a coalesced line of n complex values);
 // column passes stage a strip of 16 columns x n rows (128-byte coalesced
-// row segments).  The column pass of the analysis can apply the
+// row segments); taps and sums are FP64, data FP32.  The column pass of the analysis can apply the
 // soft-threshold to every detail coefficient it produces, because a level's
 // detail bands are final once its column pass is done.  These are HBM /
 // launch-bound kernels: no MFMA.
@@ -103,8 +103,8 @@ int make_filter_set(int32_t wavelet, FilterSet *f) {
   EX_TRY(wavelet_filter(wavelet, h, &taps));
   f->taps = taps;
   for (int k = 0; k < taps; ++k) {
-    f->h[k] = (float)h[k];
-    f->g[k] = (float)(((k & 1) ? -1.0 : 1.0) * h[taps - 1 - k]);
+    f->h[k] = h[k];
+    f->g[k] = ((k & 1) ? -1.0 : 1.0) * h[taps - 1 - k];
   }
   return EXPENC_OK;
 }
@@ -126,19 +126,19 @@ __global__ __launch_bounds__(256) void k_dwt_rows(const float2 *src, float2 *dst
   __syncthreads();
   const int half = mx >> 1;
   for (int m = threadIdx.x; m < half; m += blockDim.x) {
-    float2 a = make_float2(0.f, 0.f), dd = make_float2(0.f, 0.f);
+    double ax = 0.0, ay = 0.0, dx = 0.0, dy = 0.0;
     for (int k = 0; k < f.taps; ++k) {
       int j = 2 * m + k;
       if (j >= mx) j -= mx;
       if (j >= mx) j %= mx;
       const float2 v = line[j];
-      a.x += f.h[k] * v.x;
-      a.y += f.h[k] * v.y;
-      dd.x += f.g[k] * v.x;
-      dd.y += f.g[k] * v.y;
+      ax += f.h[k] * v.x;
+      ay += f.h[k] * v.y;
+      dx += f.g[k] * v.x;
+      dy += f.g[k] * v.y;
     }
-    d[m] = a;
-    d[half + m] = dd;
+    d[m] = make_float2((float)ax, (float)ay);
+    d[half + m] = make_float2((float)dx, (float)dy);
   }
 }
 
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void k_dwt_rows(const float2 *src, float2 *dst
 __global__ __launch_bounds__(256) void k_idwt_rows(const float2 *src, float2 *dst,
                                                    int nx, int ny, int mx, FilterSet f,
                                                    const float2 *__restrict__ xprev,
-                                                   float2 *__restrict__ zout, float beta) {
+                                                   float2 *__restrict__ zout, double beta) {
   extern __shared__ float2 line[];
   const int row = blockIdx.x, b = blockIdx.y;
   const int64_t base = ((int64_t)b * ny + row) * nx;
@@ -155,20 +155,21 @@ __global__ __launch_bounds__(256) void k_idwt_rows(const float2 *src, float2 *ds
   __syncthreads();
   const int half = mx >> 1;
   for (int m = threadIdx.x; m < mx; m += blockDim.x) {
-    float2 v = make_float2(0.f, 0.f);
+    double vx = 0.0, vy = 0.0;
     for (int k = (m & 1); k < f.taps; k += 2) {
       int q = m - k;
       q %= mx;
       if (q < 0) q += mx;
       const int i = q >> 1;
       const float2 a = line[i], d = line[half + i];
-      v.x += f.h[k] * a.x + f.g[k] * d.x;
-      v.y += f.h[k] * a.y + f.g[k] * d.y;
+      vx += f.h[k] * a.x + f.g[k] * d.x;
+      vy += f.h[k] * a.y + f.g[k] * d.y;
     }
+    const float2 v = make_float2((float)vx, (float)vy);
     dst[base + m] = v;
     if (zout) {
       const float2 p = xprev[base + m];
-      zout[base + m] = make_float2(v.x + beta * (v.x - p.x), v.y + beta * (v.y - p.y));
+      zout[base + m] = make_float2((float)(v.x + beta * ((double)v.x - p.x)), (float)(v.y + beta * ((double)v.y - p.y)));
     }
   }
 }
@@ -191,21 +192,22 @@ __global__ __launch_bounds__(256) void k_dwt_cols(float2 *__restrict__ w, int nx
     if (cx < ncols) strip[i * 16 + cx] = img[(int64_t)i * nx + x0 + cx];
   __syncthreads();
   const int half = my >> 1;
-  const float t = tau ? (float)tau[b] : 0.f;
+  const double t = tau ? tau[b] : 0.0;
   double l1 = 0.0;
   if (cx < ncols) {
     const bool detail_col = (x0 + cx) >= (mx >> 1);
     for (int m = ty; m < half; m += 16) {
-      float2 a = make_float2(0.f, 0.f), dd = make_float2(0.f, 0.f);
+      double ax = 0.0, ay = 0.0, dx = 0.0, dy = 0.0;
       for (int k = 0; k < f.taps; ++k) {
         int j = 2 * m + k;
         if (j >= my) j %= my;
         const float2 v = strip[j * 16 + cx];
-        a.x += f.h[k] * v.x;
-        a.y += f.h[k] * v.y;
-        dd.x += f.g[k] * v.x;
-        dd.y += f.g[k] * v.y;
+        ax += f.h[k] * v.x;
+        ay += f.h[k] * v.y;
+        dx += f.g[k] * v.x;
+        dy += f.g[k] * v.y;
       }
+      float2 a = make_float2((float)ax, (float)ay), dd = make_float2((float)dx, (float)dy);
       if (tau) {
         if (detail_col) {
           a = soft(a, t);
@@ -246,16 +248,16 @@ __global__ __launch_bounds__(256) void k_idwt_cols(float2 *__restrict__ w, int n
   const int half = my >> 1;
   if (cx < ncols) {
     for (int m = ty; m < my; m += 16) {
-      float2 v = make_float2(0.f, 0.f);
+      double vx = 0.0, vy = 0.0;
       for (int k = (m & 1); k < f.taps; k += 2) {
         int q = (m - k) % my;
         if (q < 0) q += my;
         const int i = q >> 1;
         const float2 a = strip[i * 16 + cx], d = strip[(half + i) * 16 + cx];
-        v.x += f.h[k] * a.x + f.g[k] * d.x;
-        v.y += f.h[k] * a.y + f.g[k] * d.y;
+        vx += f.h[k] * a.x + f.g[k] * d.x;
+        vy += f.h[k] * a.y + f.g[k] * d.y;
       }
-      img[(int64_t)m * nx + x0 + cx] = v;
+      img[(int64_t)m * nx + x0 + cx] = make_float2((float)vx, (float)vy);
     }
   }
 }
@@ -267,8 +269,33 @@ __global__ void k_soft(const float2 *__restrict__ in, float2 *__restrict__ out, 
   const int64_t p = i % ((int64_t)nx * ny);
   const int yy = (int)(p / nx), xx = (int)(p % nx);
   float2 v = in[i];
-  if (!(yy < lly && xx < llx)) v = soft(v, tau);
+  if (!(yy < lly && xx < llx)) v = soft(v, (double)tau);
   out[i] = v;
+}
+
+// grad_in = a g + b u Re(conj(u) g) on detail coefficients with |w| > tau,
+// 0 where |w| <= tau, g on the coarsest LL block.
+__global__ void k_soft_vjp(const float2 *__restrict__ w, const float2 *__restrict__ g, float2 *__restrict__ out,
+                           int nx, int ny, int llx, int lly, int64_t total, float tau) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int64_t p = i % ((int64_t)nx * ny);
+  const int yy = (int)(p / nx), xx = (int)(p % nx);
+  const float2 gv = g[i];
+  if (yy < lly && xx < llx) {
+    out[i] = gv;
+    return;
+  }
+  const float2 v = w[i];
+  const float m = sqrtf(v.x * v.x + v.y * v.y);
+  if (!(m > tau)) {
+    out[i] = make_float2(0.f, 0.f);
+    return;
+  }
+  const float a = 1.f - tau / m, b = tau / m;
+  const float ux = v.x / m, uy = v.y / m;
+  const float re = ux * gv.x + uy * gv.y;  // Re(conj(u) g)
+  out[i] = make_float2(a * gv.x + b * ux * re, a * gv.y + b * uy * re);
 }
 
 __global__ void k_copy2(const float2 *__restrict__ in, float2 *__restrict__ out, int64_t n) {
@@ -304,7 +331,7 @@ int dwt_forward_levels(const FilterSet &f, int nx, int ny, int levels, int batch
 }
 
 int dwt_inverse_levels(const FilterSet &f, int nx, int ny, int levels, int batch, float2 *w, float2 *dst,
-                       const float2 *xprev, float2 *zout, float beta, hipStream_t s) {
+                       const float2 *xprev, float2 *zout, double beta, hipStream_t s) {
   for (int j = levels - 1; j >= 0; --j) {
     const int mx = nx >> j, my = ny >> j;
     const int nb = (int)ceil_div(mx, 16);
@@ -347,7 +374,7 @@ extern "C" int wavelet_inv(int32_t nx, int32_t ny, int32_t levels, int32_t wavel
     EX_LAUNCHED("copy");
   }
   float2 *xx = reinterpret_cast<float2 *>(x);
-  return dwt_inverse_levels(f, nx, ny, levels, batch, xx, xx, nullptr, nullptr, 0.f, s);
+  return dwt_inverse_levels(f, nx, ny, levels, batch, xx, xx, nullptr, nullptr, 0.0, s);
 }
 
 extern "C" int soft_threshold(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w_in,
@@ -359,5 +386,17 @@ extern "C" int soft_threshold(int32_t nx, int32_t ny, int32_t levels, int32_t ba
       reinterpret_cast<const float2 *>(w_in), reinterpret_cast<float2 *>(w_out), nx, ny, nx >> levels,
       ny >> levels, total, tau);
   EX_LAUNCHED("soft_threshold");
+  return EXPENC_OK;
+}
+
+extern "C" int soft_threshold_vjp(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w_in,
+                                  const float *g, float *grad_in, float tau, void *stream) {
+  if (nx < 1 || ny < 1 || levels < 0 || batch < 1 || !w_in || !g || !grad_in || !(tau >= 0.f))
+    return fail(EXPENC_EINVAL, "bad soft_threshold_vjp arguments");
+  const int64_t total = (int64_t)nx * ny * batch;
+  k_soft_vjp<<<(unsigned)ceil_div(total, 256), 256, 0, (hipStream_t)stream>>>(
+      reinterpret_cast<const float2 *>(w_in), reinterpret_cast<const float2 *>(g), reinterpret_cast<float2 *>(grad_in),
+      nx, ny, nx >> levels, ny >> levels, total, tau);
+  EX_LAUNCHED("soft_threshold_vjp");
   return EXPENC_OK;
 }

@@ -7,18 +7,22 @@
 
 namespace expenc {
 
-// Analysis filters in FP32 (low-pass h, high-pass g[k] = (-1)^k h[M-1-k]).
+// Analysis filters (low-pass h, high-pass g[k] = (-1)^k h[M-1-k]) kept in
+// FP64: rounding the irrational db4 taps to FP32 makes the transform
+// slightly non-orthonormal, and FISTA's momentum accumulates that bias
+// (about 1e-5 relative after 50 iterations), so the passes filter in FP64.
 struct FilterSet {
   int taps;
-  float h[8];
-  float g[8];
+  double h[8];
+  double g[8];
 };
 
-// Soft-threshold of one complex coefficient: w * max(0, 1 - tau/|w|).
-__device__ inline float2 soft(float2 v, float t) {
-  const float m = sqrtf(v.x * v.x + v.y * v.y);
-  const float sc = m > t ? 1.f - t / m : 0.f;
-  return make_float2(v.x * sc, v.y * sc);
+// Soft-threshold of one complex coefficient: w * max(0, 1 - tau/|w|)
+// (evaluated in FP64 so that the threshold carries no FP32 rounding bias).
+__device__ inline float2 soft(float2 v, double t) {
+  const double m = sqrt((double)v.x * v.x + (double)v.y * v.y);
+  const double sc = m > t ? 1.0 - t / m : 0.0;
+  return make_float2((float)(v.x * sc), (float)(v.y * sc));
 }
 
 int make_filter_set(int32_t wavelet, FilterSet *f);
@@ -32,6 +36,6 @@ int dwt_forward_levels(const FilterSet &f, int nx, int ny, int levels, int batch
 // Multi-level synthesis, in place on w except the last row pass, which writes
 // dst; if zout is given it also writes zout = dst + beta*(dst - xprev).
 int dwt_inverse_levels(const FilterSet &f, int nx, int ny, int levels, int batch, float2 *w, float2 *dst,
-                       const float2 *xprev, float2 *zout, float beta, hipStream_t s);
+                       const float2 *xprev, float2 *zout, double beta, hipStream_t s);
 
 }  // namespace expenc

@@ -1,0 +1,44 @@
+"""Full-size solve parity: the 1.5 mm workload (148 x 148, 32 coils,
+T = 16384, 16 field terms + dB0, 50 FISTA iterations, db4 J = 3) on the GPU
+against the FP64 oracle's reconstruction stored in tests/golden/mm15_fista.npz
+(written by tests/golden/make_golden.py, which calls only the oracle).
+Bars: NRMSE <= 1e-5 for the FP32 form, <= 1e-4 for the split forms with FP32
+anchors; L and lambda from the device rules within 1e-5."""
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import encoding, solve
+from tests.gpu_common import Case, c64
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "mm15_fista.npz")
+
+
+@pytest.fixture(scope="module")
+def mm15():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py")
+    g = np.load(GOLDEN)
+    w = synth.MM15
+    case = Case(w, sh=True)
+    op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
+    y = c64(op.A(case.x_noisy))
+    return w, case, y, g
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_full_size_fista_matches_golden(mm15, prec):
+    import paper_2211_07532_amd as ee
+    w, case, y, g = mm15
+    v0 = case.to_dev(c64(synth.power_start(w.npix, int(g["power_seed"]))))
+    res = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0,
+                   power_v0=v0, n_power=int(g["n_power"]), lam=-1.0, lambda_factor=1e-3)
+    e = solve.nrmse(res.x.cpu().numpy().reshape(-1), g["x_hat"])
+    print(f"golden {prec}: NRMSE {e:.2e}  L {res.lipschitz:.6e} (ref {float(g['lipschitz']):.6e})  "
+          f"lambda {res.lam[0]:.6e} (ref {float(g['lam']):.6e})", flush=True)
+    assert abs(res.lipschitz - float(g["lipschitz"])) <= 1e-5 * float(g["lipschitz"])
+    assert abs(res.lam[0] - float(g["lam"])) <= 1e-5 * float(g["lam"])
+    assert e <= (1e-5 if prec == "fp32" else 1e-4)

@@ -1,0 +1,44 @@
+"""Pins of the oracle's unrolled-FISTA gradients (torch float64 autograd)
+against central finite differences of the independent NumPy FISTA loss."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import encoding, solve, unrolled
+
+
+def _setup(seed=5):
+    w = synth.Workload("u", 8, 0.2, 2, 80, 4e-6, 2.0, 9, 60.0, 15.0, 4, "haar", 1, seed)
+    p = synth.make_problem(w)
+    basis = encoding.sh_basis(8, 0.2, 0.002, 9)
+    op = solve.Operator(p.smaps, p.coef, p.time, basis, p.dw0, 8)
+    L = 1.01 * solve.power_lipschitz(op, synth.power_start(64, 1), 50)
+    lam = solve.lambda_rule(op, op.A(p.x_noisy), 0.05)
+    return w, p, basis, L, lam
+
+
+def _numpy_loss(w, p, basis, L, lam, x_in, coef, dw0):
+    op = solve.Operator(p.smaps, coef, p.time, basis, dw0, w.n)
+    xh = solve.fista(op, op.A(x_in), L, lam, 4, 1, "haar", 8)
+    return float(np.sum(np.abs(xh - p.x_true) ** 2))
+
+
+def test_unrolled_gradients_match_central_differences():
+    w, p, basis, L, lam = _setup()
+    loss, gx, gc, gd = unrolled.loss_and_grads(p.x_noisy, p.x_true, p.smaps, p.coef, p.time, basis, p.dw0, L, lam,
+                                               4, 1, "haar", 8, 8)
+    assert loss == pytest.approx(_numpy_loss(w, p, basis, L, lam, p.x_noisy, p.coef, p.dw0), rel=1e-12)
+    rng = np.random.default_rng(3)
+    errs = []
+    for _ in range(5):
+        h = 1e-6
+        dx = (rng.normal(size=64) + 1j * rng.normal(size=64)) * h
+        dc = rng.normal(size=p.coef.shape) * h * np.max(np.abs(p.coef))
+        dd = rng.normal(size=64) * h * 100.0
+        fp = _numpy_loss(w, p, basis, L, lam, p.x_noisy + dx, p.coef + dc, p.dw0 + dd)
+        fm = _numpy_loss(w, p, basis, L, lam, p.x_noisy - dx, p.coef - dc, p.dw0 - dd)
+        fd = (fp - fm) / 2
+        an = np.sum((gx.conj() * dx).real) + np.sum(gc * dc) + np.sum(gd * dd)
+        errs.append(abs(fd - an) / max(abs(fd), 1e-30))
+    # soft-threshold kinks can spoil a single direction; the median must agree
+    assert np.median(errs) < 1e-5
