@@ -237,6 +237,28 @@ int fista_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
                 const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Many independent reconstructions in one call (the batch of slices and
+ * diffusion directions of Methods 2.1 and Fig. 5, each solved as by
+ * fista_solve).  ops[i], y[i] ([B][T][C] device) and x[i] ([B][ny][nx]
+ * device, overwritten) describe problem i; B = batch for every problem.
+ * Problems may differ in grid, samples, fields, coil maps and slice
+ * position z0; those with equal (nx, ny, ncoils, nbasis, nsamples,
+ * basis_kind, fov, presence of dw0) are solved together, one launch per pass
+ * for the whole group, and all groups' iteration loops run inside one
+ * captured HIP graph.  Every problem uses opts (K, precision, wavelet,
+ * levels, lambda rule); each gets its own L, lambda and tau.  The wavelet
+ * grid is each problem's rounded up to 2^levels (nx_pad, ny_pad must be 0);
+ * objective and scalars must be NULL.  With lipschitz <= 0, power_v0 holds
+ * at least max_i R_i complex values and problem i starts from its first
+ * R_i.  The inputs are copied into the workspace at the start of the call.
+ */
+size_t fista_batched_workspace_size(int32_t nprob, const expenc_op *ops, int32_t batch,
+                                    const expenc_fista_opts *opts);
+int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t batch, const float *const *y,
+                        float *const *x, const expenc_fista_opts *opts, void *ws, size_t ws_bytes,
+                        void *stream);
+
+/*
  * Least-squares reconstruction by conjugate gradients on A^H A x = A^H y
  * from x = 0, stopped after n_iter iterations (Methods 2.1: early stopping
  * at 20 iterations as implicit regularisation).  Uses opts->n_iter and

@@ -71,6 +71,11 @@ SIGNATURES = {
     "expenc_field_grad": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _vp, _vp, _vp, _vp, _vp,
                                          ctypes.c_size_t, _vp]),
     "soft_threshold_vjp": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, ctypes.c_float, _vp]),
+    "fista_batched_workspace_size": (ctypes.c_size_t, [_c_int, ctypes.POINTER(ExpencOp), _c_int,
+                                                       ctypes.POINTER(FistaOpts)]),
+    "fista_solve_batched": (ctypes.c_int, [_c_int, ctypes.POINTER(ExpencOp), _c_int, ctypes.POINTER(_vp),
+                                           ctypes.POINTER(_vp), ctypes.POINTER(FistaOpts), _vp, ctypes.c_size_t,
+                                           _vp]),
     "expenc_kernel_timing": (ctypes.c_int, [_c_int, ctypes.POINTER(ctypes.c_double)]),
     "expenc_last_error": (ctypes.c_char_p, []),
 }

@@ -173,9 +173,10 @@ __global__ void k_copy_f2(const float2 *__restrict__ in, float2 *__restrict__ ou
   if (i < n) out[i] = in[i];
 }
 
-// L = 2 * num/den ;  out[0] = L
-__global__ void k_lipschitz_final(const double *__restrict__ num, const double *__restrict__ den, double *out) {
-  if (threadIdx.x == 0) out[0] = den[0] > 0.0 ? 2.0 * num[0] / den[0] : 0.0;
+// L[p] = 2 * num[p]/den[p] for each problem
+__global__ void k_lipschitz_final(const double *__restrict__ num, const double *__restrict__ den, double *out, int P) {
+  const int p = threadIdx.x;
+  if (p < P) out[p] = den[p] > 0.0 ? 2.0 * num[p] / den[p] : 0.0;
 }
 
 int scale_rsqrt(float2 *v, int64_t n, int64_t stride, int B, const double *nrm2, hipStream_t s) {
@@ -190,47 +191,49 @@ int copy_f2(const float2 *in, float2 *out, int64_t n, hipStream_t s) {
   return EXPENC_OK;
 }
 
-// A^H A v for the batch-1 plan: u = A^H (A v).  v, u: [R] (row stride nx).
+// u = A^H A v for the batch-1 plan of each of p.P problems: v, u [P][R] (row stride nx).
 int normal_apply(const EncPlan &p, const expenc_op *op, const EncBuffers &eb, const float2 *v, float2 *u,
                  hipStream_t s) {
-  EX_TRY(enc_build_z(p, op->smaps, v, p.R, p.nx, eb, s));
+  EX_TRY(enc_build_z(p, op->smaps, v, p.R, p.nx, eb, s, nullptr, p.R));
   EX_TRY(enc_forward_partials(p, eb, s));
   EX_TRY(enc_forward_residual(p, eb, nullptr, s));
   EX_TRY(enc_adjoint_partials(p, eb, s));
-  return enc_adjoint_reduce_out(p, eb, op->smaps, u, p.R, p.nx, nullptr, nullptr, s);
+  return enc_adjoint_reduce_out(p, eb, op->smaps, u, p.R, p.nx, nullptr, nullptr, s, nullptr, p.R);
 }
 
 size_t lipschitz_bytes(const EncPlan &p1) {
   Arena a;
   EncBuffers eb;
   carve_enc(p1, a, &eb);
-  a.take<float2>((size_t)p1.R);
-  a.take<float2>((size_t)p1.R);
-  a.take<double>(kRedBlocks + 8);
+  a.take<float2>((size_t)p1.R * p1.P);
+  a.take<float2>((size_t)p1.R * p1.P);
+  a.take<double>((size_t)kRedBlocks * p1.P + 8 * p1.P);
   return a.used + 256;
 }
 
-// Power iteration on the batch-1 plan with kap/bet already prepared in eb.
-// Scratch: vec [R], tmp [R], dpart [kRedBlocks], dsc [4].
+// Power iteration for each of p1.P problems (batch-1 plan, kap/bet prepared
+// in eb), all from the same start vector v0 [R].  Scratch: vec, tmp [P][R],
+// dpart [P * kRedBlocks], dsc [3P].  Writes L[p] to L_out[p].
 int lipschitz_run(const EncPlan &p1, const expenc_op *op, const EncBuffers &eb, int n_iter, const float *v0,
                   float2 *vec, float2 *tmp, double *dpart, double *dsc, double *L_out, hipStream_t s) {
   const int64_t R = p1.R;
-  EX_TRY(copy_f2(reinterpret_cast<const float2 *>(v0), vec, R, s));
-  EX_TRY(reduce_dot(vec, vec, R, R, 1, 1.0, dpart, dsc, s));
-  EX_TRY(scale_rsqrt(vec, R, R, 1, dsc, s));
+  const int P = p1.P;
+  for (int q = 0; q < P; ++q) EX_TRY(copy_f2(reinterpret_cast<const float2 *>(v0), vec + q * R, R, s));
+  EX_TRY(reduce_dot(vec, vec, R, R, P, 1.0, dpart, dsc, s));
+  EX_TRY(scale_rsqrt(vec, R, R, P, dsc, s));
   for (int it = 0; it < n_iter; ++it) {
     EX_TRY(normal_apply(p1, op, eb, vec, tmp, s));
-    EX_TRY(reduce_dot(tmp, tmp, R, R, 1, 1.0, dpart, dsc, s));
-    EX_TRY(scale_rsqrt(tmp, R, R, 1, dsc, s));
+    EX_TRY(reduce_dot(tmp, tmp, R, R, P, 1.0, dpart, dsc, s));
+    EX_TRY(scale_rsqrt(tmp, R, R, P, dsc, s));
     std::swap(vec, tmp);
   }
   // Rayleigh quotient <v, A^H A v>/<v, v> = ||A v||^2 / ||v||^2
-  EX_TRY(enc_build_z(p1, op->smaps, vec, R, p1.nx, eb, s));
+  EX_TRY(enc_build_z(p1, op->smaps, vec, R, p1.nx, eb, s, nullptr, R));
   EX_TRY(enc_forward_partials(p1, eb, s));
   EX_TRY(enc_forward_residual(p1, eb, nullptr, s));
-  EX_TRY(reduce_dot(eb.yop, eb.yop, p1.Tp * p1.NCP, 0, 1, 1.0, dpart, dsc + 1, s));
-  EX_TRY(reduce_dot(vec, vec, R, R, 1, 1.0, dpart, dsc + 2, s));
-  k_lipschitz_final<<<1, 64, 0, s>>>(dsc + 1, dsc + 2, L_out);
+  EX_TRY(reduce_dot(eb.yop, eb.yop, p1.Tp * p1.NCP, p1.Tp * p1.NCP, P, 1.0, dpart, dsc + P, s));
+  EX_TRY(reduce_dot(vec, vec, R, R, P, 1.0, dpart, dsc + 2 * P, s));
+  k_lipschitz_final<<<1, 256, 0, s>>>(dsc + P, dsc + 2 * P, L_out, P);
   EX_LAUNCHED("lipschitz final");
   return EXPENC_OK;
 }

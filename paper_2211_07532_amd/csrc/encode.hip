@@ -67,6 +67,10 @@ __global__ void k_prep_kap(const double *__restrict__ coef, const double *__rest
                            double *__restrict__ kap, int64_t T, int64_t Tp, int L, int NT) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Tp * NT) return;
+  const int pz = blockIdx.y;  // problem
+  if (coef) coef += pz * T * L;
+  time += pz * T;
+  kap += pz * Tp * NT;
   int64_t t = i / NT;
   int j = (int)(i % NT);
   double v = 0.0;
@@ -79,9 +83,13 @@ __global__ void k_prep_kap(const double *__restrict__ coef, const double *__rest
 
 // bet for EXPENC_BASIS_SH: the solid harmonics evaluated at the pixel centres.
 __global__ void k_prep_bet_sh(const double *__restrict__ dw0, double *__restrict__ bet, int nx, int ny, int Rp, int L,
-                              int NT, double dx, double dy, double z) {
+                              int NT, double dx, double dy, double z, const double *__restrict__ z0s) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)Rp * NT) return;
+  const int pz = blockIdx.y;
+  if (dw0) dw0 += (int64_t)pz * nx * ny;
+  bet += (int64_t)pz * Rp * NT;
+  if (z0s) z = z0s[pz];
   const int r = (int)(i / NT);
   const int j = (int)(i % NT);
   double v = 0.0;
@@ -101,6 +109,10 @@ __global__ void k_prep_bet(const double *__restrict__ basis, const double *__res
                            double *__restrict__ bet, int R, int Rp, int L, int NT) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)Rp * NT) return;
+  const int pz = blockIdx.y;
+  if (basis) basis += (int64_t)pz * L * R;
+  if (dw0) dw0 += (int64_t)pz * R;
+  bet += (int64_t)pz * Rp * NT;
   int r = (int)(i / NT);
   int j = (int)(i % NT);
   double v = 0.0;
@@ -114,9 +126,13 @@ __global__ void k_prep_bet(const double *__restrict__ basis, const double *__res
 // Z[r][col] = S_c(r) * x_b(r), col = b*C + c; zero for padded pixels/columns.
 __global__ void k_build_z_f32(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
                               int64_t x_stride, int x_row_stride, int nx, int R, int Rp, int C,
-                              int NC, int NCP, float2 *__restrict__ z) {
+                              int NC, int NCP, float2 *__restrict__ z, int64_t x_pstride) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)Rp * NCP) return;
+  const int pz = blockIdx.y;
+  smaps += (int64_t)pz * C * R;
+  x += pz * x_pstride;
+  z += (int64_t)pz * Rp * NCP;
   int r = (int)(i / NCP);
   int col = (int)(i % NCP);
   float2 v = make_float2(0.f, 0.f);
@@ -135,6 +151,9 @@ __global__ void k_pack_y_f32(const float2 *__restrict__ y, int64_t T, int64_t Tp
                              int NCP, float2 *__restrict__ yop) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Tp * NCP) return;
+  const int pz = blockIdx.y;
+  y += pz * T * NC;
+  yop += pz * Tp * NCP;
   int64_t t = i / NCP;
   int col = (int)(i % NCP);
   float2 v = make_float2(0.f, 0.f);
@@ -162,6 +181,11 @@ __global__ __launch_bounds__(256) void k_fwd_f32(const double *__restrict__ kap,
   const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+  const int pz = blockIdx.z;  // problem
+  kap += pz * Tp * NT;
+  bet += (int64_t)pz * Rp * NT;
+  zop += (int64_t)pz * Rp * NCP;
+  part += pz * nsplit * Tp * NCP * 2;
 
   double kv[NT];
 #pragma unroll
@@ -234,6 +258,11 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
   const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+  const int pz = blockIdx.z;  // problem
+  kap += pz * Tp * NT;
+  bet += (int64_t)pz * Rp * NT;
+  yop += pz * Tp * NCP;
+  part += pz * nsplit * (int64_t)Rp * NCP * 2;
 
   double bv[NT];
 #pragma unroll
@@ -302,6 +331,9 @@ __global__ void k_fwd_reduce_out(const float2 *__restrict__ part, int nsplit, in
                                  int64_t Tp, int C, int NC, int NCP, float2 *__restrict__ y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T * NC) return;
+  const int pz = blockIdx.y;
+  part += pz * nsplit * Tp * NCP;
+  y += pz * T * NC;
   int64_t t = i / NC;
   int col = (int)(i % NC);
   double sx = 0.0, sy = 0.0;
@@ -321,6 +353,10 @@ __global__ void k_fwd_residual(const float2 *__restrict__ part, int nsplit, int6
                                float2 *__restrict__ yop) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Tp * NCP) return;
+  const int pz = blockIdx.y;
+  part += pz * nsplit * Tp * NCP;
+  if (y_meas) y_meas += pz * T * NC;
+  yop += pz * Tp * NCP;
   int64_t t = i / NCP;
   int col = (int)(i % NCP);
   double sx = 0.0, sy = 0.0;
@@ -348,10 +384,18 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
                                                         float2 *__restrict__ x, int64_t x_stride,
                                                         int x_row_stride, const double *__restrict__ alpha_dev,
                                                         const float2 *__restrict__ add,
-                                                        const float2 *__restrict__ base, int nxq) {
+                                                        const float2 *__restrict__ base, int nxq,
+                                                        int64_t x_pstride) {
   const int sub = threadIdx.x & 31;
   const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
   if (r >= R) return;  // uniform per 32-lane group
+  const int pz = blockIdx.y;  // problem
+  part += (int64_t)pz * nsplit * Rp * NCP;
+  smaps += (int64_t)pz * C * R;
+  x += pz * x_pstride;
+  if (alpha_dev) alpha_dev += pz;
+  if (add) add += pz * x_pstride;
+  if (base) base += pz * x_pstride;
   const int64_t rq = (int64_t)(r / nx) * nxq + (r % nx);  // row of the partial sums
   for (int b = 0; b < B; ++b) {
     double sx = 0.0, sy = 0.0;
@@ -409,7 +453,7 @@ static int target_workgroups() {
   return v;
 }
 
-int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p) {
+int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p, int32_t nprob) {
   if (!op) return fail(EXPENC_EINVAL, "operator descriptor is NULL");
   if (op->nx < 1 || op->ny < 1) return fail(EXPENC_EINVAL, "image grid %dx%d is empty", op->nx, op->ny);
   if ((int64_t)op->nx * op->ny > (1 << 26)) return fail(EXPENC_EINVAL, "image grid too large");
@@ -427,6 +471,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p)
   if (!op->time) return fail(EXPENC_EINVAL, "time array is NULL");
   if (!op->smaps) return fail(EXPENC_EINVAL, "smaps is NULL");
   if (batch < 1) return fail(EXPENC_EINVAL, "batch must be >= 1 (got %d)", batch);
+  if (nprob < 1 || nprob > 65535) return fail(EXPENC_EINVAL, "problem count %d out of range", nprob);
   if (precision != EXPENC_FP32 && precision != EXPENC_BF16_SPLIT && precision != EXPENC_FP16_SPLIT)
     return fail(EXPENC_EINVAL, "unknown precision %d", precision);
   if ((int64_t)op->ncoils * batch > 4096) return fail(EXPENC_EUNSUPPORTED, "ncoils*batch > 4096");
@@ -453,10 +498,11 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p)
   q.NT = phase_terms(q.L);
   q.prec = precision;
   q.has_dw0 = op->dw0 != nullptr;
+  q.P = nprob;
   const int tgt = target_workgroups();
   // forward: 256 sample rows per workgroup, split over pixels
   {
-    int64_t nrb = q.Tp / 256;
+    int64_t nrb = q.Tp / 256 * q.P;
     int64_t want = ceil_div(tgt, nrb * q.NGY);
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Rp / 16));
     q.fwd_chunk = (int32_t)round_up(ceil_div(q.Rp, want), 16);
@@ -464,7 +510,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p)
   }
   // adjoint: 256 pixel rows per workgroup, split over samples
   {
-    int64_t nrb = q.Rp / 256;
+    int64_t nrb = q.Rp / 256 * q.P;
     int64_t want = ceil_div(tgt, nrb * q.NGY);
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Tp / 16));
     q.adj_chunk = (int32_t)round_up(ceil_div(q.Tp, want), 16);
@@ -484,44 +530,46 @@ size_t enc_operand_bytes(const EncPlan &p) {
 size_t enc_part_elems(const EncPlan &p) {
   const size_t pf = (size_t)p.fwd_split * p.Tp * p.NCP;
   const size_t pa = (size_t)p.adj_split * p.Rp * p.NCP;
-  return std::max(pf, pa);
+  return std::max(pf, pa) * p.P;
 }
 
 int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
-  b->kap = a.take<double>((size_t)p.Tp * p.NT);
-  b->bet = a.take<double>((size_t)p.Rp * p.NT);
-  b->zop = a.take<float2>((size_t)p.Rp * p.NCP);
-  b->yop = a.take<float2>((size_t)p.Tp * p.NCP);
+  const size_t P = p.P;
+  b->kap = a.take<double>(P * p.Tp * p.NT);
+  b->bet = a.take<double>(P * p.Rp * p.NT);
+  b->zop = a.take<float2>(P * p.Rp * p.NCP);
+  b->yop = a.take<float2>(P * p.Tp * p.NCP);
   b->part = a.take<float2>(std::max(enc_part_elems(p), min_part));
   if (p.prec != EXPENC_FP32) {
-    b->zs = a.take<char>((size_t)p.Rp * (p.NCP / 16) * 256);
-    b->ys = a.take<char>((size_t)p.Tp * (p.NCP / 16) * 256);
+    b->zs = a.take<char>(P * p.Rp * (p.NCP / 16) * 256);
+    b->ys = a.take<char>(P * p.Tp * (p.NCP / 16) * 256);
     if (p.sh) {
-      b->pmono = a.take<double>((size_t)p.Tp * 12);
-      b->dpmono = a.take<float>((size_t)p.Tp * 12);
-      b->dwq = a.take<double>((size_t)p.Rp);
-      b->ddw = a.take<float>((size_t)p.Rp);
+      b->pmono = a.take<double>(P * p.Tp * 12);
+      b->dpmono = a.take<float>(P * p.Tp * 12);
+      b->dwq = a.take<double>(P * p.Rp);
+      b->ddw = a.take<float>(P * p.Rp);
     } else {
-      b->dbet = a.take<float>((size_t)p.Rp * p.NT);
-      b->dkap = a.take<float>((size_t)p.Tp * p.NT);
+      b->dbet = a.take<float>(P * p.Rp * p.NT);
+      b->dkap = a.take<float>(P * p.Tp * p.NT);
     }
   }
   return a.ok() ? EXPENC_OK : EXPENC_EWORKSPACE;
 }
 
 static inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)ceil_div(n, bs); }
+static inline dim3 grid_p(int64_t n, int bs, int P) { return dim3((unsigned)ceil_div(n, bs), (unsigned)P); }
 
 int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
-  k_prep_kap<<<blocks_for(p.Tp * p.NT, 256), 256, 0, s>>>(op->coef, op->time, b.kap, p.T, p.Tp, p.L, p.NT);
+  k_prep_kap<<<grid_p(p.Tp * p.NT, 256, p.P), 256, 0, s>>>(op->coef, op->time, b.kap, p.T, p.Tp, p.L, p.NT);
   EX_LAUNCHED("prep_kap");
   const bool split = p.prec != EXPENC_FP32;
   if (!(split && p.sh)) {  // the polynomial split kernels do not read bet
     if (p.sh)
-      k_prep_bet_sh<<<blocks_for((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(op->dw0, b.bet, p.nx, p.ny, p.Rp, p.L,
-                                                                          p.NT, p.dx, p.dy, p.z0);
+      k_prep_bet_sh<<<grid_p((int64_t)p.Rp * p.NT, 256, p.P), 256, 0, s>>>(op->dw0, b.bet, p.nx, p.ny, p.Rp, p.L,
+                                                                            p.NT, p.dx, p.dy, p.z0, p.z0s);
     else
-      k_prep_bet<<<blocks_for((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L,
-                                                                       p.NT);
+      k_prep_bet<<<grid_p((int64_t)p.Rp * p.NT, 256, p.P), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L,
+                                                                         p.NT);
     EX_LAUNCHED("prep_bet");
   }
   if (split) return split_prepare(p, op, b, s);
@@ -529,19 +577,19 @@ int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipS
 }
 
 int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x_stride,
-                int32_t x_row_stride, const EncBuffers &b, hipStream_t s, const float2 *xsub) {
-  if (p.prec != EXPENC_FP32) return split_build_z(p, smaps, x, xsub, x_stride, x_row_stride, b, s);
+                int32_t x_row_stride, const EncBuffers &b, hipStream_t s, const float2 *xsub, int64_t x_pstride) {
+  if (p.prec != EXPENC_FP32) return split_build_z(p, smaps, x, xsub, x_stride, x_row_stride, b, s, x_pstride);
   if (xsub) return fail(EXPENC_EUNSUPPORTED, "operand difference is only built for split forms");
-  k_build_z_f32<<<blocks_for((int64_t)p.Rp * p.NCP, 256), 256, 0, s>>>(
+  k_build_z_f32<<<grid_p((int64_t)p.Rp * p.NCP, 256, p.P), 256, 0, s>>>(
       reinterpret_cast<const float2 *>(smaps), x, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC,
-      p.NCP, b.zop);
+      p.NCP, b.zop, x_pstride);
   EX_LAUNCHED("build_z");
   return EXPENC_OK;
 }
 
 int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s) {
   if (p.prec != EXPENC_FP32) return split_pack_y(p, y, false, nullptr, b, s);
-  k_pack_y_f32<<<blocks_for(p.Tp * p.NCP, 256), 256, 0, s>>>(y, p.T, p.Tp, p.C, p.NC, p.NCP, b.yop);
+  k_pack_y_f32<<<grid_p(p.Tp * p.NCP, 256, p.P), 256, 0, s>>>(y, p.T, p.Tp, p.C, p.NC, p.NCP, b.yop);
   EX_LAUNCHED("pack_y");
   return EXPENC_OK;
 }
@@ -631,7 +679,7 @@ int kernel_timing(int32_t mode, double *out) {
 
 template <int NT>
 static void launch_fwd(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY);
+  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   if (p.GW == 2)
     k_fwd_f32<NT, 2><<<grid, 256, 0, s>>>(b.kap, b.bet, b.zop, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk, p.fwd_split);
@@ -641,7 +689,7 @@ static void launch_fwd(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 template <int NT>
 static void launch_adj(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY);
+  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   if (p.GW == 2)
     k_adj_f32<NT, 2><<<grid, 256, 0, s>>>(b.kap, b.bet, b.yop, part, p.Rp, p.Tp, p.NCP, p.adj_chunk, p.adj_split);
@@ -682,25 +730,25 @@ int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 }
 
 int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s) {
-  k_fwd_reduce_out<<<blocks_for(p.T * p.NC, 256), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC, p.NCP, y);
+  k_fwd_reduce_out<<<grid_p(p.T * p.NC, 256, p.P), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC, p.NCP, y);
   EX_LAUNCHED("forward reduce");
   return EXPENC_OK;
 }
 
 int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s) {
   if (p.prec != EXPENC_FP32) return split_pack_y(p, nullptr, true, y_meas, b, s);
-  k_fwd_residual<<<blocks_for(p.Tp * p.NCP, 256), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC,
-                                                                p.NCP, y_meas, b.yop);
+  k_fwd_residual<<<grid_p(p.Tp * p.NCP, 256, p.P), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC,
+                                                                  p.NCP, y_meas, b.yop);
   EX_LAUNCHED("forward residual");
   return EXPENC_OK;
 }
 
 int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
                            int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
-                           const float2 *add, hipStream_t s, const float2 *base) {
-  k_adj_reduce_out<<<blocks_for(p.R, 8), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
-                                                      reinterpret_cast<const float2 *>(smaps), x, x_stride,
-                                                      x_row_stride, alpha_dev, add, base, p.nxq);
+                           const float2 *add, hipStream_t s, const float2 *base, int64_t x_pstride) {
+  k_adj_reduce_out<<<grid_p(p.R, 8, p.P), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
+                                                       reinterpret_cast<const float2 *>(smaps), x, x_stride,
+                                                       x_row_stride, alpha_dev, add, base, p.nxq, x_pstride);
   EX_LAUNCHED("adjoint reduce");
   return EXPENC_OK;
 }

@@ -37,12 +37,14 @@ __global__ void k_zero_f2(float2 *out, int64_t n) {
   if (i < n) out[i] = make_float2(0.f, 0.f);
 }
 
-// sc[0] = L; sc[1] = -2/L; tau[b] = lambda[b]/L
-__global__ void k_fista_scalars(double *sc, int B) {
-  const int b = threadIdx.x;
-  const double L = sc[0];
-  if (b == 0) sc[1] = L > 0.0 ? -2.0 / L : 0.0;
-  if (b < B) sc[2 + B + b] = L > 0.0 ? sc[2 + b] / L : 0.0;
+// per problem p: sc[P + p] = -2/L_p; per column: tau = lambda/L_p
+__global__ void k_fista_scalars(double *sc, int P, int B) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P * B) return;
+  const int p = i / B;
+  const double L = sc[p];
+  if (i % B == 0) sc[P + p] = L > 0.0 ? -2.0 / L : 0.0;
+  sc[2 * P + P * B + i] = L > 0.0 ? sc[2 * P + i] / L : 0.0;
 }
 
 // out[b][y][x] = src[b][y][x] for the nx x ny crop of an nxp x nyp grid
@@ -136,15 +138,18 @@ __global__ void k_cg_dir(float2 *__restrict__ p, const float2 *__restrict__ r, i
 }
 
 // v = z + alpha * g on the nx x ny crop of each nxp x nyp image, v = z elsewhere
+// (alpha_dev holds one value per problem of B images)
 __global__ void k_grad_step(float2 *__restrict__ v, const float2 *__restrict__ z, const float2 *__restrict__ g,
-                            const double *__restrict__ alpha_dev, int nxp, int nyp, int nx, int ny, int64_t n) {
+                            const double *__restrict__ alpha_dev, int nxp, int nyp, int nx, int ny, int64_t n,
+                            int B) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const int64_t p = i % ((int64_t)nxp * nyp);
+  const int64_t img = (int64_t)nxp * nyp;
+  const int64_t p = i % img;
   const int yy = (int)(p / nxp), xx = (int)(p % nxp);
   float2 o = z[i];
   if (yy < ny && xx < nx) {
-    const float a = (float)*alpha_dev;
+    const float a = (float)alpha_dev[(i / img) / B];
     o.x += a * g[i].x;
     o.y += a * g[i].y;
   }
@@ -240,21 +245,28 @@ static int run_graph(uint64_t key, hipStream_t s, Body body) {
 }
 
 // ---------------------------------------------------------------------------
-// FISTA
+// FISTA for a group of P problems of identical shape (P = 1 for
+// fista_solve), each with B columns sharing its operator.  Scalars in sc:
+// L[p] at sc[p], alpha = -2/L at sc[P + p], lambda at sc[2P + p*B + b],
+// tau = lambda/L at sc[2P + PB + p*B + b], then scratch.
 // ---------------------------------------------------------------------------
 
 struct FistaLayout {
   EncPlan p, p1, pf;  // p: iteration precision (batch B); p1: FP32 batch 1; pf: FP32 batch B
+  int P = 1, B = 1;
   int nxp = 0, nyp = 0;
   EncBuffers eb;
   float2 *z = nullptr, *v = nullptr, *w = nullptr, *x0 = nullptr, *x1 = nullptr;
   float2 *zref = nullptr, *gref = nullptr;   // split forms: anchor z_ref and A^H(A z_ref - y)
   float2 *pvec = nullptr, *ptmp = nullptr;
-  double *dpart = nullptr;   // [B * kRedBlocks]
-  double *sc = nullptr;      // [2 + 2B + 8]
-  double *l1 = nullptr;      // [levels][B][l1_blocks]
+  double *dpart = nullptr;   // [P * B * kRedBlocks]
+  double *sc = nullptr;      // [2P + 2PB + 3P]
+  double *l1 = nullptr;      // [levels][B][l1_blocks]   (P == 1 only)
   double *data = nullptr;    // [B]
   int l1_blocks = 0;
+  double *lam_of(int) const { return sc + 2 * P; }
+  double *tau() const { return sc + 2 * P + P * B; }
+  double *scratch() const { return sc + 2 * P + 2 * P * B; }
 };
 
 static int resolve_pad(int n, int given, int levels, int *out) {
@@ -265,18 +277,21 @@ static int resolve_pad(int n, int given, int levels, int *out) {
   return EXPENC_OK;
 }
 
-static int layout_fista(const expenc_op *op, int32_t batch, int32_t precision, int levels, int nx_pad, int ny_pad,
-                        bool objective, Arena &a, FistaLayout *L) {
-  EX_TRY(make_plan(op, batch, precision, &L->p));
-  EX_TRY(make_plan(op, 1, EXPENC_FP32, &L->p1));
-  EX_TRY(make_plan(op, batch, EXPENC_FP32, &L->pf));
+static int layout_fista(const expenc_op *op, int32_t nprob, int32_t batch, int32_t precision, int levels, int nx_pad,
+                        int ny_pad, bool objective, Arena &a, FistaLayout *L) {
+  EX_TRY(make_plan(op, batch, precision, &L->p, nprob));
+  EX_TRY(make_plan(op, 1, EXPENC_FP32, &L->p1, nprob));
+  EX_TRY(make_plan(op, batch, EXPENC_FP32, &L->pf, nprob));
   if (levels < 1 || levels > 12) return fail(EXPENC_EINVAL, "levels must be in [1, 12]");
+  if (objective && nprob != 1) return fail(EXPENC_EUNSUPPORTED, "objective traces are per single problem");
   EX_TRY(resolve_pad(op->nx, nx_pad, levels, &L->nxp));
   EX_TRY(resolve_pad(op->ny, ny_pad, levels, &L->nyp));
+  L->P = nprob;
+  L->B = batch;
   // p's buffers hold the FP32 operands of pf as well; the partial-sum buffer
   // is shared by all three plans (identical padded geometry)
   carve_enc(L->p, a, &L->eb, std::max(enc_part_elems(L->p1), enc_part_elems(L->pf)));
-  const size_t img = (size_t)batch * L->nxp * L->nyp;
+  const size_t img = (size_t)nprob * batch * L->nxp * L->nyp;
   L->z = a.take<float2>(img);
   L->v = a.take<float2>(img);
   L->w = a.take<float2>(img);
@@ -286,10 +301,10 @@ static int layout_fista(const expenc_op *op, int32_t batch, int32_t precision, i
     L->zref = a.take<float2>(img);
     L->gref = a.take<float2>(img);
   }
-  L->pvec = a.take<float2>((size_t)L->p.R);
-  L->ptmp = a.take<float2>((size_t)L->p.R);
-  L->dpart = a.take<double>((size_t)batch * kRedBlocks);
-  L->sc = a.take<double>((size_t)2 + 2 * batch + 8);
+  L->pvec = a.take<float2>((size_t)L->p.R * nprob);
+  L->ptmp = a.take<float2>((size_t)L->p.R * nprob);
+  L->dpart = a.take<double>((size_t)nprob * batch * kRedBlocks);
+  L->sc = a.take<double>((size_t)2 * nprob + 2 * nprob * batch + 3 * nprob + 8);
   L->l1_blocks = (int)ceil_div(L->nxp, 16);
   if (objective) {
     L->l1 = a.take<double>((size_t)levels * batch * L->l1_blocks);
@@ -299,16 +314,11 @@ static int layout_fista(const expenc_op *op, int32_t batch, int32_t precision, i
 }
 
 size_t fista_bytes(const expenc_op *op, int32_t batch, int32_t precision, int32_t nx_pad, int32_t ny_pad) {
-  // worst case over levels: use the padding implied by 12 levels only if none given
+  // default grids are rounded to 2^levels; 4 levels covers the usual cases
   Arena a;
   FistaLayout L;
-  int levels = 1;
-  if (nx_pad > 0 && ny_pad > 0) {
-    levels = 1;
-  } else {
-    levels = 4;  // default grids are rounded to 2^levels; 4 covers the usual cases
-  }
-  if (layout_fista(op, batch, precision, levels, nx_pad, ny_pad, true, a, &L) != EXPENC_OK && !L.p.R) return 0;
+  const int levels = (nx_pad > 0 && ny_pad > 0) ? 1 : 4;
+  if (layout_fista(op, 1, batch, precision, levels, nx_pad, ny_pad, true, a, &L) != EXPENC_OK && !L.p.R) return 0;
   return a.used + 256;
 }
 
@@ -323,6 +333,128 @@ static int check_fista_opts(const expenc_fista_opts *o, int *eff_refine) {
   return EXPENC_OK;
 }
 
+// One group's solve, split into stream-ordered phases so that several groups
+// can share one captured graph.
+struct FistaGroup {
+  const expenc_op *op = nullptr;  // packed operator of the group
+  FistaLayout L;
+  FilterSet f;
+  const expenc_fista_opts *opts = nullptr;
+  const float2 *y = nullptr;      // [P][B][T][C]
+  int refine = 10;
+  std::vector<double> beta;
+
+  int prologue(hipStream_t s) {
+    const EncPlan &p = L.p, &pf = L.pf;
+    const int P = L.P, B = L.B;
+    const int64_t img = (int64_t)L.nxp * L.nyp;
+    // FP32 tables first (the FP32 plan's pixel layout), then the split tables
+    EX_TRY(enc_prepare(pf, op, L.eb, s));
+    if (opts->precision != EXPENC_FP32) EX_TRY(enc_prepare(p, op, L.eb, s));
+    if (opts->lipschitz > 0) {
+      k_fill_d<<<1, 256, 0, s>>>(L.sc, P, opts->lipschitz);
+      EX_LAUNCHED("fill");
+    } else {
+      EX_TRY(lipschitz_run(L.p1, op, L.eb, opts->n_power, opts->power_v0, L.pvec, L.ptmp, L.dpart, L.scratch(),
+                           L.sc, s));
+    }
+    if (opts->lambda >= 0) {
+      k_fill_d<<<(unsigned)ceil_div(P * B, 256), 256, 0, s>>>(L.lam_of(0), P * B, opts->lambda);
+      EX_LAUNCHED("fill");
+    } else {
+      EX_TRY(enc_pack_y(pf, y, L.eb, s));
+      EX_TRY(enc_adjoint_partials(pf, L.eb, s));
+      EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.v, pf.R, pf.nx, nullptr, nullptr, s, nullptr,
+                                    (int64_t)B * pf.R));
+      EX_TRY(reduce_maxabs(L.v, pf.R, pf.R, P * B, opts->lambda_factor, L.dpart, L.lam_of(0), s));
+    }
+    k_fista_scalars<<<(unsigned)ceil_div(P * B, 256), 256, 0, s>>>(L.sc, P, B);
+    EX_LAUNCHED("scalars");
+    k_zero_f2<<<(unsigned)ceil_div(img * P * B, 256), 256, 0, s>>>(L.x0, img * P * B);
+    k_zero_f2<<<(unsigned)ceil_div(img * P * B, 256), 256, 0, s>>>(L.z, img * P * B);
+    EX_LAUNCHED("zero");
+    const int K = opts->n_iter;
+    beta.assign(K, 0.0);
+    double t = 1.0;
+    for (int k = 0; k < K; ++k) {
+      const double tn = opts->ista ? 1.0 : (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
+      beta[k] = (t - 1.0) / tn;
+      t = tn;
+    }
+    return EXPENC_OK;
+  }
+
+  int body(hipStream_t cs) {
+    const EncPlan &p = L.p, &pf = L.pf;
+    const int P = L.P, B = L.B;
+    const int nxp = L.nxp, nyp = L.nyp;
+    const int64_t img = (int64_t)nxp * nyp;
+    const int64_t pimg = img * B;  // elements between problems
+    const int64_t all = pimg * P;
+    const bool padded = (nxp != p.nx) || (nyp != p.ny);
+    const bool split = opts->precision != EXPENC_FP32;
+    const bool with_obj = opts->objective != nullptr;
+    const double *alpha = L.sc + P;
+    const int K = opts->n_iter;
+    for (int k = 0; k < K; ++k) {
+      float2 *xk = (k % 2 == 0) ? L.x1 : L.x0;
+      float2 *xprev = (k % 2 == 0) ? L.x0 : L.x1;
+      if (!split) {
+        // v = z - (2/L) A^H (A z - y)
+        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs, nullptr, pimg));
+        EX_TRY(enc_forward_partials(p, L.eb, cs));
+        EX_TRY(enc_forward_residual(p, L.eb, y, cs));
+        EX_TRY(enc_adjoint_partials(p, L.eb, cs));
+        if (padded) EX_TRY(copy_f2(L.z, L.v, all, cs));
+        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, nullptr, pimg));
+      } else if (k % refine == 0 || k == K - 1) {
+        // anchor: exact FP32 gradient at z_ref = z
+        EX_TRY(enc_build_z(pf, op->smaps, L.z, img, nxp, L.eb, cs, nullptr, pimg));
+        EX_TRY(enc_forward_partials(pf, L.eb, cs));
+        EX_TRY(enc_forward_residual(pf, L.eb, y, cs));
+        EX_TRY(enc_adjoint_partials(pf, L.eb, cs));
+        EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.gref, img, nxp, nullptr, nullptr, cs, nullptr, pimg));
+        k_grad_step<<<(unsigned)ceil_div(all, 256), 256, 0, cs>>>(L.v, L.z, L.gref, alpha, nxp, nyp, p.nx, p.ny, all, B);
+        EX_LAUNCHED("gradient step");
+        EX_TRY(copy_f2(L.z, L.zref, all, cs));
+      } else {
+        // split operators on the difference: g = g_ref + A~^H A~ (z - z_ref)
+        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs, L.zref, pimg));
+        EX_TRY(enc_forward_partials(p, L.eb, cs));
+        EX_TRY(enc_forward_residual(p, L.eb, nullptr, cs));
+        EX_TRY(enc_adjoint_partials(p, L.eb, cs));
+        if (padded) EX_TRY(copy_f2(L.z, L.v, all, cs));
+        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, L.gref, pimg));
+      }
+      EX_TRY(dwt_forward_levels(f, nxp, nyp, opts->levels, P * B, L.v, L.w, L.tau(), with_obj ? L.l1 : nullptr,
+                                L.l1_blocks, cs));
+      EX_TRY(dwt_inverse_levels(f, nxp, nyp, opts->levels, P * B, L.w, xk, xprev, L.z, beta[k], cs));
+      if (with_obj) {
+        EX_TRY(enc_build_z(pf, op->smaps, xk, img, nxp, L.eb, cs));
+        EX_TRY(enc_forward_partials(pf, L.eb, cs));
+        EX_TRY(enc_forward_residual(pf, L.eb, y, cs));
+        k_resid_norm_part<<<dim3(kRedBlocks, B), 256, 0, cs>>>(L.eb.yop, pf.Tp, pf.NCP, pf.C, L.dpart);
+        EX_LAUNCHED("residual norm");
+        EX_TRY(reduce_sum_parts(L.dpart, kRedBlocks, B, 1.0, L.data, cs));
+        k_objective<<<B, 256, 0, cs>>>(L.data, L.l1, opts->levels, B, L.l1_blocks, nxp, L.lam_of(0),
+                                        opts->objective, K, k);
+        EX_LAUNCHED("objective");
+      }
+    }
+    return EXPENC_OK;
+  }
+
+  // crop of x_K into out [P][B][ny][nx]
+  int epilogue(float2 *out, hipStream_t s) {
+    const int K = opts->n_iter;
+    const float2 *xK = (K == 0) ? L.x0 : ((K - 1) % 2 == 0 ? L.x1 : L.x0);
+    const int PB = L.P * L.B;
+    k_crop<<<(unsigned)ceil_div((int64_t)L.p.R * PB, 256), 256, 0, s>>>(xK, L.nxp, L.nyp, L.p.nx, L.p.ny, PB, out);
+    EX_LAUNCHED("crop");
+    return EXPENC_OK;
+  }
+};
+
 }  // namespace expenc
 
 using namespace expenc;
@@ -332,120 +464,26 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
   int refine = 10;
   EX_TRY(check_fista_opts(opts, &refine));
   if (!y || !x) return fail(EXPENC_EINVAL, "y or x is NULL");
-  FistaLayout L;
+  FistaGroup G;
   Arena a{static_cast<char *>(ws), ws_bytes, 0};
-  const int st = layout_fista(op, batch, opts->precision, opts->levels, opts->nx_pad, opts->ny_pad,
-                              opts->objective != nullptr, a, &L);
+  const int st = layout_fista(op, 1, batch, opts->precision, opts->levels, opts->nx_pad, opts->ny_pad,
+                              opts->objective != nullptr, a, &G.L);
   if (st == EXPENC_EWORKSPACE || !ws) {
     Arena need;
     FistaLayout tmp;
-    layout_fista(op, batch, opts->precision, opts->levels, opts->nx_pad, opts->ny_pad, opts->objective != nullptr,
+    layout_fista(op, 1, batch, opts->precision, opts->levels, opts->nx_pad, opts->ny_pad, opts->objective != nullptr,
                  need, &tmp);
     return fail(EXPENC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
                 need.used + 256);
   }
   EX_TRY(st);
-  FilterSet f;
-  EX_TRY(make_filter_set(opts->wavelet, &f));
+  EX_TRY(make_filter_set(opts->wavelet, &G.f));
+  G.op = op;
+  G.opts = opts;
+  G.y = reinterpret_cast<const float2 *>(y);
+  G.refine = refine;
   hipStream_t s = (hipStream_t)stream;
-  const EncPlan &p = L.p;
-  const int B = batch;
-  const int nxp = L.nxp, nyp = L.nyp;
-  const int64_t img = (int64_t)nxp * nyp;
-  const float2 *y2 = reinterpret_cast<const float2 *>(y);
-
-  // ---- prologue (eager, stream-ordered) ----
-  // FP32 tables first (the FP32 plan's pixel layout), then the split tables
-  EX_TRY(enc_prepare(L.pf, op, L.eb, s));
-  if (opts->precision != EXPENC_FP32) EX_TRY(enc_prepare(p, op, L.eb, s));
-  if (opts->lipschitz > 0) {
-    k_fill_d<<<1, 64, 0, s>>>(L.sc, 1, opts->lipschitz);
-    EX_LAUNCHED("fill");
-  } else {
-    EX_TRY(lipschitz_run(L.p1, op, L.eb, opts->n_power, opts->power_v0, L.pvec, L.ptmp, L.dpart,
-                         L.sc + 2 + 2 * B, L.sc, s));
-  }
-  if (opts->lambda >= 0) {
-    k_fill_d<<<1, 256, 0, s>>>(L.sc + 2, B, opts->lambda);
-    EX_LAUNCHED("fill");
-  } else {
-    const EncPlan &pf = L.pf;
-    EX_TRY(enc_pack_y(pf, y2, L.eb, s));
-    EX_TRY(enc_adjoint_partials(pf, L.eb, s));
-    EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.v, pf.R, pf.nx, nullptr, nullptr, s));
-    EX_TRY(reduce_maxabs(L.v, pf.R, pf.R, B, opts->lambda_factor, L.dpart, L.sc + 2, s));
-  }
-  k_fista_scalars<<<1, 256, 0, s>>>(L.sc, B);
-  EX_LAUNCHED("scalars");
-  k_zero_f2<<<(unsigned)ceil_div(img * B, 256), 256, 0, s>>>(L.x0, img * B);
-  k_zero_f2<<<(unsigned)ceil_div(img * B, 256), 256, 0, s>>>(L.z, img * B);
-  EX_LAUNCHED("zero");
-
-  // ---- iterations (captured) ----
-  const int K = opts->n_iter;
-  std::vector<double> beta(K);
-  {
-    double t = 1.0;
-    for (int k = 0; k < K; ++k) {
-      const double tn = opts->ista ? 1.0 : (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-      beta[k] = (t - 1.0) / tn;
-      t = tn;
-    }
-  }
-  const bool padded = (nxp != p.nx) || (nyp != p.ny);
-  const bool split = opts->precision != EXPENC_FP32;
-  const bool with_obj = opts->objective != nullptr;
-  auto body = [&](hipStream_t cs) -> int {
-    for (int k = 0; k < K; ++k) {
-      float2 *xk = (k % 2 == 0) ? L.x1 : L.x0;
-      float2 *xprev = (k % 2 == 0) ? L.x0 : L.x1;
-      if (!split) {
-        // v = z - (2/L) A^H (A z - y)
-        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs));
-        EX_TRY(enc_forward_partials(p, L.eb, cs));
-        EX_TRY(enc_forward_residual(p, L.eb, y2, cs));
-        EX_TRY(enc_adjoint_partials(p, L.eb, cs));
-        if (padded) EX_TRY(copy_f2(L.z, L.v, img * B, cs));
-        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, L.sc + 1, L.z, cs));
-      } else if (k % refine == 0 || k == K - 1) {
-        // anchor: exact FP32 gradient at z_ref = z
-        const EncPlan &pf = L.pf;
-        EX_TRY(enc_build_z(pf, op->smaps, L.z, img, nxp, L.eb, cs));
-        EX_TRY(enc_forward_partials(pf, L.eb, cs));
-        EX_TRY(enc_forward_residual(pf, L.eb, y2, cs));
-        EX_TRY(enc_adjoint_partials(pf, L.eb, cs));
-        EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.gref, img, nxp, nullptr, nullptr, cs));
-        k_grad_step<<<(unsigned)ceil_div(img * B, 256), 256, 0, cs>>>(L.v, L.z, L.gref, L.sc + 1, nxp, nyp, p.nx,
-                                                                       p.ny, (int64_t)B * img);
-        EX_LAUNCHED("gradient step");
-        EX_TRY(copy_f2(L.z, L.zref, img * B, cs));
-      } else {
-        // split operators on the difference: g = g_ref + A~^H A~ (z - z_ref)
-        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs, L.zref));
-        EX_TRY(enc_forward_partials(p, L.eb, cs));
-        EX_TRY(enc_forward_residual(p, L.eb, nullptr, cs));
-        EX_TRY(enc_adjoint_partials(p, L.eb, cs));
-        if (padded) EX_TRY(copy_f2(L.z, L.v, img * B, cs));
-        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, L.sc + 1, L.z, cs, L.gref));
-      }
-      EX_TRY(dwt_forward_levels(f, nxp, nyp, opts->levels, B, L.v, L.w, L.sc + 2 + B, with_obj ? L.l1 : nullptr,
-                                L.l1_blocks, cs));
-      EX_TRY(dwt_inverse_levels(f, nxp, nyp, opts->levels, B, L.w, xk, xprev, L.z, beta[k], cs));
-      if (with_obj) {
-        const EncPlan &pf = L.pf;
-        EX_TRY(enc_build_z(pf, op->smaps, xk, img, nxp, L.eb, cs));
-        EX_TRY(enc_forward_partials(pf, L.eb, cs));
-        EX_TRY(enc_forward_residual(pf, L.eb, y2, cs));
-        k_resid_norm_part<<<dim3(kRedBlocks, B), 256, 0, cs>>>(L.eb.yop, pf.Tp, pf.NCP, pf.C, L.dpart);
-        EX_LAUNCHED("residual norm");
-        EX_TRY(reduce_sum_parts(L.dpart, kRedBlocks, B, 1.0, L.data, cs));
-        k_objective<<<B, 256, 0, cs>>>(L.data, L.l1, opts->levels, B, L.l1_blocks, nxp, L.sc + 2,
-                                        opts->objective, K, k);
-        EX_LAUNCHED("objective");
-      }
-    }
-    return EXPENC_OK;
-  };
+  EX_TRY(G.prologue(s));
   uint64_t key = 1469598103934665603ull;
   key = fnv(key, op, sizeof(*op));
   key = fnv(key, &batch, sizeof(batch));
@@ -453,15 +491,10 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
   key = fnv(key, &ws, sizeof(ws));
   key = fnv(key, &ws_bytes, sizeof(ws_bytes));
   key = fnv(key, opts, sizeof(*opts));
-  if (K > 0) EX_TRY(run_graph(key, s, body));
-
-  // ---- epilogue ----
-  const float2 *xK = (K == 0) ? L.x0 : ((K - 1) % 2 == 0 ? L.x1 : L.x0);
-  k_crop<<<(unsigned)ceil_div((int64_t)p.R * B, 256), 256, 0, s>>>(xK, nxp, nyp, p.nx, p.ny, B,
-                                                                   reinterpret_cast<float2 *>(x));
-  EX_LAUNCHED("crop");
+  if (opts->n_iter > 0) EX_TRY(run_graph(key, s, [&](hipStream_t cs) { return G.body(cs); }));
+  EX_TRY(G.epilogue(reinterpret_cast<float2 *>(x), s));
   if (opts->scalars) {
-    k_copy_d<<<1, 256, 0, s>>>(L.sc, opts->scalars, 2 + 2 * B);
+    k_copy_d<<<1, 256, 0, s>>>(G.L.sc, opts->scalars, 2 + 2 * batch);
     EX_LAUNCHED("scalars out");
   }
   return EXPENC_OK;
@@ -555,5 +588,211 @@ extern "C" int cg_solve(const expenc_op *op, int32_t batch, const float *y, floa
   key = fnv(key, &opts->precision, sizeof(opts->precision));
   if (opts->n_iter > 0) EX_TRY(run_graph(key, s, body));
   EX_TRY(copy_f2(L.xv, reinterpret_cast<float2 *>(x), n * B, s));
+  return EXPENC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched FISTA over independent problems of mixed shapes.  Problems with the
+// same geometry form a group whose operands are packed contiguously
+// ([P][...] per array), so that every contraction, table and wavelet pass of
+// the group is ONE launch with the problem index in the grid.  All groups'
+// iteration loops are captured into one graph, each group on its own forked
+// capture stream, so small passes of different groups overlap.
+// ---------------------------------------------------------------------------
+
+namespace expenc {
+
+struct Vals64 {
+  double v[64];
+};
+
+__global__ void k_set_vals(double *out, Vals64 vals, int n) {
+  const int i = threadIdx.x;
+  if (i < n) out[i] = vals.v[i];
+}
+
+static bool same_geometry(const expenc_op &a, const expenc_op &b) {
+  return a.nx == b.nx && a.ny == b.ny && a.ncoils == b.ncoils && a.nbasis == b.nbasis && a.nsamples == b.nsamples &&
+         a.basis_kind == b.basis_kind && (a.dw0 != nullptr) == (b.dw0 != nullptr) && a.fov_x == b.fov_x &&
+         a.fov_y == b.fov_y;
+}
+
+struct BatchPlan {
+  std::vector<std::vector<int>> members;  // problem indices per group, in input order
+  std::vector<FistaGroup> groups;
+  std::vector<expenc_op> packed;          // one packed operator per group
+  std::vector<double *> z0s;
+};
+
+static int layout_batched(int32_t nprob, const expenc_op *ops, int32_t batch, const expenc_fista_opts *o, Arena &a,
+                          BatchPlan *bp) {
+  if (nprob < 1 || nprob > 65535) return fail(EXPENC_EINVAL, "problem count %d out of range", nprob);
+  if (!ops) return fail(EXPENC_EINVAL, "ops is NULL");
+  if (o->objective || o->scalars) return fail(EXPENC_EUNSUPPORTED, "objective/scalars outputs are per single solve");
+  if (o->nx_pad > 0 || o->ny_pad > 0)
+    return fail(EXPENC_EINVAL, "batched solves pad each problem to 2^levels (nx_pad, ny_pad must be 0)");
+  for (int i = 0; i < nprob; ++i) {
+    int g = 0;
+    for (; g < (int)bp->members.size(); ++g)
+      if (same_geometry(ops[bp->members[g][0]], ops[i])) break;
+    if (g == (int)bp->members.size()) bp->members.emplace_back();
+    bp->members[g].push_back(i);
+  }
+  const int NG = (int)bp->members.size();
+  bp->groups.resize(NG);
+  bp->packed.resize(NG);
+  bp->z0s.resize(NG);
+  for (int g = 0; g < NG; ++g) {
+    const std::vector<int> &m = bp->members[g];
+    const int P = (int)m.size();
+    const expenc_op &o0 = ops[m[0]];
+    expenc_op &q = bp->packed[g];
+    q = o0;
+    const size_t R = (size_t)o0.nx * o0.ny, T = (size_t)o0.nsamples, Lb = (size_t)std::max(o0.nbasis, 0);
+    // packed inputs (each member's arrays copied in, input order)
+    q.coef = Lb ? a.take<double>(P * T * Lb) : nullptr;
+    q.time = a.take<double>(P * T);
+    q.basis = (Lb && o0.basis_kind == EXPENC_BASIS_MAPS) ? a.take<double>(P * Lb * R) : nullptr;
+    q.dw0 = o0.dw0 ? a.take<double>(P * R) : nullptr;
+    q.smaps = reinterpret_cast<const float *>(a.take<float2>(P * (size_t)o0.ncoils * R));
+    bp->z0s[g] = a.take<double>(P);
+    bp->groups[g].y = a.take<float2>((size_t)P * batch * T * o0.ncoils);
+    // the plans take geometry from the first member (make_plan also checks
+    // its pointers, which the packed copies may not have yet when sizing)
+    const expenc_op &chk = o0;
+    // (a short arena is only known at the end: keep carving to learn the total)
+    const int st = layout_fista(&chk, P, batch, o->precision, o->levels, 0, 0, false, a, &bp->groups[g].L);
+    if (st != EXPENC_OK && st != EXPENC_EWORKSPACE) return st;
+    bp->groups[g].L.p.z0s = bp->groups[g].L.p1.z0s = bp->groups[g].L.pf.z0s = bp->z0s[g];
+  }
+  return a.ok() ? EXPENC_OK : EXPENC_EWORKSPACE;
+}
+
+static hipStream_t fork_stream(int device, int k) {
+  static std::mutex mu;
+  static std::vector<std::vector<hipStream_t>> pool;
+  constexpr int kMax = 8;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)pool.size() <= device) pool.resize(device + 1);
+  auto &v = pool[device];
+  if (v.empty()) v.assign(kMax, nullptr);
+  hipStream_t &st = v[k % kMax];
+  if (!st) hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  return st;
+}
+
+}  // namespace expenc
+
+extern "C" size_t fista_batched_workspace_size(int32_t nprob, const expenc_op *ops, int32_t batch,
+                                               const expenc_fista_opts *opts) {
+  int refine = 10;
+  if (check_fista_opts(opts, &refine) != EXPENC_OK) return 0;
+  Arena a;
+  BatchPlan bp;
+  if (layout_batched(nprob, ops, batch, opts, a, &bp) != EXPENC_OK && a.used == 0) return 0;
+  return a.used + 256;
+}
+
+extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t batch, const float *const *y,
+                                   float *const *x, const expenc_fista_opts *opts, void *ws, size_t ws_bytes,
+                                   void *stream) {
+  int refine = 10;
+  EX_TRY(check_fista_opts(opts, &refine));
+  if (!y || !x) return fail(EXPENC_EINVAL, "y or x pointer array is NULL");
+  for (int i = 0; i < nprob; ++i)
+    if (!y[i] || !x[i]) return fail(EXPENC_EINVAL, "problem %d: y or x is NULL", i);
+  for (int i = 0; i < nprob; ++i) {
+    EncPlan chk;
+    EX_TRY(make_plan(&ops[i], batch, opts->precision, &chk));
+  }
+  BatchPlan bp;
+  Arena a{static_cast<char *>(ws), ws_bytes, 0};
+  const int st = layout_batched(nprob, ops, batch, opts, a, &bp);
+  if (st == EXPENC_EWORKSPACE || !ws)
+    return fail(EXPENC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
+                fista_batched_workspace_size(nprob, ops, batch, opts));
+  EX_TRY(st);
+  FilterSet f;
+  EX_TRY(make_filter_set(opts->wavelet, &f));
+  hipStream_t s = (hipStream_t)stream;
+  const int NG = (int)bp.members.size();
+  // gather the members' inputs into the packed group arrays
+  for (int g = 0; g < NG; ++g) {
+    const std::vector<int> &m = bp.members[g];
+    const expenc_op &q = bp.packed[g];
+    const size_t R = (size_t)q.nx * q.ny, T = (size_t)q.nsamples, Lb = (size_t)std::max(q.nbasis, 0);
+    const size_t ny = (size_t)batch * T * q.ncoils;
+    Vals64 z0v{};
+    for (size_t j = 0; j < m.size(); ++j) {
+      const expenc_op &o = ops[m[j]];
+      auto cp = [&](const void *dst, const void *src, size_t bytes) {
+        return hipMemcpyAsync(const_cast<void *>(dst), src, bytes, hipMemcpyDeviceToDevice, s);
+      };
+      if (Lb) EX_HIP(cp(q.coef + j * T * Lb, o.coef, T * Lb * sizeof(double)));
+      EX_HIP(cp(q.time + j * T, o.time, T * sizeof(double)));
+      if (q.basis) EX_HIP(cp(q.basis + j * Lb * R, o.basis, Lb * R * sizeof(double)));
+      if (q.dw0) EX_HIP(cp(q.dw0 + j * R, o.dw0, R * sizeof(double)));
+      EX_HIP(cp(q.smaps + j * q.ncoils * R * 2, o.smaps, q.ncoils * R * sizeof(float2)));
+      EX_HIP(cp(bp.groups[g].y + j * ny, y[m[j]], ny * sizeof(float2)));
+      z0v.v[j % 64] = o.z0;
+      if (j % 64 == 63 || j + 1 == m.size()) {
+        const size_t base = j - j % 64;
+        k_set_vals<<<1, 64, 0, s>>>(bp.z0s[g] + base, z0v, (int)(j - base + 1));
+        EX_LAUNCHED("z0 table");
+      }
+    }
+    FistaGroup &G = bp.groups[g];
+    G.op = &bp.packed[g];
+    G.opts = opts;
+    G.f = f;
+    G.refine = refine;
+    EX_TRY(G.prologue(s));
+  }
+  uint64_t key = 0x9e3779b97f4a7c15ull;
+  key = fnv(key, &nprob, sizeof(nprob));
+  key = fnv(key, ops, sizeof(expenc_op) * (size_t)nprob);
+  key = fnv(key, &batch, sizeof(batch));
+  key = fnv(key, &ws, sizeof(ws));
+  key = fnv(key, &ws_bytes, sizeof(ws_bytes));
+  key = fnv(key, opts, sizeof(*opts));
+  if (opts->n_iter > 0) {
+    EX_TRY(run_graph(key, s, [&](hipStream_t cs) -> int {
+      if (NG == 1) return bp.groups[0].body(cs);
+      int dev = 0;
+      EX_HIP(hipGetDevice(&dev));
+      std::vector<hipEvent_t> ev(NG + 1, nullptr);
+      int rc = EXPENC_OK;
+      for (auto &e : ev)
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = fail(EXPENC_EHIP, "event");
+      if (rc == EXPENC_OK && hipEventRecord(ev[NG], cs) != hipSuccess) rc = fail(EXPENC_EHIP, "fork record");
+      for (int g = 0; g < NG && rc == EXPENC_OK; ++g) {
+        hipStream_t gs = fork_stream(dev, g);
+        if (!gs || hipStreamWaitEvent(gs, ev[NG], 0) != hipSuccess) {
+          rc = fail(EXPENC_EHIP, "fork");
+          break;
+        }
+        rc = bp.groups[g].body(gs);
+        // always join a forked stream back, also after an error, so that a
+        // capture can end cleanly
+        if (hipEventRecord(ev[g], gs) != hipSuccess || hipStreamWaitEvent(cs, ev[g], 0) != hipSuccess)
+          rc = rc ? rc : fail(EXPENC_EHIP, "join");
+      }
+      for (auto &e : ev)
+        if (e) hipEventDestroy(e);
+      return rc;
+    }));
+  }
+  for (int g = 0; g < NG; ++g) {
+    const FistaGroup &G = bp.groups[g];
+    const int K = opts->n_iter;
+    const float2 *xK = (K == 0) ? G.L.x0 : ((K - 1) % 2 == 0 ? G.L.x1 : G.L.x0);
+    const int64_t img = (int64_t)G.L.nxp * G.L.nyp;
+    for (size_t j = 0; j < bp.members[g].size(); ++j) {
+      k_crop<<<(unsigned)ceil_div((int64_t)G.L.p.R * batch, 256), 256, 0, s>>>(
+          xK + j * batch * img, G.L.nxp, G.L.nyp, G.L.p.nx, G.L.p.ny, batch,
+          reinterpret_cast<float2 *>(x[bp.members[g][j]]));
+      EX_LAUNCHED("crop");
+    }
+  }
   return EXPENC_OK;
 }

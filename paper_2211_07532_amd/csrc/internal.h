@@ -70,9 +70,15 @@ struct EncPlan {
   bool sh = false;
   int32_t nxq = 0;                        // padded row length of the pixel index
   double dx = 0, dy = 0, z0 = 0;          // pixel pitch and slice position (metres)
+  // P independent problems of identical shape, each with its own operator
+  // data packed contiguously (coef [P][T][L], time [P][T], dw0 [P][R],
+  // smaps [P][C][R], basis [P][L][R], y [P][B][T][C]) and its own buffers;
+  // every kernel takes the problem index as an extra grid dimension.
+  int32_t P = 1;
+  const double *z0s = nullptr;            // [P] slice positions (SH basis), or NULL: z0 for all
 };
 
-int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p);
+int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p, int32_t nprob = 1);
 
 // Device buffers of one operator application, carved from the workspace.
 struct EncBuffers {
@@ -102,8 +108,10 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part = 0);
 int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s);
 // Z[r][b*C+c] = S_c(r) x_b(r) from x [B][R] (x_stride elements between problems);
 // for split precisions, pre-split and packed in the MFMA operand order.
+// (x_pstride: elements between problems)
 int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x_stride,
-                int32_t x_row_stride, const EncBuffers &b, hipStream_t s, const float2 *xsub = nullptr);
+                int32_t x_row_stride, const EncBuffers &b, hipStream_t s, const float2 *xsub = nullptr,
+                int64_t x_pstride = 0);
 int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // y[b][t][c] = sum_split partials (ABI layout)
 int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s);
@@ -115,9 +123,11 @@ int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // x_row_stride (pixels); alpha = *alpha_dev (device FP64) or 1 if NULL.
 // If base is given (same layout as x) it is added to the sum before scaling:
 // x = add + alpha * (base + sum).
+// alpha_dev, if given, holds one value per problem.
 int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
                            int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
-                           const float2 *add, hipStream_t s, const float2 *base = nullptr);
+                           const float2 *add, hipStream_t s, const float2 *base = nullptr,
+                           int64_t x_pstride = 0);
 // Residual r = A z - y (y_meas [B][T][C], or NULL for r = A z) written
 // straight into the adjoint operand.
 int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s);
@@ -127,7 +137,7 @@ int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hi
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
-                  int32_t x_row_stride, const EncBuffers &b, hipStream_t s);
+                  int32_t x_row_stride, const EncBuffers &b, hipStream_t s, int64_t x_pstride);
 int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, const float2 *y_meas,
                  const EncBuffers &b, hipStream_t s);
 

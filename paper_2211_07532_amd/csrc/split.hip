@@ -178,6 +178,12 @@ __global__ __launch_bounds__(256) void k_fwd_split(const double *__restrict__ ka
   const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
+  const int pz = blockIdx.z;  // problem
+  kap += pz * Tp * NT;
+  bet += (int64_t)pz * Rp * NT;
+  dbet += (int64_t)pz * Rp * NT;
+  zs += (int64_t)pz * Rp * NGP * 16;
+  part += pz * nsplit * Tp * NCP * 2;
   double kv[NT];
   float kf[NT];
 #pragma unroll
@@ -221,6 +227,12 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
   const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
+  const int pz = blockIdx.z;  // problem
+  kap += pz * Tp * NT;
+  dkap += pz * Tp * NT;
+  bet += (int64_t)pz * Rp * NT;
+  ys += pz * Tp * NGP * 16;
+  part += pz * nsplit * (int64_t)Rp * NCP * 2;
   double bv[NT];
   float bf[NT];
 #pragma unroll
@@ -280,6 +292,12 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__
   const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
+  const int pz = blockIdx.z;  // problem
+  pmono += pz * Tp * 12;
+  dwq += (int64_t)pz * Rp;
+  ddw += (int64_t)pz * Rp;
+  zs += (int64_t)pz * Rp * NGP * 16;
+  part += pz * nsplit * Tp * NCP * 2;
   double P[10];
 #pragma unroll
   for (int m = 0; m < 10; ++m) P[m] = pmono[(row0 + lane) * 12 + m];
@@ -341,6 +359,12 @@ __global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__
   const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
+  const int pz = blockIdx.z;  // problem
+  pmono += pz * Tp * 12;
+  dpmono += pz * Tp * 12;
+  dwq += (int64_t)pz * Rp;
+  ys += pz * Tp * NGP * 16;
+  part += pz * nsplit * (int64_t)Rp * NCP * 2;
   const int rq = (int)(row0 + lane);
   const double xm = (rq % nxq - 0.5 * nx) * dx, ym = (rq / nxq - 0.5 * ny) * dy;
   double mono[11];
@@ -435,8 +459,13 @@ __device__ inline void write_record(u32x4 *out, int64_t q, int g, int NGP, int l
 template <bool BF>
 __global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
                                 const float2 *__restrict__ xsub, int64_t x_stride, int x_row_stride, int nx, int ny,
-                                int nxq, int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs) {
+                                int nxq, int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs, int64_t x_pstride) {
   const int R = nx * ny;
+  const int pz = blockIdx.y;  // problem
+  smaps += (int64_t)pz * C * R;
+  x += pz * x_pstride;
+  if (xsub) xsub += pz * x_pstride;
+  zs += (int64_t)pz * Rp * NGP * 16;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (int64_t)(Rp / 16) * NGP * 64) return;
   const int lane = (int)(id & 63);
@@ -476,6 +505,11 @@ __global__ void k_pack_y_split(const float2 *__restrict__ src_abi, const float2 
                                const float2 *__restrict__ y_meas, int64_t T, int64_t Tp, int C, int NC, int NCP,
                                u32x4 *__restrict__ ys) {
   const int NGP = NCP / 16;
+  const int pz = blockIdx.y;  // problem
+  if (src_abi) src_abi += pz * T * NC;
+  if (src_part) src_part += pz * nsplit * Tp * NCP;
+  if (y_meas) y_meas += pz * T * NC;
+  ys += pz * Tp * NGP * 16;
   const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (id >= (Tp / 16) * NGP * 64) return;
   const int lane = (int)(id & 63);
@@ -515,6 +549,8 @@ __global__ void k_pack_y_split(const float2 *__restrict__ src_abi, const float2 
 __global__ void k_tile_diff(const double *__restrict__ src, float *__restrict__ d, int64_t rows, int NT) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows * NT) return;
+  src += blockIdx.y * rows * NT;  // problem
+  d += blockIdx.y * rows * NT;
   const int64_t r = i / NT;
   const int k = (int)(i % NT);
   const int64_t centre = (r & ~int64_t(15)) + 8;
@@ -527,7 +563,7 @@ struct MonoMatrix {
   double m[16][10];
 };
 
-static MonoMatrix mono_matrix(double z) {
+__host__ __device__ inline MonoMatrix mono_matrix(double z) {
   MonoMatrix M{};
   auto &m = M.m;
   m[0][0] = 1;
@@ -549,11 +585,16 @@ static MonoMatrix mono_matrix(double z) {
   return M;
 }
 
-// pmono[t][m] = sum_l kap[t][l] M[l][m] (m < 10), pmono[t][10] = t.
-__global__ void k_prep_pmono(const double *__restrict__ kap, int NT, int L, int64_t Tp, MonoMatrix M,
-                             double *__restrict__ pmono) {
+// pmono[t][m] = sum_l kap[t][l] M[l][m] (m < 10), pmono[t][10] = t; the
+// monomial matrix M comes from the problem's slice position (z0s[p], or M0).
+__global__ void k_prep_pmono(const double *__restrict__ kap, int NT, int L, int64_t Tp, MonoMatrix M0,
+                             const double *__restrict__ z0s, double *__restrict__ pmono) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Tp) return;
+  const int pz = blockIdx.y;
+  kap += pz * Tp * NT;
+  pmono += pz * Tp * 12;
+  MonoMatrix M = z0s ? mono_matrix(z0s[pz]) : M0;
   double out[12];
   for (int m = 0; m < 12; ++m) out[m] = 0.0;
   for (int l = 0; l < L; ++l) {
@@ -568,6 +609,8 @@ __global__ void k_prep_pmono(const double *__restrict__ kap, int NT, int L, int6
 __global__ void k_prep_dwq(const double *__restrict__ dw0, int nx, int ny, int nxq, int Rp, double *__restrict__ dwq) {
   const int rq = blockIdx.x * blockDim.x + threadIdx.x;
   if (rq >= Rp) return;
+  if (dw0) dw0 += (int64_t)blockIdx.y * nx * ny;  // problem
+  dwq += (int64_t)blockIdx.y * Rp;
   const int yy = rq / nxq, xx = rq % nxq;
   double v = 0.0;
   if (dw0 && yy < ny && xx < nx) v = dw0[yy * nx + xx] * 0.15915494309189533576888376337251436;
@@ -575,20 +618,21 @@ __global__ void k_prep_dwq(const double *__restrict__ dw0, int nx, int ny, int n
 }
 
 int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
+  auto gp = [&](int64_t n) { return dim3((unsigned)ceil_div(n, 256), (unsigned)p.P); };
   if (p.sh) {
-    k_prep_pmono<<<(unsigned)ceil_div(p.Tp, 256), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), b.pmono);
+    k_prep_pmono<<<gp(p.Tp), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), p.z0s, b.pmono);
     EX_LAUNCHED("monomial coefficients");
-    k_tile_diff<<<(unsigned)ceil_div(p.Tp * 12, 256), 256, 0, s>>>(b.pmono, b.dpmono, p.Tp, 12);
+    k_tile_diff<<<gp(p.Tp * 12), 256, 0, s>>>(b.pmono, b.dpmono, p.Tp, 12);
     EX_LAUNCHED("tile differences (samples)");
-    k_prep_dwq<<<(unsigned)ceil_div(p.Rp, 256), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);
+    k_prep_dwq<<<gp(p.Rp), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);
     EX_LAUNCHED("off-resonance layout");
-    k_tile_diff<<<(unsigned)ceil_div(p.Rp, 256), 256, 0, s>>>(b.dwq, b.ddw, p.Rp, 1);
+    k_tile_diff<<<gp(p.Rp), 256, 0, s>>>(b.dwq, b.ddw, p.Rp, 1);
     EX_LAUNCHED("tile differences (pixels)");
     return EXPENC_OK;
   }
-  k_tile_diff<<<(unsigned)ceil_div((int64_t)p.Rp * p.NT, 256), 256, 0, s>>>(b.bet, b.dbet, p.Rp, p.NT);
+  k_tile_diff<<<gp((int64_t)p.Rp * p.NT), 256, 0, s>>>(b.bet, b.dbet, p.Rp, p.NT);
   EX_LAUNCHED("tile differences (pixels)");
-  k_tile_diff<<<(unsigned)ceil_div(p.Tp * p.NT, 256), 256, 0, s>>>(b.kap, b.dkap, p.Tp, p.NT);
+  k_tile_diff<<<gp(p.Tp * p.NT), 256, 0, s>>>(b.kap, b.dkap, p.Tp, p.NT);
   EX_LAUNCHED("tile differences (samples)");
   return EXPENC_OK;
 }
@@ -599,7 +643,7 @@ int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hi
 
 template <int NT, bool BF>
 static void launch_fwd_split(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY);
+  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
   if (p.GW == 2)
@@ -612,7 +656,7 @@ static void launch_fwd_split(const EncPlan &p, const EncBuffers &b, hipStream_t 
 
 template <int NT, bool BF>
 static void launch_adj_split(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY);
+  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
   if (p.GW == 2)
@@ -643,7 +687,7 @@ static void adj_split_nt(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 template <bool BF>
 static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY);
+  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
   if (p.GW == 2)
@@ -656,7 +700,7 @@ static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 template <bool BF>
 static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY);
+  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
   if (p.GW == 2)
@@ -690,18 +734,18 @@ void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) 
 }
 
 int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
-                  int32_t x_row_stride, const EncBuffers &b, hipStream_t s) {
+                  int32_t x_row_stride, const EncBuffers &b, hipStream_t s, int64_t x_pstride) {
   const int NGP = p.NCP / 16;
   const int64_t n = (int64_t)(p.Rp / 16) * NGP * 64;
-  const unsigned nb = (unsigned)ceil_div(n, 256);
+  const dim3 nb((unsigned)ceil_div(n, 256), (unsigned)p.P);
   const float2 *sm = reinterpret_cast<const float2 *>(smaps);
   u32x4 *zs = reinterpret_cast<u32x4 *>(b.zs);
   if (p.prec == EXPENC_BF16_SPLIT)
     k_build_z_split<true><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
-                                             p.NC, NGP, zs);
+                                             p.NC, NGP, zs, x_pstride);
   else
     k_build_z_split<false><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
-                                              p.NC, NGP, zs);
+                                              p.NC, NGP, zs, x_pstride);
   EX_LAUNCHED("build_z split");
   return EXPENC_OK;
 }
@@ -710,7 +754,7 @@ int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, cons
                  const EncBuffers &b, hipStream_t s) {
   const int NGP = p.NCP / 16;
   const int64_t n = (p.Tp / 16) * NGP * 64;
-  const unsigned nb = (unsigned)ceil_div(n, 256);
+  const dim3 nb((unsigned)ceil_div(n, 256), (unsigned)p.P);
   u32x4 *ys = reinterpret_cast<u32x4 *>(b.ys);
   const float2 *part = from_partials ? b.part : nullptr;
   if (p.prec == EXPENC_BF16_SPLIT)

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
-from typing import Optional
+from typing import Optional, Sequence
 
 import torch
 
@@ -232,6 +232,49 @@ def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4"
     else:
         res = FistaResult(x[0] if single else x, float("nan"), [], [], obj)
     return res
+
+
+_batch_ws = {}
+
+
+def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: int, levels: int, wavelet="db4",
+                  precision="fp32", lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3,
+                  power_v0=None, n_power: int = 30, ista: bool = False, refine_every: int = 0):
+    """Independent FISTA solves of problems (ys[i], ops[i]) in one call (see
+    fista_solve_batched in include/expenc.h).  Every ys[i] is [T_i][C_i] (or
+    [B][T_i][C_i] with one B for all).  Returns the list of x_i."""
+    if len(ys) != len(ops) or not ops:
+        raise ValueError("need one y per operator")
+    dev = ops[0].device
+    single = ys[0].dim() == 2
+    batch = 1 if single else ys[0].shape[0]
+    ybs, xs = [], []
+    for y, op in zip(ys, ops):
+        yb = y.reshape(batch, op.nsamples, op.ncoils)
+        _need(yb, torch.complex64, "y", dev)
+        ybs.append(yb)
+        xs.append(torch.empty((batch, op.ny, op.nx), dtype=torch.complex64, device=dev))
+    if lipschitz <= 0 and power_v0 is None:
+        raise ValueError("lipschitz <= 0 needs power_v0 (the seeded start vector)")
+    opts = _b.FistaOpts(n_iter, _prec(precision), _wav(wavelet), levels, 0, 0, int(ista), refine_every,
+                        n_power, 0, float(lipschitz), float(lam), float(lambda_factor),
+                        None if power_v0 is None else _need(power_v0, torch.complex64, "power_v0", dev).data_ptr(),
+                        None, None)
+    n = len(ops)
+    carr = (_b.ExpencOp * n)(*[op._c for op in ops])
+    yp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ybs])
+    xp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in xs])
+    need = _b.lib().fista_batched_workspace_size(n, carr, batch, ctypes.byref(opts))
+    if need == 0:
+        raise _b.ExpencError(_b.EXPENC_EINVAL, "fista_batched_workspace_size")
+    ws = _batch_ws.get(dev)
+    if ws is None or ws.numel() < need:
+        _batch_ws.pop(dev, None)
+        ws = torch.empty(need, dtype=torch.uint8, device=dev)
+        _batch_ws[dev] = ws
+    check(_b.lib().fista_solve_batched(n, carr, batch, yp, xp, ctypes.byref(opts), _ptr(ws), ws.numel(),
+                                       _stream(dev)), "fista_solve_batched")
+    return [x[0] if single else x for x in xs]
 
 
 def cg(y: torch.Tensor, op: Operator, n_iter: int, precision="fp32") -> torch.Tensor:

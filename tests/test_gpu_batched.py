@@ -1,0 +1,151 @@
+"""GPU parity of the batched solve (fista_solve_batched): many independent
+problems of mixed sizes, fields, coil maps and slice positions in one call.
+
+* small mixed batches: every size class's first problem against the FP64
+  oracle's FISTA (L from the oracle's power iteration on the same start
+  vector, lambda by the same rule), every problem against the single-problem
+  entry point on the same inputs (a consistency check of the grouping);
+* full size: the 1.5 mm problem solved inside a batch (grouped with a second
+  148 px problem, beside a 170 px group) against the stored FP64 oracle
+  reconstruction.
+Bars: NRMSE <= 1e-5 (FP32 form), <= 1e-4 (split forms), L and lambda 1e-5."""
+import dataclasses
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import solve
+from tests.gpu_common import Case, c64, rel
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "mm15_fista.npz")
+
+
+def _ee():
+    import paper_2211_07532_amd as ee
+    return ee
+
+
+def _mixed_workloads(n_per=2, n_iter=10, levels=2):
+    # three size classes with T ~ 3 N^2 / R, per-problem seeds and slice positions
+    sizes = ((20, 4.0), (24, 5.0), (28, 6.0))
+    zs = (-0.003, 0.0, 0.003)
+    out = []
+    for k in range(3 * n_per):
+        n, accel = sizes[k % 3]
+        t = int(round(3 * n * n / accel))
+        out.append(synth.Workload(f"mix-{k}", n, 0.222, 6, t, 2e-6, accel, 16, 100.0, 15.0, n_iter, "db4",
+                                  levels, 500 + k, z0=zs[(k // 3) % 3]))
+    return out
+
+
+def _oracle_op(case):
+    return solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, case.w.n)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_mixed_batch_matches_oracle_and_single_solves(prec):
+    ee = _ee()
+    ws = _mixed_workloads()
+    cases = [Case(w, sh=True) for w in ws]
+    ops = [_oracle_op(c) for c in cases]
+    ys = [c64(o.A(c.x_noisy)) for o, c in zip(ops, cases)]
+    rmax = max(w.npix for w in ws)
+    v0 = c64(synth.power_start(rmax, 11))
+    n_power = 25
+    print(f"[case] batched {prec}: {len(ws)} problems, sizes {[w.n for w in ws]}", flush=True)
+    xs = ee.fista_batched([c.to_dev(y) for c, y in zip(cases, ys)], [c.op for c in cases], ws[0].n_iter,
+                          ws[0].levels, "db4", precision=prec, lipschitz=0.0, power_v0=cases[0].to_dev(v0),
+                          n_power=n_power, lam=-1.0, lambda_factor=1e-3)
+    bar = 1e-5 if prec == "fp32" else 1e-4
+    for k in range(3):  # one oracle solve per size class
+        w, op, y = ws[k], ops[k], ys[k]
+        L = solve.power_lipschitz(op, v0[:w.npix], n_power)
+        lam = solve.lambda_rule(op, y)
+        ref = solve.fista(op, y, L, lam, w.n_iter, w.levels, w.wavelet, w.n_pad)
+        e = solve.nrmse(xs[k].cpu().numpy().reshape(-1), ref)
+        print(f"  problem {k} (n={w.n}): NRMSE vs oracle {e:.2e}", flush=True)
+        assert e <= bar
+    for k, (c, y) in enumerate(zip(cases, ys)):
+        single = ee.fista(c.to_dev(y), c.op, ws[k].n_iter, ws[k].levels, "db4", precision=prec, lipschitz=0.0,
+                          power_v0=c.to_dev(v0[:ws[k].npix]), n_power=n_power, lam=-1.0, lambda_factor=1e-3)
+        e = rel(xs[k].cpu().numpy(), single.x.cpu().numpy())
+        print(f"  problem {k}: batched vs single {e:.2e}", flush=True)
+        assert e <= bar
+
+
+def test_batched_fixed_scalars_and_repeat_is_bitwise():
+    ee = _ee()
+    ws = _mixed_workloads(n_per=1, n_iter=6)
+    cases = [Case(w, sh=False) for w in ws]
+    ops = [_oracle_op(c) for c in cases]
+    ys = [c64(o.A(c.x_noisy)) for o, c in zip(ops, cases)]
+    # one L that bounds every problem's Lipschitz constant, one fixed lambda
+    L = 1.05 * max(solve.power_lipschitz(o, c64(synth.power_start(w.npix, 12)), 20) for o, w in zip(ops, ws))
+    lam = 2e-3
+    args = ([c.to_dev(y) for c, y in zip(cases, ys)], [c.op for c in cases], 6, 2, "db4")
+    xs = ee.fista_batched(*args, lipschitz=L, lam=lam)
+    for k in range(3):
+        ref = solve.fista(ops[k], ys[k], L, lam, 6, 2, "db4", ws[k].n_pad)
+        assert solve.nrmse(xs[k].cpu().numpy().reshape(-1), ref) <= 1e-5
+    # the second call replays the cached graph
+    xs2 = ee.fista_batched(*args, lipschitz=L, lam=lam)
+    for a, b in zip(xs, xs2):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+
+
+def test_batched_rejects_bad_arguments():
+    import ctypes
+    import torch
+    from paper_2211_07532_amd import _binding as b
+    ee = _ee()
+    w = _mixed_workloads(n_per=1)[0]
+    c = Case(w, sh=True)
+    y = torch.zeros((w.nsamples, 6), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError):
+        ee.fista_batched([y], [c.op], 2, 2, lipschitz=0.0)      # no power start vector
+    opts = b.FistaOpts(2, 0, 1, 2, 24, 24, 0, 0, 0, 0, 1.0, 1.0, 0.0, None, None, None)
+    arr = (b.ExpencOp * 1)(c.op._c)
+    assert b.lib().fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) == 0  # padding is per problem
+    opts.nx_pad = opts.ny_pad = 0
+    assert b.lib().fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) > 0
+    yp = (ctypes.c_void_p * 1)(y.data_ptr())
+    xp = (ctypes.c_void_p * 1)(None)
+    st = b.lib().fista_solve_batched(1, arr, 1, yp, xp, ctypes.byref(opts), None, 0, None)
+    assert st == b.EXPENC_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_full_size_problem_inside_batch_matches_golden(prec):
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py")
+    import torch
+    ee = _ee()
+    g = np.load(GOLDEN)
+    w = synth.MM15
+    main = Case(w, sh=True)
+    y = c64(solve.Operator(main.smaps, main.coef, main.time, main.basis_np, main.dw0, w.n).A(main.x_noisy))
+    # batch partners: a second 148 px problem (same group) and a 170 px one
+    bw = synth.batch_workloads(n_slices=1, n_vol=3)
+    partners = [Case(dataclasses.replace(bw[0], n_iter=w.n_iter), sh=True),
+                Case(dataclasses.replace(bw[1], n_iter=w.n_iter), sh=True)]
+    yps = [ee.forward(p.to_dev(p.x_noisy), p.op) for p in partners]
+    v0 = c64(synth.power_start(max(p.w.npix for p in partners + [main]), int(g["power_seed"])))
+    v0[:w.npix] = c64(synth.power_start(w.npix, int(g["power_seed"])))
+    print(f"[case] full-size batch {prec}: 148 (golden) + 148 + 170", flush=True)
+    xs = ee.fista_batched([main.to_dev(y)] + yps, [main.op] + [p.op for p in partners], w.n_iter, w.levels,
+                          w.wavelet, precision=prec, lipschitz=0.0, power_v0=main.to_dev(v0),
+                          n_power=int(g["n_power"]), lam=-1.0, lambda_factor=1e-3)
+    torch.cuda.synchronize()
+    e = solve.nrmse(xs[0].cpu().numpy().reshape(-1), g["x_hat"])
+    print(f"  golden NRMSE {e:.2e}", flush=True)
+    assert e <= (1e-5 if prec == "fp32" else 1e-4)
+    for p, yp, x in zip(partners, yps, xs[1:]):
+        single = ee.fista(yp, p.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0,
+                          power_v0=main.to_dev(v0[:p.w.npix]), n_power=int(g["n_power"]), lam=-1.0,
+                          lambda_factor=1e-3)
+        e2 = rel(x.cpu().numpy(), single.x.cpu().numpy())
+        print(f"  partner n={p.w.n}: batched vs single {e2:.2e}", flush=True)
+        assert e2 <= (1e-5 if prec == "fp32" else 1e-4)
