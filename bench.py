@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import dataclasses
 import json
 import os
 import sys
@@ -40,6 +41,10 @@ def parse():
     ap.add_argument("--precision", default="all", choices=["all", "fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
+    ap.add_argument("--batch-nprob", type=int, default=36,
+                    help="problems of the mixed-size batch measured beside the headline (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in launch shapes")
     return ap.parse_args()
 
 
@@ -56,6 +61,70 @@ def cpu_baseline(w, prob, basis):
             "cores": int(os.environ.get("ORACLE_THREADS", os.cpu_count() or 1)), "kind": "oracle",
             "sample": f"one A_exp and one A_exp^H application of the {w.name} operator "
                       f"({2 * cmac:.3e} CMAC, {dt:.1f} s)"}
+
+
+def run_batch(args, prec, ee, torch):
+    """The mixed-size batch (148 px / R=4, 170 px / R=5, 200 px / R=6 in turn,
+    per-problem fields, dB0, coil maps and slice positions; 100 FISTA
+    iterations each with db4 J=3, L by power iteration, lambda rule), solved
+    by one fista_solve_batched call and by a loop of fista_solve calls."""
+    from paper_2211_07532_amd import autotune
+    dev = torch.device("cuda:0")
+    ws = synth.batch_workloads()[: args.batch_nprob]
+    ops, ys = [], []
+    for w in ws:
+        p = synth.make_problem(w)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+        op = ee.Operator(w.n, w.n, t(p.smaps.astype(np.complex64)), t(p.coef), t(p.time), None, t(p.dw0),
+                         sh_grid=(w.fov, w.fov, w.z0))
+        ops.append(op)
+        ys.append(ee.forward(t(p.x_noisy.astype(np.complex64)), op))
+    tuning = {}
+    if not args.no_tune:
+        for op, w in zip(ops, ws):
+            if w.n in tuning:
+                continue
+            forms = ["fp32"] + ([prec] if prec != "fp32" else [])
+            tuning[w.n] = {f: dataclasses.asdict(autotune.tune(op, 1, f)) for f in forms}
+            for f in forms:
+                tuning[w.n][f].pop("timings", None)
+    v0 = torch.from_numpy(synth.power_start(max(w.npix for w in ws), 7).astype(np.complex64)).to(dev)
+    K, J, wav = ws[0].n_iter, ws[0].levels, ws[0].wavelet
+    kw = dict(precision=prec, lipschitz=0.0, power_v0=v0, n_power=N_POWER, lam=-1.0, lambda_factor=1e-3)
+
+    def batched():
+        return ee.fista_batched(ys, ops, K, J, wav, **kw)
+
+    def looped():
+        out = []
+        for y, op in zip(ys, ops):
+            k1 = dict(kw, power_v0=v0[:op.npix])
+            out.append(ee.fista(y, op, K, J, wav, sync_scalars=False, **k1).x)
+        return out
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.batch_steps, r
+
+    tb, xb = timed(batched)
+    tl, xl = timed(looped)
+    diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xb, xl))
+    apps = 2 * K + (2 * N_POWER + 1) + 1
+    cmac = sum(w.nsamples * w.npix * w.ncoils for w in ws) * apps
+    sizes = {}
+    for w in ws:
+        sizes[f"{w.n}px/T={w.nsamples}"] = sizes.get(f"{w.n}px/T={w.nsamples}", 0) + 1
+    return {"problems": len(ws), "sizes": sizes, "coils": ws[0].ncoils, "fista_iters": K,
+            "wavelet": f"{wav} J={J}", "dtype": FORMS[prec],
+            "recon_per_s_batched": round(len(ws) / tb, 3), "recon_per_s_looped": round(len(ws) / tl, 3),
+            "speedup_vs_looped": round(tl / tb, 3), "gcmac_per_s_batched": round(cmac / tb / 1e9, 2),
+            "s_per_batch": round(tb, 3), "s_per_loop": round(tl, 3),
+            "batched_vs_looped_max_rel_diff": float(f"{diff:.3e}"), "tuning": tuning}
 
 
 FORMS = {"fp32": "f32", "bf16": "bf16-split", "fp16": "f16-split"}
@@ -92,6 +161,16 @@ def main():
     forms = [args.precision] if args.precision != "all" else list(FORMS)
     out = {}
     for prec in forms:
+        tuning = None
+        if not args.no_tune:
+            # launch shapes from the project autotuner (cached per device and geometry);
+            # the split forms' FP32 anchors use the FP32 plan
+            from paper_2211_07532_amd import autotune
+            for f in (["fp32"] if prec != "fp32" else []) + [prec]:
+                r = autotune.tune(op, 1, f)
+            tuning = {"fwd_target": r.fwd_target, "adj_target": r.adj_target, "cached": r.cached,
+                      **autotune.plan_info(op, 1, prec)}
+
         def step():
             return ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
                             n_power=N_POWER, lam=-1.0, lambda_factor=1e-3, sync_scalars=False)
@@ -137,6 +216,7 @@ def main():
             "gcmac_per_s": round(apps * cmac / dt / 1e9, 2), "ms_per_step": round(dt * 1e3, 3),
             "fista_iter_per_s": round(it_s, 2), "nrmse_vs_fp64": None if nrmse is None else float(f"{nrmse:.3e}"),
             "kernel_ms": {"forward_contraction": round(fwd_ms, 4), "adjoint_contraction": round(adj_ms, 4)},
+            "launch_shape": tuning,
             "roofline": {"bound": "mfma", "kernel": ("forward" if fwd_ms >= adj_ms else "adjoint") + " contraction",
                          "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
                          "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": None},
@@ -169,6 +249,8 @@ def main():
     }
     if "fp32" in out and head != "fp32":
         line["split_vs_fp32_fista_iter_ratio"] = round(h["fista_iter_per_s"] / out["fp32"]["fista_iter_per_s"], 3)
+    if args.batch_nprob > 0:
+        line["batch"] = run_batch(args, head, ee, torch)
     if not args.no_cpu_baseline:
         from oracle import encoding
         line["cpu_baseline"] = cpu_baseline(w, prob, encoding.sh_basis(w.n, w.fov, w.z0, w.nbasis))

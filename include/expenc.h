@@ -268,6 +268,30 @@ int cg_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
              const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Launch-shape tuning (not part of the method).  The contraction kernels
+ * split their reduction (pixels for A, samples for A^H) so that one launch
+ * has about `target` workgroups (default 2048, or the EXPENC_TARGET_WG
+ * environment variable).  expenc_set_tuning sets the forward and adjoint
+ * targets for every later plan of op's geometry (nx, ny, ncoils, nbasis,
+ * nsamples, basis_kind) at this batch and precision; 0 restores the default
+ * for that direction, both 0 remove the entry.  A batched solve of P such
+ * problems uses the same totals across its P problems.  Later calls plan
+ * with the new targets (workspace sizes may change: query them again).
+ * Process-wide and thread-safe; changing it while a call is being issued on
+ * another thread leaves that call on either setting.
+ */
+int expenc_set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target,
+                      int32_t adj_target);
+
+/*
+ * The launch shape a call would use for nprob problems of op's geometry:
+ * out[0] = forward split, out[1] = adjoint split, out[2] / out[3] = forward /
+ * adjoint workgroups per launch, out[4] / out[5] = largest forward / adjoint
+ * split (host array of 6).
+ */
+int expenc_plan_info(const expenc_op *op, int32_t batch, int32_t precision, int32_t nprob, int64_t *out);
+
+/*
  * Profiling aid (not part of the method): per-kernel timing of the two
  * contraction kernels with HIP events recorded on their launch stream around
  * every eager launch (launches captured into a graph are not timed).

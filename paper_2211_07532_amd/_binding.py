@@ -76,6 +76,9 @@ SIGNATURES = {
     "fista_solve_batched": (ctypes.c_int, [_c_int, ctypes.POINTER(ExpencOp), _c_int, ctypes.POINTER(_vp),
                                            ctypes.POINTER(_vp), ctypes.POINTER(FistaOpts), _vp, ctypes.c_size_t,
                                            _vp]),
+    "expenc_set_tuning": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int, _c_int]),
+    "expenc_plan_info": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int,
+                                        ctypes.POINTER(ctypes.c_int64)]),
     "expenc_kernel_timing": (ctypes.c_int, [_c_int, ctypes.POINTER(ctypes.c_double)]),
     "expenc_last_error": (ctypes.c_char_p, []),
 }

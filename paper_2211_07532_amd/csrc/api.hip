@@ -335,3 +335,24 @@ extern "C" int expenc_lipschitz(const expenc_op *op, int32_t precision, int32_t 
 }
 
 extern "C" int expenc_kernel_timing(int32_t mode, double *out) { return kernel_timing(mode, out); }
+
+extern "C" int expenc_set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target,
+                                 int32_t adj_target) {
+  EncPlan chk;
+  EX_TRY(make_plan(op, batch, precision, &chk));
+  return set_tuning(op, batch, precision, fwd_target, adj_target);
+}
+
+extern "C" int expenc_plan_info(const expenc_op *op, int32_t batch, int32_t precision, int32_t nprob,
+                                int64_t *out) {
+  if (!out) return fail(EXPENC_EINVAL, "out is NULL");
+  EncPlan p;
+  EX_TRY(make_plan(op, batch, precision, &p, nprob));
+  out[0] = p.fwd_split;
+  out[1] = p.adj_split;
+  out[2] = (int64_t)p.Tp / 256 * p.fwd_split * p.NGY * p.P;  // forward workgroups per launch
+  out[3] = (int64_t)p.Rp / 256 * p.adj_split * p.NGY * p.P;  // adjoint workgroups per launch
+  out[4] = p.Rp / 16;                                         // largest forward split
+  out[5] = p.Tp / 16;                                         // largest adjoint split
+  return EXPENC_OK;
+}

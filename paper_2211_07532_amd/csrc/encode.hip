@@ -23,6 +23,7 @@
 // [Yr|Yi] in one accumulator.  The reduction index is split across
 // workgroups (split-K); partial sums are added in fixed order afterwards,
 // so results are bitwise reproducible.
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <mutex>
@@ -453,6 +454,53 @@ static int target_workgroups() {
   return v;
 }
 
+// Workgroup targets per operator geometry, batch and precision, set by the
+// autotuner through expenc_set_tuning.  Plans made after a change differ, so
+// the generation counter is part of every graph-cache key.
+struct TuneEntry {
+  int32_t nx, ny, ncoils, nbasis, basis_kind, batch, precision;
+  int64_t nsamples;
+  int32_t fwd_target, adj_target;
+};
+static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+static std::atomic<uint64_t> g_tune_gen{0};
+
+uint64_t tuning_generation() { return g_tune_gen.load(); }
+
+static bool tune_match(const TuneEntry &e, const expenc_op *op, int32_t batch, int32_t precision) {
+  return e.nx == op->nx && e.ny == op->ny && e.ncoils == op->ncoils && e.nbasis == op->nbasis &&
+         e.basis_kind == op->basis_kind && e.batch == batch && e.precision == precision &&
+         e.nsamples == op->nsamples;
+}
+
+static void tuned_targets(const expenc_op *op, int32_t batch, int32_t precision, int *fwd, int *adj) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const TuneEntry &e : g_tune)
+    if (tune_match(e, op, batch, precision)) {
+      if (e.fwd_target > 0) *fwd = e.fwd_target;
+      if (e.adj_target > 0) *adj = e.adj_target;
+      return;
+    }
+}
+
+int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target) {
+  if (!op) return fail(EXPENC_EINVAL, "operator descriptor is NULL");
+  if (fwd_target < 0 || adj_target < 0 || fwd_target > (1 << 20) || adj_target > (1 << 20))
+    return fail(EXPENC_EINVAL, "workgroup targets must be in [0, 2^20]");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (size_t i = 0; i < g_tune.size(); ++i)
+    if (tune_match(g_tune[i], op, batch, precision)) {
+      g_tune.erase(g_tune.begin() + i);
+      break;
+    }
+  if (fwd_target > 0 || adj_target > 0)
+    g_tune.push_back(TuneEntry{op->nx, op->ny, op->ncoils, op->nbasis, op->basis_kind, batch, precision,
+                               op->nsamples, fwd_target, adj_target});
+  g_tune_gen.fetch_add(1);
+  return EXPENC_OK;
+}
+
 int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p, int32_t nprob) {
   if (!op) return fail(EXPENC_EINVAL, "operator descriptor is NULL");
   if (op->nx < 1 || op->ny < 1) return fail(EXPENC_EINVAL, "image grid %dx%d is empty", op->nx, op->ny);
@@ -499,11 +547,12 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.prec = precision;
   q.has_dw0 = op->dw0 != nullptr;
   q.P = nprob;
-  const int tgt = target_workgroups();
+  int tgt_fwd = target_workgroups(), tgt_adj = tgt_fwd;
+  tuned_targets(op, batch, precision, &tgt_fwd, &tgt_adj);
   // forward: 256 sample rows per workgroup, split over pixels
   {
     int64_t nrb = q.Tp / 256 * q.P;
-    int64_t want = ceil_div(tgt, nrb * q.NGY);
+    int64_t want = ceil_div(tgt_fwd, nrb * q.NGY);
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Rp / 16));
     q.fwd_chunk = (int32_t)round_up(ceil_div(q.Rp, want), 16);
     q.fwd_split = (int32_t)ceil_div(q.Rp, q.fwd_chunk);
@@ -511,7 +560,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   // adjoint: 256 pixel rows per workgroup, split over samples
   {
     int64_t nrb = q.Rp / 256 * q.P;
-    int64_t want = ceil_div(tgt, nrb * q.NGY);
+    int64_t want = ceil_div(tgt_adj, nrb * q.NGY);
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Tp / 16));
     q.adj_chunk = (int32_t)round_up(ceil_div(q.Tp, want), 16);
     q.adj_split = (int32_t)ceil_div(q.Tp, q.adj_chunk);

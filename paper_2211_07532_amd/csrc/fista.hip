@@ -173,7 +173,7 @@ struct GraphEntry {
 };
 static std::mutex g_graph_mu;
 static std::vector<GraphEntry> g_graphs;
-static constexpr size_t kGraphCacheMax = 16;
+static constexpr size_t kGraphCacheMax = 64;
 
 static uint64_t fnv(uint64_t h, const void *p, size_t n) {
   const unsigned char *c = static_cast<const unsigned char *>(p);
@@ -491,6 +491,8 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
   key = fnv(key, &ws, sizeof(ws));
   key = fnv(key, &ws_bytes, sizeof(ws_bytes));
   key = fnv(key, opts, sizeof(*opts));
+  const uint64_t gen = tuning_generation();
+  key = fnv(key, &gen, sizeof(gen));
   if (opts->n_iter > 0) EX_TRY(run_graph(key, s, [&](hipStream_t cs) { return G.body(cs); }));
   EX_TRY(G.epilogue(reinterpret_cast<float2 *>(x), s));
   if (opts->scalars) {
@@ -586,6 +588,8 @@ extern "C" int cg_solve(const expenc_op *op, int32_t batch, const float *y, floa
   key = fnv(key, &ws_bytes, sizeof(ws_bytes));
   key = fnv(key, &opts->n_iter, sizeof(opts->n_iter));
   key = fnv(key, &opts->precision, sizeof(opts->precision));
+  const uint64_t gen = tuning_generation();
+  key = fnv(key, &gen, sizeof(gen));
   if (opts->n_iter > 0) EX_TRY(run_graph(key, s, body));
   EX_TRY(copy_f2(L.xv, reinterpret_cast<float2 *>(x), n * B, s));
   return EXPENC_OK;
@@ -748,13 +752,15 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
     G.refine = refine;
     EX_TRY(G.prologue(s));
   }
-  uint64_t key = 0x9e3779b97f4a7c15ull;
+  uint64_t key = 0x84222325cbf29ce4ull;
   key = fnv(key, &nprob, sizeof(nprob));
   key = fnv(key, ops, sizeof(expenc_op) * (size_t)nprob);
   key = fnv(key, &batch, sizeof(batch));
   key = fnv(key, &ws, sizeof(ws));
   key = fnv(key, &ws_bytes, sizeof(ws_bytes));
   key = fnv(key, opts, sizeof(*opts));
+  const uint64_t gen = tuning_generation();
+  key = fnv(key, &gen, sizeof(gen));
   if (opts->n_iter > 0) {
     EX_TRY(run_graph(key, s, [&](hipStream_t cs) -> int {
       if (NG == 1) return bp.groups[0].body(cs);

@@ -100,6 +100,9 @@ struct EncBuffers {
 size_t enc_operand_bytes(const EncPlan &p);
 // Split-K partial-sum elements (float2) a plan needs.
 size_t enc_part_elems(const EncPlan &p);
+// Autotuner overrides of the contraction workgroup targets (0 = default).
+int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target);
+uint64_t tuning_generation();
 // Carves the buffers of plan p; the partial-sum buffer gets at least
 // min_part float2 elements (so a second plan can share it).
 int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part = 0);

@@ -1,0 +1,111 @@
+"""Host-side checks of the C-ABI library (no GPU needed): the library loads,
+exports every function include/expenc.h declares, the Python binding knows
+each of them, and the calls that only validate arguments or plan launch
+shapes behave as documented (status codes, error text, tuning overrides)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "expenc.h")
+
+
+def _lib():
+    from paper_2211_07532_amd import _binding as b
+    if not os.path.exists(b.path()):
+        from paper_2211_07532_amd import build
+        build.build()
+    return b, b.lib()
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"typedef struct[^;]*?\{.*?\}[^;]*;", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names) - {"defined"})
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for n in ("expenc_forward", "expenc_adjoint", "wavelet_fwd", "wavelet_inv", "soft_threshold", "fista_solve",
+              "fista_solve_batched", "expenc_field_grad", "expenc_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    b, lib = _lib()
+    names = _declared()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    unbound = [n for n in names if n not in b.SIGNATURES]
+    assert not unbound, unbound
+
+
+def _op(b, n=148, c=32, t=16384, nb=16):
+    op = b.ExpencOp()
+    op.nx = op.ny = n
+    op.ncoils, op.nbasis, op.nsamples = c, nb, t
+    op.coef = op.time = op.smaps = 0x1000    # never dereferenced by the planning calls
+    op.basis_kind = b.BASIS_SH
+    op.fov_x = op.fov_y = 0.222
+    return op
+
+
+def _info(b, lib, op, batch=1, prec=0, nprob=1):
+    out = (ctypes.c_int64 * 6)()
+    assert lib.expenc_plan_info(ctypes.byref(op), batch, prec, nprob, out) == b.EXPENC_OK
+    return list(out)
+
+
+def test_argument_errors_return_status_and_text():
+    b, lib = _lib()
+    assert lib.expenc_forward(None, 1, 0, None, None, None, 0, None) == b.EXPENC_EINVAL
+    assert b"NULL" in lib.expenc_last_error()
+    op = _op(b)
+    op.nbasis = 17
+    assert lib.expenc_workspace_size(ctypes.byref(op), 1, 0, 0, 0, 0) == 0
+    op = _op(b)
+    op.reserved = 1
+    assert lib.expenc_set_tuning(ctypes.byref(op), 1, 0, 0, 0) == b.EXPENC_EINVAL
+    op = _op(b)
+    assert lib.expenc_set_tuning(ctypes.byref(op), 1, 0, -1, 0) == b.EXPENC_EINVAL
+    assert lib.expenc_plan_info(ctypes.byref(op), 1, 7, 1, (ctypes.c_int64 * 6)()) == b.EXPENC_EINVAL
+    # batched: per-problem padding only, no objective trace
+    opts = b.FistaOpts(2, 0, 1, 2, 152, 152, 0, 0, 0, 0, 1.0, 1.0, 0.0, None, None, None)
+    arr = (b.ExpencOp * 2)(op, _op(b, 170, 32, 17340))
+    assert lib.fista_batched_workspace_size(2, arr, 1, ctypes.byref(opts)) == 0
+    opts.nx_pad = opts.ny_pad = 0
+    one = lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts))
+    two = lib.fista_batched_workspace_size(2, arr, 1, ctypes.byref(opts))
+    assert 0 < one < two
+    opts.objective = 0x1000
+    assert lib.fista_batched_workspace_size(2, arr, 1, ctypes.byref(opts)) == 0
+
+
+def test_tuning_targets_shape_the_split():
+    b, lib = _lib()
+    op = _op(b)
+    base = _info(b, lib, op)
+    fs, as_, fw, aw, fmax, amax = base
+    # default target: about 2048 workgroups per launch (chunks are rounded up
+    # to 16 rows, which can drop a split)
+    assert fw >= 0.9 * 2048 and aw >= 0.9 * 2048
+    assert 1 <= fs <= fmax and 1 <= as_ <= amax
+    try:
+        assert lib.expenc_set_tuning(ctypes.byref(op), 1, 0, 4096, 1024) == b.EXPENC_OK
+        f2, a2, fw2, aw2, _, _ = _info(b, lib, op)
+        assert fw2 >= 0.9 * 4096 and f2 > fs
+        assert aw2 >= 0.9 * 1024 and a2 < as_
+        # other batch sizes and precisions keep their own (default) plans
+        assert _info(b, lib, op, batch=2)[:2] != [f2, a2]
+        # P problems share the totals: fewer splits per problem, similar workgroups
+        fp, ap, fwp, awp, _, _ = _info(b, lib, op, nprob=8)
+        assert fp <= f2 and ap <= a2 and fwp >= 0.9 * 4096 and awp >= 0.9 * 1024
+        # a workspace sized after the change reflects the new partial-sum buffers
+        assert lib.expenc_workspace_size(ctypes.byref(op), 1, 0, 0, 0, 0) > 0
+    finally:
+        assert lib.expenc_set_tuning(ctypes.byref(op), 1, 0, 0, 0) == b.EXPENC_OK
+    assert _info(b, lib, op) == base
