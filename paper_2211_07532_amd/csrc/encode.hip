@@ -562,7 +562,8 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
     int64_t nrb = q.Rp / 256 * q.P;
     int64_t want = ceil_div(tgt_adj, nrb * q.NGY);
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Tp / 16));
-    q.adj_chunk = (int32_t)round_up(ceil_div(q.Tp, want), 16);
+    // (the polynomial split adjoint steps over 32 samples at a time)
+    q.adj_chunk = (int32_t)round_up(ceil_div(q.Tp, want), (q.sh && precision != EXPENC_FP32) ? 32 : 16);
     q.adj_split = (int32_t)ceil_div(q.Tp, q.adj_chunk);
   }
   *p = q;
@@ -594,7 +595,7 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
     b->ys = a.take<char>(P * p.Tp * (p.NCP / 16) * 256);
     if (p.sh) {
       b->pmono = a.take<double>(P * p.Tp * 12);
-      b->dpmono = a.take<float>(P * p.Tp * 12);
+      b->dpa = a.take<float>(P * p.Tp * 16);
       b->dwq = a.take<double>(P * p.Rp);
       b->ddw = a.take<float>(P * p.Rp);
     } else {

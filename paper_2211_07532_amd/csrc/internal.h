@@ -92,7 +92,7 @@ struct EncBuffers {
   float *dbet = nullptr;   // split forms: [Rp][NT] bet minus its 16-row tile centre (FP32)
   float *dkap = nullptr;   // split forms: [Tp][NT] kap minus its 16-row tile centre (FP32)
   double *pmono = nullptr; // split + SH: [Tp][12] cubic-monomial phase coefficients (turns) and t
-  float *dpmono = nullptr; // split + SH: [Tp][12] pmono minus its 16-row tile centre (FP32)
+  float *dpa = nullptr;    // split + SH: [Tp/32][64][8] adjoint increment operand (FP32)
   double *dwq = nullptr;   // split + SH: [Rp] dw0/2pi in the row-padded pixel layout
   float *ddw = nullptr;    // split + SH: [Rp] dwq minus its 16-pixel tile centre (FP32)
 };

@@ -41,7 +41,12 @@ __device__ inline void split_pair(float a, float b, uint32_t &hi, uint32_t &lo) 
   } else {
     const f16x2 h = {(_Float16)a, (_Float16)b};
     hi = __builtin_bit_cast(uint32_t, h);
-    const f16x2 l = {(_Float16)(a - (float)h[0]), (_Float16)(b - (float)h[1])};
+    // v - hi in one fused multiply-add that reads the 16-bit half directly
+    // (exact: hi is within a factor 2 of v), instead of converting hi back
+    float la, lb;
+    __asm__("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(la) : "v"(hi), "v"(a));
+    __asm__("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(lb) : "v"(hi), "v"(b));
+    const f16x2 l = {(_Float16)la, (_Float16)lb};
     lo = __builtin_bit_cast(uint32_t, l);
   }
 }
@@ -276,9 +281,17 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
 // Pixel x_c + k dx (k = -8..7, a literal) then costs three FP32 FMAs, plus
 // one for the off-resonance difference t (dw0(r) - dw0(r_c)) / 2pi.
 //
-// Adjoint (lane = pixel, 16 samples per step): the FP64 anchor at the tile's
-// centre sample, then FP32 increments sum_m (P_m(t_j) - P_m(t_c)) mono_m(r)
-// + (t_j - t_c) dw0(r)/2pi over the ten monomials (one of which is 1).
+// Adjoint (32 samples x 64 pixels per wave and step): the phase is the
+// FP64 anchor of the tile's centre sample t_c at each pixel plus the
+// increment sum_m (P_m(t) - P_m(t_c)) mono_m(r) + (t - t_c) dw0(r)/2pi, a
+// rank-11 product of a [32 samples x 12] table with a [12 x 32 pixels]
+// operand.  The increments therefore run on the matrix cores as six
+// v_mfma_f32_32x32x2_f32 per 32-pixel block (term 11 carries the anchor
+// with a unit A entry), instead of eleven FP32 FMAs per entry on the vector
+// unit.  The product's output layout gives each lane 16 samples of ONE
+// pixel, which is the A-operand layout of the contraction up to a fixed
+// permutation of the samples inside each group of 16; the adjoint records
+// are packed in that order, so no exchange between lanes is needed.
 // ---------------------------------------------------------------------------
 
 template <int GW, bool BF>
@@ -349,39 +362,42 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__
 }
 
 template <int GW, bool BF>
-__global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__ pmono, const float *__restrict__ dpmono,
+__global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__ pmono, const float *__restrict__ dpa,
                                                       const double *__restrict__ dwq, const u32x4 *__restrict__ ys,
                                                       float *__restrict__ part, int Rp, int64_t Tp, int NCP, int chunk,
                                                       int nsplit, int nxq, int nx, int ny, double dx, double dy) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
+  const int hl = lane >> 5, jl = lane & 31;
   const int split = blockIdx.x % nsplit;
   const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
   const int pz = blockIdx.z;  // problem
   pmono += pz * Tp * 12;
-  dpmono += pz * Tp * 12;
+  dpa += pz * Tp * 16;
   dwq += (int64_t)pz * Rp;
   ys += pz * Tp * NGP * 16;
   part += pz * nsplit * (int64_t)Rp * NCP * 2;
-  const int rq = (int)(row0 + lane);
-  const double xm = (rq % nxq - 0.5 * nx) * dx, ym = (rq / nxq - 0.5 * ny) * dy;
-  double mono[11];
-  mono[0] = 1.0;
-  mono[1] = xm;
-  mono[2] = ym;
-  mono[3] = xm * xm;
-  mono[4] = xm * ym;
-  mono[5] = ym * ym;
-  mono[6] = xm * xm * xm;
-  mono[7] = xm * xm * ym;
-  mono[8] = xm * ym * ym;
-  mono[9] = ym * ym * ym;
-  mono[10] = dwq[rq];
-  float mf[11];
+  // this lane's pixel in each 32-row block, and its B operand of the
+  // increment product: the monomial (or dw0) of term 2J + hl
+  double xg[2], yg[2], wg[2];
+  float bm[2][6];
 #pragma unroll
-  for (int m = 0; m < 11; ++m) mf[m] = (float)mono[m];
+  for (int blk = 0; blk < 2; ++blk) {
+    const int rq = (int)(row0 + 32 * blk + jl);
+    const double x = (rq % nxq - 0.5 * nx) * dx, y = (rq / nxq - 0.5 * ny) * dy, w = dwq[rq];
+    xg[blk] = x;
+    yg[blk] = y;
+    wg[blk] = w;
+    // terms 0..11: 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3, dw0, anchor
+    bm[blk][0] = (float)(hl ? x : 1.0);
+    bm[blk][1] = (float)(hl ? x * x : y);
+    bm[blk][2] = (float)(hl ? y * y : x * y);
+    bm[blk][3] = (float)(hl ? x * x * y : x * x * x);
+    bm[blk][4] = (float)(hl ? y * y * y : x * y * y);
+    bm[blk][5] = (float)w;  // lanes 32..63 replace it by the anchor per step
+  }
   f32x16 acc[2][GW];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -391,43 +407,64 @@ __global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__
       for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
   const int64_t t0 = (int64_t)split * chunk;
   const int64_t t1 = min(Tp, t0 + chunk);
-  for (int64_t t = t0; t < t1; t += 16) {
-    const double *pc = pmono + (t + 8) * 12;
-    double pa = 0.0;
+  for (int64_t t = t0; t < t1; t += 32) {
+    // A operand of the increment product (this lane's sample, terms 2J + hl)
+    const float4 *ap = reinterpret_cast<const float4 *>(dpa + ((t >> 5) * 64 + lane) * 8);
+    const float4 a03 = ap[0], a47 = ap[1];
+    const float av[6] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y};
+    // anchor: FP64 phase of the tile's centre sample at this lane's pixels,
+    // reduced to turns; it enters the product as term 11 (A = 1)
+    const double *pc = pmono + (t + 16) * 12;
+    f32x16 ph[2];
 #pragma unroll
-    for (int m = 0; m < 11; ++m) pa = fma(pc[m], mono[m], pa);
-    const float an = (float)__builtin_amdgcn_fract(pa);
-    __builtin_amdgcn_sched_barrier(0);
-    const float *dq = dpmono + t * 12;
-    float c[16], sn[16];
-    float buf[2][11];
+    for (int blk = 0; blk < 2; ++blk) {
+      const double y = yg[blk], x = xg[blk];
+      const double a0 = pc[0] + y * (pc[2] + y * (pc[5] + y * pc[9]));
+      const double a1 = pc[1] + y * (pc[4] + y * pc[8]);
+      const double a2 = pc[3] + y * pc[7];
+      const double pa = fma(pc[10], wg[blk], a0 + x * (a1 + x * (a2 + x * pc[6])));
+      const float anc = (float)__builtin_amdgcn_fract(pa);
+      const float b5 = hl ? anc : bm[blk][5];
 #pragma unroll
-    for (int m = 0; m < 11; ++m) buf[0][m] = dq[m];
+      for (int v = 0; v < 16; ++v) ph[blk][v] = 0.f;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      if (i + 1 < 16) {
-        // opaque offset: keeps the next sample's scalar loads from being
-        // merged with, or hoisted above, the current ones
-        int off = (i + 1) * 12;
-        __asm__ volatile("" : "+s"(off));
-#pragma unroll
-        for (int m = 0; m < 11; ++m) buf[(i + 1) & 1][m] = dq[off + m];
-      }
-      float ph = an + buf[i & 1][0];
-#pragma unroll
-      for (int m = 1; m < 11; ++m) ph = fmaf(buf[i & 1][m], mf[m], ph);
-      const float f = __builtin_amdgcn_fractf(ph);
-      c[i] = __builtin_amdgcn_cosf(f);
-      sn[i] = __builtin_amdgcn_sinf(f);
+      for (int J = 0; J < 5; ++J) ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[J], bm[blk][J], ph[blk], 0, 0, 0);
+      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[5], b5, ph[blk], 0, 0, 0);
     }
-    u32x4 A[2][4];
-    pack_tile16<BF>(c, sn, A);
+    // two contraction steps of 16 samples; ph[blk][8h + i] is sample
+    // 16h + 8(i/4) + 4hl + i%4 of pixel jl, which is K index 8hl + i of
+    // step h in the permuted sample order of the adjoint records
 #pragma unroll
-    for (int g = 0; g < GW; ++g) {
-      const u32x4 *yq = ys + ((t >> 4) * NGP + (g0 + g)) * 256 + lane;
-      const u32x4 b[4] = {yq[0], yq[64], yq[128], yq[192]};
-      acc[0][g] = step6<BF>(A[0], b, acc[0][g]);
-      acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
+    for (int h = 0; h < 2; ++h) {
+      u32x4 b[GW][4];
+#pragma unroll
+      for (int g = 0; g < GW; ++g) {
+        const u32x4 *yq = ys + (((t >> 4) + h) * NGP + (g0 + g)) * 256 + lane;
+        b[g][0] = yq[0];
+        b[g][1] = yq[64];
+        b[g][2] = yq[128];
+        b[g][3] = yq[192];
+      }
+#pragma unroll
+      for (int blk = 0; blk < 2; ++blk) {
+        uint32_t w[4][4];  // [kind: c hi, c lo, s hi, s lo][word]
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          float c2[2], s2[2];
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const float f = __builtin_amdgcn_fractf(ph[blk][8 * h + 2 * m + e]);
+            c2[e] = __builtin_amdgcn_cosf(f);
+            s2[e] = __builtin_amdgcn_sinf(f);
+          }
+          split_pair<BF>(c2[0], c2[1], w[0][m], w[1][m]);
+          split_pair<BF>(s2[0], s2[1], w[2][m], w[3][m]);
+        }
+        const u32x4 A[4] = {u32x4{w[0][0], w[0][1], w[0][2], w[0][3]}, u32x4{w[1][0], w[1][1], w[1][2], w[1][3]},
+                            u32x4{w[2][0], w[2][1], w[2][2], w[2][3]}, u32x4{w[3][0], w[3][1], w[3][2], w[3][3]}};
+#pragma unroll
+        for (int g = 0; g < GW; ++g) acc[blk][g] = step6<BF>(A, b[g], acc[blk][g]);
+      }
     }
   }
   store_partials<GW>(part + (int64_t)split * Rp * NCP * 2, row0, NCP, g0, lane, acc);
@@ -500,10 +537,12 @@ __global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *
 
 // Adjoint operand from y [B][T][C] (src_abi) or from forward partials minus
 // y_meas (src_part, nsplit partial arrays in [Tp][NCP] layout).
+// With perm, K index 8h + i of a step holds sample 8(i/4) + 4h + i%4 of its
+// 16 (the order in which the polynomial adjoint produces its phase tile).
 template <bool BF>
 __global__ void k_pack_y_split(const float2 *__restrict__ src_abi, const float2 *__restrict__ src_part, int nsplit,
                                const float2 *__restrict__ y_meas, int64_t T, int64_t Tp, int C, int NC, int NCP,
-                               u32x4 *__restrict__ ys) {
+                               u32x4 *__restrict__ ys, int perm) {
   const int NGP = NCP / 16;
   const int pz = blockIdx.y;  // problem
   if (src_abi) src_abi += pz * T * NC;
@@ -520,7 +559,7 @@ __global__ void k_pack_y_split(const float2 *__restrict__ src_abi, const float2 
   float b1[8], b2[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int64_t t = 16 * q + 8 * (lane >> 5) + i;
+    const int64_t t = 16 * q + (perm ? 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3) : 8 * (lane >> 5) + i);
     float2 y = make_float2(0.f, 0.f);
     if (t < T && col < NC) {
       const int b = col / C, c = col % C;
@@ -605,6 +644,30 @@ __global__ void k_prep_pmono(const double *__restrict__ kap, int NT, int L, int6
   for (int m = 0; m < 12; ++m) pmono[t * 12 + m] = out[m];
 }
 
+// A operand of the adjoint's phase-increment product, in lane order: for the
+// 32-sample tile q, lane l and term pair J, the entry is
+// pmono[t][k] - pmono[32q + 16][k] with t = 32q + l%32, k = 2J + l/32 (k <= 10),
+// and 1 for k = 11 (the term that carries the per-pixel anchor).
+__global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, float *__restrict__ dpa) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Tp / 32 * 64) return;
+  pmono += blockIdx.y * Tp * 12;  // problem
+  dpa += blockIdx.y * Tp * 16;
+  const int64_t q = i >> 6;
+  const int l = (int)(i & 63);
+  const int64_t t = 32 * q + (l & 31), ta = 32 * q + 16;
+  float v[8];
+#pragma unroll
+  for (int J = 0; J < 6; ++J) {
+    const int k = 2 * J + (l >> 5);
+    v[J] = k <= 10 ? (float)(pmono[t * 12 + k] - pmono[ta * 12 + k]) : 1.0f;
+  }
+  v[6] = v[7] = 0.f;
+  float4 *o = reinterpret_cast<float4 *>(dpa + i * 8);
+  o[0] = make_float4(v[0], v[1], v[2], v[3]);
+  o[1] = make_float4(v[4], v[5], v[6], v[7]);
+}
+
 // dwq[r'] = dw0(r)/2pi in the row-padded pixel layout.
 __global__ void k_prep_dwq(const double *__restrict__ dw0, int nx, int ny, int nxq, int Rp, double *__restrict__ dwq) {
   const int rq = blockIdx.x * blockDim.x + threadIdx.x;
@@ -622,8 +685,8 @@ int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hi
   if (p.sh) {
     k_prep_pmono<<<gp(p.Tp), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), p.z0s, b.pmono);
     EX_LAUNCHED("monomial coefficients");
-    k_tile_diff<<<gp(p.Tp * 12), 256, 0, s>>>(b.pmono, b.dpmono, p.Tp, 12);
-    EX_LAUNCHED("tile differences (samples)");
+    k_prep_dpa<<<gp(p.Tp / 32 * 64), 256, 0, s>>>(b.pmono, p.Tp, b.dpa);
+    EX_LAUNCHED("increment table (samples)");
     k_prep_dwq<<<gp(p.Rp), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);
     EX_LAUNCHED("off-resonance layout");
     k_tile_diff<<<gp(p.Rp), 256, 0, s>>>(b.dwq, b.ddw, p.Rp, 1);
@@ -704,10 +767,10 @@ static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
   if (p.GW == 2)
-    k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpmono, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
+    k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
                                                p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
   else
-    k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpmono, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
+    k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
                                                p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
 }
 
@@ -758,9 +821,11 @@ int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, cons
   u32x4 *ys = reinterpret_cast<u32x4 *>(b.ys);
   const float2 *part = from_partials ? b.part : nullptr;
   if (p.prec == EXPENC_BF16_SPLIT)
-    k_pack_y_split<true><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys);
+    k_pack_y_split<true><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys,
+                                            p.sh ? 1 : 0);
   else
-    k_pack_y_split<false><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys);
+    k_pack_y_split<false><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys,
+                                             p.sh ? 1 : 0);
   EX_LAUNCHED("pack_y split");
   return EXPENC_OK;
 }
