@@ -178,8 +178,9 @@ __global__ __launch_bounds__(256) void k_fwd_f32(const double *__restrict__ kap,
                                                  int NCP, int chunk, int nsplit) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  int split, rb;
+  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
   const int pz = blockIdx.z;  // problem
@@ -255,8 +256,9 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
                                                  int NCP, int chunk, int nsplit) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  int split, rb;
+  if (!split_tile(Rp / 256, nsplit, &split, &rb)) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
   const int pz = blockIdx.z;  // problem
@@ -729,7 +731,7 @@ int kernel_timing(int32_t mode, double *out) {
 
 template <int NT>
 static void launch_fwd(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
+  dim3 grid(split_grid(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   if (p.GW == 2)
     k_fwd_f32<NT, 2><<<grid, 256, 0, s>>>(b.kap, b.bet, b.zop, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk, p.fwd_split);
@@ -739,7 +741,7 @@ static void launch_fwd(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 template <int NT>
 static void launch_adj(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
+  dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   if (p.GW == 2)
     k_adj_f32<NT, 2><<<grid, 256, 0, s>>>(b.kap, b.bet, b.yop, part, p.Rp, p.Tp, p.NCP, p.adj_chunk, p.adj_split);

@@ -53,6 +53,25 @@ struct Arena {
 // Geometry of one encoding contraction: a GEMM-shaped sum over pixels
 // (forward) or samples (adjoint) with B*C complex columns, padded so that
 // the kernels never test bounds inside their loops.
+// XCD-aware decomposition of a split-K contraction launch.  Workgroup ids
+// go to the eight XCDs in turn (id % 8), each XCD with its own L2.  Id b is
+// remapped to b' = (b % 8) * Q + b / 8 (Q = ceil(N / 8), N = row blocks x
+// splits) and b' is read split-major, so every XCD works through a
+// contiguous range of reduction chunks and the slice of the streamed operand
+// it needs stays in its L2.  The grid has 8Q >= N workgroups; the at most 7
+// surplus ones return at once.
+__device__ inline bool split_tile(int nrb, int nsplit, int *split, int *rb) {
+  const int n = nrb * nsplit;
+  const int q = (n + 7) >> 3;
+  const int b = blockIdx.x;
+  const int bp = (b & 7) * q + (b >> 3);
+  if (bp >= n) return false;
+  *split = bp / nrb;
+  *rb = bp - *split * nrb;
+  return true;
+}
+inline unsigned split_grid(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
+
 struct EncPlan {
   int32_t nx = 0, ny = 0, R = 0, Rp = 0;  // pixels, padded to a multiple of 256
   int64_t T = 0, Tp = 0;                  // samples, padded to a multiple of 256

@@ -179,8 +179,9 @@ __global__ __launch_bounds__(256) void k_fwd_split(const double *__restrict__ ka
                                                    int nsplit) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  int split, rb;
+  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
   const int pz = blockIdx.z;  // problem
@@ -228,8 +229,9 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
                                                    int nsplit) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  int split, rb;
+  if (!split_tile(Rp / 256, nsplit, &split, &rb)) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
   const int pz = blockIdx.z;  // problem
@@ -301,8 +303,9 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__
                                                       int nsplit, int nxq, int nx, int ny, double dx, double dy) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  int split, rb;
+  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
   const int pz = blockIdx.z;  // problem
@@ -369,8 +372,9 @@ __global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int hl = lane >> 5, jl = lane & 31;
-  const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * 256 + wave * 64;
+  int split, rb;
+  if (!split_tile(Rp / 256, nsplit, &split, &rb)) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
   const int pz = blockIdx.z;  // problem
@@ -706,7 +710,7 @@ int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hi
 
 template <int NT, bool BF>
 static void launch_fwd_split(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
+  dim3 grid(split_grid(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
   if (p.GW == 2)
@@ -719,7 +723,7 @@ static void launch_fwd_split(const EncPlan &p, const EncBuffers &b, hipStream_t 
 
 template <int NT, bool BF>
 static void launch_adj_split(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
+  dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
   if (p.GW == 2)
@@ -750,7 +754,7 @@ static void adj_split_nt(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 template <bool BF>
 static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
+  dim3 grid(split_grid(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
   if (p.GW == 2)
@@ -763,7 +767,7 @@ static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 template <bool BF>
 static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid((unsigned)(p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
+  dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
   if (p.GW == 2)
