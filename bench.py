@@ -30,7 +30,43 @@ sys.path.insert(0, ROOT)
 import synth  # noqa: E402
 
 PEAK_TFLOPS = {"fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6}
+# flops the form issues per complex MAC: 8 real, times 3 products for the splits
+FORM_FLOP_PER_CMAC = {"fp32": 8, "bf16": 24, "fp16": 24}
+# v_sin_f32 / v_cos_f32: half the FP32 lane rate, 256 CUs x 2.4 GHz x 32 lanes
+SINCOS_PEAK = 256 * 2.4e9 * 32
 N_POWER = 20
+
+# HBM bytes per launch of each form's dominant kernel (the adjoint contraction
+# at 1.5 mm), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes over the
+# profiling workload, each scaled by the counter's reading for a plain
+# 256 MiB copy.  Valid only for the kernel source and launch shape they were
+# taken on: `sha` is the SHA-256 of the files the kernel is built from.
+TRAFFIC = {
+    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 407869645,
+             "sha": "0461502a2f440ed36dc943c0c94122f280ffadaea1e26ed5cb6d646c7dd9b14a"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 211471995,
+             "sha": "58134d0a28d25ef0d825d8978e8270ac089d3a596fbc0e3d12eb5e2ff6c24b0a"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 212124918,
+             "sha": "58134d0a28d25ef0d825d8978e8270ac089d3a596fbc0e3d12eb5e2ff6c24b0a"},
+}
+TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h"], "bf16": ["split.hip", "internal.h"],
+                   "fp16": ["split.hip", "internal.h"]}
+
+
+def source_sha(form):
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES[form]:
+        with open(os.path.join(ROOT, "paper_2211_07532_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_for(form, adj_split):
+    e = TRAFFIC.get(form)
+    if not e or e["sha"] != source_sha(form) or e["adj_split"] != adj_split:
+        return None
+    return e["bytes"]
 
 
 def parse():
@@ -45,6 +81,7 @@ def parse():
                     help="problems of the mixed-size batch measured beside the headline (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch shapes")
+    ap.add_argument("--retune", action="store_true", help="time the launch shapes instead of using cached ones")
     return ap.parse_args()
 
 
@@ -85,7 +122,8 @@ def run_batch(args, prec, ee, torch):
             if w.n in tuning:
                 continue
             forms = ["fp32"] + ([prec] if prec != "fp32" else [])
-            tuning[w.n] = {f: dataclasses.asdict(autotune.tune(op, 1, f)) for f in forms}
+            tuning[w.n] = {f: dataclasses.asdict(autotune.tune(op, 1, f, use_cache=not args.retune))
+                           for f in forms}
             for f in forms:
                 tuning[w.n][f].pop("timings", None)
     v0 = torch.from_numpy(synth.power_start(max(w.npix for w in ws), 7).astype(np.complex64)).to(dev)
@@ -161,13 +199,14 @@ def main():
     forms = [args.precision] if args.precision != "all" else list(FORMS)
     out = {}
     for prec in forms:
+        print(f"[bench] {prec}: timing the 1.5 mm reconstruction", file=sys.stderr, flush=True)
         tuning = None
         if not args.no_tune:
             # launch shapes from the project autotuner (cached per device and geometry);
             # the split forms' FP32 anchors use the FP32 plan
             from paper_2211_07532_amd import autotune
             for f in (["fp32"] if prec != "fp32" else []) + [prec]:
-                r = autotune.tune(op, 1, f)
+                r = autotune.tune(op, 1, f, use_cache=not args.retune)
             tuning = {"fwd_target": r.fwd_target, "adj_target": r.adj_target, "cached": r.cached,
                       **autotune.plan_info(op, 1, prec)}
 
@@ -212,6 +251,11 @@ def main():
         adj_ms = ev[2] / max(ev[3], 1)
         dom_ms = max(fwd_ms, adj_ms)
         achieved = 8.0 * cmac / (dom_ms * 1e-3) / 1e12     # algorithmic: 4 real MAC per CMAC
+        # the MFMA/sincos roofline of the form: the larger of its matrix-core
+        # time (all products it issues) and its sincos time, over the measured time
+        t_mfma = FORM_FLOP_PER_CMAC[prec] * cmac / (PEAK_TFLOPS[prec] * 1e12) * 1e3
+        t_sincos = 2.0 * w.nsamples * w.npix / SINCOS_PEAK * 1e3
+        adj_split = tuning["adj_split"] if tuning else None
         out[prec] = {
             "gcmac_per_s": round(apps * cmac / dt / 1e9, 2), "ms_per_step": round(dt * 1e3, 3),
             "fista_iter_per_s": round(it_s, 2), "nrmse_vs_fp64": None if nrmse is None else float(f"{nrmse:.3e}"),
@@ -219,7 +263,11 @@ def main():
             "launch_shape": tuning,
             "roofline": {"bound": "mfma", "kernel": ("forward" if fwd_ms >= adj_ms else "adjoint") + " contraction",
                          "achieved": round(achieved, 2), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
-                         "frac": round(achieved / PEAK_TFLOPS[prec], 4), "traffic": None},
+                         "frac": round(achieved / PEAK_TFLOPS[prec], 4),
+                         "traffic": traffic_for(prec, adj_split)},
+            "roofline_form": {"t_mfma_ms": round(t_mfma, 4), "t_sincos_ms": round(t_sincos, 4),
+                              "kernel_ms": round(dom_ms, 4), "frac": round(max(t_mfma, t_sincos) / dom_ms, 4),
+                              "frac_forward": round(max(t_mfma, t_sincos) / fwd_ms, 4)},
         }
 
     # headline: the fastest form whose solve meets NRMSE <= 1e-4 against the FP64 oracle
@@ -245,13 +293,16 @@ def main():
         "fista_iter_per_s": h["fista_iter_per_s"],
         "nrmse_vs_fp64": h["nrmse_vs_fp64"],
         "roofline": h["roofline"],
+        "roofline_form": h["roofline_form"],
         "forms": out,
     }
     if "fp32" in out and head != "fp32":
         line["split_vs_fp32_fista_iter_ratio"] = round(h["fista_iter_per_s"] / out["fp32"]["fista_iter_per_s"], 3)
     if args.batch_nprob > 0:
+        print(f"[bench] batch of {args.batch_nprob} problems ({head})", file=sys.stderr, flush=True)
         line["batch"] = run_batch(args, head, ee, torch)
     if not args.no_cpu_baseline:
+        print("[bench] oracle on the host cores", file=sys.stderr, flush=True)
         from oracle import encoding
         line["cpu_baseline"] = cpu_baseline(w, prob, encoding.sh_basis(w.n, w.fov, w.z0, w.nbasis))
     print(json.dumps(line), flush=True)

@@ -7,10 +7,13 @@ longer reduction.  For one operator geometry (grid, coils, samples, basis
 terms and kind), batch and precision, ``tune`` times whole forward and
 adjoint applications (torch events on the launch stream) over a ladder of
 targets, keeps the fastest per direction, registers it with the library
-(``expenc_set_tuning``) and stores it in a JSON cache keyed by the device
-name and the geometry, so later processes apply it without timing again
-(``apply_cached``).  A batched solve of P problems of that geometry uses the
-tuned totals across its P problems.
+(``expenc_set_tuning``) and stores it in a JSON cache keyed by the GPU
+architecture and compute-unit count and the geometry, so later processes
+apply it without timing again (``apply_cached``).  ``tuning_defaults.json``
+beside this module ships the shapes measured for the benchmark geometries on
+an MI355X (regenerate with ``python -m paper_2211_07532_amd.autotune --out
+FILE``); a user cache entry takes precedence.  A batched solve of P problems
+of one geometry uses the tuned totals across its P problems.
 """
 from __future__ import annotations
 
@@ -33,10 +36,19 @@ def cache_path() -> str:
         os.path.expanduser("~"), ".cache", "paper_2211_07532_amd", "tuning.json")
 
 
+DEFAULTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_defaults.json")
+
+
+def device_tag(device) -> str:
+    """GPU architecture and compute-unit count, e.g. 'gfx950_cu256'."""
+    p = torch.cuda.get_device_properties(device)
+    arch = getattr(p, "gcnArchName", "") or p.name
+    return f"{arch.split(':')[0]}_cu{p.multi_processor_count}".replace(" ", "_")
+
+
 def _key(op: _e.Operator, batch: int, precision) -> str:
-    name = torch.cuda.get_device_name(op.device).replace(" ", "_")
     kind = "sh" if op._c.basis_kind == _b.BASIS_SH else "maps"
-    return (f"{name}/nx{op.nx}_ny{op.ny}_c{op.ncoils}_t{op.nsamples}_l{op.nbasis}_{kind}"
+    return (f"{device_tag(op.device)}/nx{op.nx}_ny{op.ny}_c{op.ncoils}_t{op.nsamples}_l{op.nbasis}_{kind}"
             f"_b{batch}_p{_e._prec(precision)}")
 
 
@@ -82,9 +94,15 @@ class TuneResult:
     cached: bool = False
 
 
-def apply_cached(op: _e.Operator, batch: int = 1, precision="fp32", path: Optional[str] = None):
-    """Registers a cached result for this geometry if there is one; returns it (or None)."""
-    e = _load(path or cache_path()).get(_key(op, batch, precision))
+def apply_cached(op: _e.Operator, batch: int = 1, precision="fp32", path: Optional[str] = None,
+                 defaults: bool = True):
+    """Registers a cached result for this geometry if there is one (the user
+    cache first, then the shipped table of measured defaults); returns it
+    (or None)."""
+    key = _key(op, batch, precision)
+    e = _load(path or cache_path()).get(key)
+    if not e and defaults:
+        e = _load(DEFAULTS).get(key)
     if not e:
         return None
     set_targets(op, batch, precision, e["fwd_target"], e["adj_target"])
@@ -137,3 +155,44 @@ def tune(op: _e.Operator, batch: int = 1, precision="fp32", candidates: Sequence
     _store(path, _key(op, batch, precision), {"fwd_target": best_f, "adj_target": best_a,
                                               "fwd_ms": res.fwd_ms, "adj_ms": res.adj_ms})
     return res
+
+
+def main(argv=None):
+    """Times the launch shapes of the benchmark geometries on this GPU and
+    writes them to a JSON file (the format of the shipped defaults)."""
+    import argparse
+    import sys
+    import numpy as np
+    ap = argparse.ArgumentParser(prog="python -m paper_2211_07532_amd.autotune")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--forms", default="fp32,bf16,fp16")
+    ap.add_argument("--workloads", default="mm15,mm11,batch")
+    a = ap.parse_args(argv)
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import synth
+    ws = []
+    for name in a.workloads.split(","):
+        if name == "mm15":
+            ws.append(synth.MM15)
+        elif name == "mm11":
+            ws.append(synth.MM11)
+        elif name == "batch":
+            ws.extend(synth.batch_workloads(1, 3))
+    dev = torch.device("cuda:0")
+    for w in ws:
+        p = synth.make_problem(w)
+
+        def t(v):
+            return torch.from_numpy(np.ascontiguousarray(v)).to(dev)
+
+        op = _e.Operator(w.n, w.n, t(p.smaps.astype(np.complex64)), t(p.coef), t(p.time), None, t(p.dw0),
+                         sh_grid=(w.fov, w.fov, w.z0))
+        for f in a.forms.split(","):
+            r = tune(op, 1, f, reps=10, path=a.out, use_cache=False)
+            print(f"{w.name} {f}: forward target {r.fwd_target} ({r.fwd_ms:.4f} ms), "
+                  f"adjoint target {r.adj_target} ({r.adj_ms:.4f} ms)", flush=True)
+            set_targets(op, 1, f, 0, 0)
+
+
+if __name__ == "__main__":
+    main()
