@@ -87,8 +87,10 @@ def test_full_size_sampled_outputs(wl, sh):
     """Full-size operators in the benchmark's launch configuration: sampled
     samples/pixels against the oracle's one-output direct sums."""
     ee = _ee()
+    from paper_2211_07532_amd import autotune
     print(f"[case] full {wl.name} sh={sh}", flush=True)
     case = Case(wl, sh=sh)
+    autotune.apply_cached(case.op, 1, "fp32")    # the shipped launch shapes (the bench's)
     x = case.x_noisy
     y = ee.forward(case.to_dev(x), case.op).cpu().numpy()
     rng = np.random.default_rng(5)

@@ -62,12 +62,15 @@ def test_split_operators(prec, name, sh):
     assert e_fwd <= 5 * emu + 2e-6
 
 
+@pytest.mark.parametrize("wl", [synth.MM15, synth.MM11], ids=["1.5mm", "1.1mm"])
 @pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
-def test_split_full_size_sampled(prec, sh):
+def test_split_full_size_sampled(prec, sh, wl):
     ee = _ee()
-    wl = synth.MM15
+    from paper_2211_07532_amd import autotune
+    print(f"[case] split full {wl.name} {prec} sh={sh}", flush=True)
     case = Case(wl, sh=sh)
+    autotune.apply_cached(case.op, 1, prec)      # the shipped launch shapes (the bench's)
     x = case.x_noisy
     y = ee.forward(case.to_dev(x), case.op, precision=prec).cpu().numpy()
     rng = np.random.default_rng(6)
@@ -80,7 +83,7 @@ def test_split_full_size_sampled(prec, sh):
     got = np.array([xa[r] for r in rs])
     ref = np.array([encoding.adjoint_one(y.astype(np.complex128), *case.oracle_args(), int(r)) for r in rs])
     e2 = rel(got, ref)
-    print(f"split {prec} full sh={sh}: forward {e:.2e} adjoint {e2:.2e}", flush=True)
+    print(f"split {prec} full {wl.name} sh={sh}: forward {e:.2e} adjoint {e2:.2e}", flush=True)
     assert e <= 1e-3 and e2 <= 1e-3
 
 
