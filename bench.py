@@ -100,6 +100,37 @@ def cpu_baseline(w, prob, basis):
                       f"({2 * cmac:.3e} CMAC, {dt:.1f} s)"}
 
 
+def run_coil_compression(prec, ee, torch, w, op, y, v0, x_ref, nv=20):
+    """32 physical coils compressed to nv virtual coils (the count the paper
+    recommends for a 32-channel receiver): time of the compression (Gram
+    matrix, eigen-decomposition, data and maps), FISTA iter/s on the
+    compressed problem, and its reconstruction's distance to the
+    32-coil one."""
+    yv, sv, _, _ = ee.coil_compress(y, nv, op.smaps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        yv, sv, _, _ = ee.coil_compress(y, nv, op.smaps)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    opv = ee.Operator(w.n, w.n, sv, op.coef, op.time, None, op.dw0, sh_grid=(w.fov, w.fov, w.z0))
+    res = ee.fista(yv, opv, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
+                   n_power=N_POWER)
+    L, lam = res.lipschitz, res.lam[0]
+    ee.fista(yv, opv, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        ee.fista(yv, opv, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+    torch.cuda.synchronize()
+    its = w.n_iter * reps / (time.perf_counter() - t1)
+    d = float(torch.linalg.vector_norm(res.x - x_ref) / torch.linalg.vector_norm(x_ref))
+    return {"virtual_coils": nv, "physical_coils": w.ncoils, "compress_ms": round(ms, 3),
+            "fista_iter_per_s": round(its, 2), "dtype": FORMS[prec],
+            "nrmse_vs_32_coil_reconstruction": float(f"{d:.3e}")}
+
+
 def run_batch(args, prec, ee, torch):
     """The mixed-size batch (148 px / R=4, 170 px / R=5, 200 px / R=6 in turn,
     per-problem fields, dB0, coil maps and slice positions; 100 FISTA
@@ -298,6 +329,10 @@ def main():
     }
     if "fp32" in out and head != "fp32":
         line["split_vs_fp32_fista_iter_ratio"] = round(h["fista_iter_per_s"] / out["fp32"]["fista_iter_per_s"], 3)
+    print(f"[bench] coil compression ({head})", file=sys.stderr, flush=True)
+    xh = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=head, lipschitz=0.0, power_v0=v0,
+                  n_power=N_POWER).x
+    line["coil_compression"] = [run_coil_compression(head, ee, torch, w, op, y, v0, xh, nv) for nv in (16, 20)]
     if args.batch_nprob > 0:
         print(f"[bench] batch of {args.batch_nprob} problems ({head})", file=sys.stderr, flush=True)
         line["batch"] = run_batch(args, head, ee, torch)

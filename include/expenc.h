@@ -268,6 +268,38 @@ int cg_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
              const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * Receiver pre-whitening and coil compression (Methods 2.2.1: noise
+ * correlation between receivers corrected by pre-whitening; k-space data
+ * compressed to virtual coils to speed up the reconstruction).  C = ncoils in
+ * [1, 64].  Workspace (device, caller-owned) from expenc_coil_workspace_size
+ * (ncoils, nsamples); 0 for invalid sizes.
+ *
+ * expenc_prewhiten: psi [C][C] complex128 (interleaved FP64), the receivers'
+ * Hermitian positive-definite noise covariance, factored as psi = L L^H
+ * (Cholesky, FP64).  In place, every coil vector becomes L^{-1} v: the data
+ * y [nsamples][C] (one vector per sample; pass B*T samples for a batch) and
+ * the maps smaps [C][npix] (one vector per pixel).  Either may be skipped with
+ * a zero size.  A psi that is not positive definite yields NaN outputs.
+ *
+ * expenc_coil_compress: G = Y^H Y over the nsamples rows of y [nsamples][C]
+ * (FP64 sums), its eigenvectors V (columns, eigenvalues descending) by a
+ * cyclic Jacobi method; with V_k = the first k = nvirtual columns:
+ * y_out [nsamples][k] = Y V_k, smaps_out [k][npix] with
+ * smaps_out[j] = sum_c V[c][j] smaps[c], so that y_out follows the encoding
+ * model with the virtual maps.  eigvec ([C][C] complex128, row-major, column j
+ * = eigenvector j) and eigval ([C] float64) receive the full decomposition if
+ * not NULL; y_out may be NULL (maps only), npix may be 0 (data only).
+ * Eigenvectors are unique up to a phase per column (and within degenerate
+ * eigenvalues); the compressed subspace is what is determined.
+ */
+size_t expenc_coil_workspace_size(int32_t ncoils, int64_t nsamples);
+int expenc_prewhiten(int32_t ncoils, const double *psi, int64_t nsamples, float *y, int32_t npix, float *smaps,
+                     void *ws, size_t ws_bytes, void *stream);
+int expenc_coil_compress(int32_t ncoils, int32_t nvirtual, int64_t nsamples, const float *y, int32_t npix,
+                         const float *smaps, float *y_out, float *smaps_out, double *eigvec, double *eigval,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Launch-shape tuning (not part of the method).  The contraction kernels
  * split their reduction (pixels for A, samples for A^H) so that one launch
  * has about `target` workgroups (default 2048, or the EXPENC_TARGET_WG

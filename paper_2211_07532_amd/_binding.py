@@ -76,6 +76,10 @@ SIGNATURES = {
     "fista_solve_batched": (ctypes.c_int, [_c_int, ctypes.POINTER(ExpencOp), _c_int, ctypes.POINTER(_vp),
                                            ctypes.POINTER(_vp), ctypes.POINTER(FistaOpts), _vp, ctypes.c_size_t,
                                            _vp]),
+    "expenc_coil_workspace_size": (ctypes.c_size_t, [_c_int, ctypes.c_int64]),
+    "expenc_prewhiten": (ctypes.c_int, [_c_int, _vp, ctypes.c_int64, _vp, _c_int, _vp, _vp, ctypes.c_size_t, _vp]),
+    "expenc_coil_compress": (ctypes.c_int, [_c_int, _c_int, ctypes.c_int64, _vp, _c_int, _vp, _vp, _vp, _vp, _vp,
+                                            _vp, ctypes.c_size_t, _vp]),
     "expenc_set_tuning": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int, _c_int]),
     "expenc_plan_info": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int,
                                         ctypes.POINTER(ctypes.c_int64)]),

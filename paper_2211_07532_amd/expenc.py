@@ -234,6 +234,53 @@ def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4"
     return res
 
 
+def _coil_ws(ncoils: int, nsamples: int, device):
+    n = _b.lib().expenc_coil_workspace_size(ncoils, nsamples)
+    if n == 0:
+        raise _b.ExpencError(_b.EXPENC_EINVAL, "expenc_coil_workspace_size")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def prewhiten(psi: torch.Tensor, y: Optional[torch.Tensor] = None, smaps: Optional[torch.Tensor] = None):
+    """In place: every coil vector of y [..., C] and smaps [C, ...] becomes L^{-1} v with
+    psi = L L^H (psi [C][C] complex128).  Returns (y, smaps)."""
+    C = psi.shape[0]
+    dev = psi.device
+    _need(psi, torch.complex128, "psi", dev)
+    ny = 0 if y is None else y.numel() // C
+    npix = 0 if smaps is None else smaps.numel() // C
+    if y is not None:
+        _need(y, torch.complex64, "y", dev)
+    if smaps is not None:
+        _need(smaps, torch.complex64, "smaps", dev)
+    ws = _coil_ws(C, 0, dev)
+    check(_b.lib().expenc_prewhiten(C, _ptr(psi), ny, _ptr(y), npix, _ptr(smaps), _ptr(ws), ws.numel(),
+                                    _stream(dev)), "expenc_prewhiten")
+    return y, smaps
+
+
+def coil_compress(y: torch.Tensor, nvirtual: int, smaps: Optional[torch.Tensor] = None):
+    """Virtual coils from the leading eigenvectors of Y^H Y (y [..., C]).
+    Returns (y_v [..., nv], smaps_v [nv, ...] or None, eigenvalues [C], V [C][C])."""
+    C = y.shape[-1]
+    dev = y.device
+    _need(y, torch.complex64, "y", dev)
+    n = y.numel() // C
+    yv = torch.empty(tuple(y.shape[:-1]) + (nvirtual,), dtype=torch.complex64, device=dev)
+    npix = 0
+    sv = None
+    if smaps is not None:
+        _need(smaps, torch.complex64, "smaps", dev)
+        npix = smaps.numel() // C
+        sv = torch.empty((nvirtual,) + tuple(smaps.shape[1:]), dtype=torch.complex64, device=dev)
+    v = torch.empty((C, C), dtype=torch.complex128, device=dev)
+    w = torch.empty(C, dtype=torch.float64, device=dev)
+    ws = _coil_ws(C, n, dev)
+    check(_b.lib().expenc_coil_compress(C, nvirtual, n, _ptr(y), npix, _ptr(smaps), _ptr(yv), _ptr(sv), _ptr(v),
+                                        _ptr(w), _ptr(ws), ws.numel(), _stream(dev)), "expenc_coil_compress")
+    return yv, sv, w, v
+
+
 _batch_ws = {}
 
 

@@ -109,3 +109,13 @@ def test_tuning_targets_shape_the_split():
     finally:
         assert lib.expenc_set_tuning(ctypes.byref(op), 1, 0, 0, 0) == b.EXPENC_OK
     assert _info(b, lib, op) == base
+
+
+def test_coil_arguments_rejected():
+    b, lib = _lib()
+    assert lib.expenc_coil_workspace_size(0, 10) == 0
+    assert lib.expenc_coil_workspace_size(65, 10) == 0
+    assert lib.expenc_coil_workspace_size(32, 16384) > 0
+    assert lib.expenc_coil_compress(8, 9, 10, ctypes.c_void_p(1), 0, None, None, None, None, None, None, 0,
+                                    None) == b.EXPENC_EINVAL
+    assert lib.expenc_prewhiten(8, None, 0, None, 0, None, None, 0, None) == b.EXPENC_EINVAL
