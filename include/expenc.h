@@ -259,6 +259,72 @@ int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t batch, cons
                         void *stream);
 
 /*
+ * The paper's regulariser (Methods 2.1; Supporting Information S1):
+ * undecimated wavelet transform, sigma/2 weights per level, balanced FISTA.
+ *
+ * swt_fwd / swt_inv: undecimated ("a trous") periodised separable 2D
+ * transform with J = levels (1..8) on any nx x ny grid, and its adjoint.
+ * Level j (step d = 2^j) applies the 1D filters
+ * f(u)[i] = 2^-1/2 sum_k f[k] u[(i + d k) mod n] (low pass h, high pass g of
+ * the chosen wavelet) along x and y; coefficients w [B][3J+1][ny][nx] hold
+ * level j in bands 3j (high x, low y), 3j+1 (low x, high y), 3j+2 (high,
+ * high) and the final low pass in band 3J.  With orthonormal filters this
+ * is a tight frame: swt_inv(swt_fwd(x)) = x.  Workspace: for levels > 1,
+ * expenc_swt_workspace_size() bytes of device scratch (NULL allowed at one
+ * level).
+ *
+ * expenc_sigma_weights: weights lam [B][3J+1] (device, float64) from the
+ * coefficients w (e.g. of A^H y): per image and level, the magnitudes |w| of
+ * the level's three high-pass bands are counted in 256 equal bins over
+ * [0, 4 mean|w|) (larger values are not counted); sigma = the centre of the
+ * fullest bin (lowest bin on ties) and the level's weight is
+ * scale * sigma / 2; the low-pass band gets 0.  counts [B][J][256]
+ * (uint32, device) receives the histograms if not NULL.
+ *
+ * fista_balanced_solve: balanced FISTA (Methods 2.1) on the coefficients
+ * alpha of the undecimated frame:
+ *   F(alpha) = ||A W^H alpha - y||^2 + kappa/2 ||(I - W W^H) alpha||^2
+ *              + sum_b lambda_b ||alpha_b||_1,
+ * from alpha = 0 for exactly n_iter iterations with step 1/L,
+ * L = L_A + kappa, L_A = 2 lambda_max(A^H A), gradient
+ * 2 W A^H (A W^H beta - y) + kappa (beta - W W^H beta), per-band soft
+ * threshold tau_b = lambda_b / L and the FISTA momentum; x = W^H alpha_K
+ * ([B][ny][nx]).  Weights: opts->lambda ([B][3J+1] device) or, when NULL,
+ * lambda_scale * sigma/2 from W A^H y (FP32 operators).  Split precisions use
+ * the anchored gradient of fista_solve (every refine_every-th and the last
+ * iteration exact in FP32).  The loop is captured into a cached HIP graph.
+ * scalars (device, optional): [L_A, kappa, L, lambda[B][3J+1], tau[B][3J+1]].
+ */
+typedef struct expenc_balanced_opts {
+  int32_t n_iter;        /* iterations K                                           */
+  int32_t precision;     /* EXPENC_FP32 / EXPENC_BF16_SPLIT / EXPENC_FP16_SPLIT    */
+  int32_t wavelet;       /* EXPENC_HAAR / EXPENC_DB4                               */
+  int32_t levels;        /* J in [1, 8] (the paper: 1)                             */
+  int32_t refine_every;  /* split forms: FP32 anchor cadence (0 = 10)              */
+  int32_t n_power;       /* power steps when lipschitz <= 0                        */
+  int32_t ista;          /* 1: momentum off                                        */
+  int32_t reserved;      /* must be 0                                              */
+  double lipschitz;      /* > 0: L_A to use; <= 0: power iteration from power_v0   */
+  double kappa;          /* >= 0: balance weight; < 0: kappa = L_A                 */
+  double lambda_scale;   /* factor on the sigma/2 rule (1 = the paper's)           */
+  const float *power_v0; /* device [R] complex64 power-iteration start             */
+  const double *lambda;  /* device [B][3J+1] weights, or NULL for the sigma/2 rule */
+  double *scalars;       /* device output (see above), or NULL                     */
+} expenc_balanced_opts;
+
+size_t expenc_swt_workspace_size(int32_t nx, int32_t ny, int32_t levels, int32_t batch);
+int swt_fwd(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch, const float *x, float *w,
+            void *ws, size_t ws_bytes, void *stream);
+int swt_inv(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch, const float *w, float *x,
+            void *ws, size_t ws_bytes, void *stream);
+size_t expenc_sigma_workspace_size(int32_t nx, int32_t ny, int32_t levels, int32_t batch);
+int expenc_sigma_weights(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w, double scale,
+                         double *lam, unsigned *counts, void *ws, size_t ws_bytes, void *stream);
+size_t fista_balanced_workspace_size(const expenc_op *op, int32_t batch, const expenc_balanced_opts *opts);
+int fista_balanced_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
+                         const expenc_balanced_opts *opts, void *ws, size_t ws_bytes, void *stream);
+
+/*
  * Least-squares reconstruction by conjugate gradients on A^H A x = A^H y
  * from x = 0, stopped after n_iter iterations (Methods 2.1: early stopping
  * at 20 iterations as implicit regularisation).  Uses opts->n_iter and

@@ -52,6 +52,17 @@ class FistaOpts(ctypes.Structure):
     ]
 
 
+class BalancedOpts(ctypes.Structure):
+    _fields_ = [
+        ("n_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("wavelet", ctypes.c_int32), ("levels", ctypes.c_int32),
+        ("refine_every", ctypes.c_int32), ("n_power", ctypes.c_int32),
+        ("ista", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("lipschitz", ctypes.c_double), ("kappa", ctypes.c_double), ("lambda_scale", ctypes.c_double),
+        ("power_v0", _vp), ("lambda_", _vp), ("scalars", _vp),
+    ]
+
+
 # name -> (restype, argtypes); every symbol include/expenc.h declares
 SIGNATURES = {
     "expenc_sh_basis": (ctypes.c_int, [_c_int, _c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -79,6 +90,16 @@ SIGNATURES = {
     "expenc_coil_workspace_size": (ctypes.c_size_t, [_c_int, ctypes.c_int64]),
     "expenc_prewhiten": (ctypes.c_int, [_c_int, _vp, ctypes.c_int64, _vp, _c_int, _vp, _vp, ctypes.c_size_t, _vp]),
     "expenc_coil_compress": (ctypes.c_int, [_c_int, _c_int, ctypes.c_int64, _vp, _c_int, _vp, _vp, _vp, _vp, _vp,
+                                            _vp, ctypes.c_size_t, _vp]),
+    "expenc_swt_workspace_size": (ctypes.c_size_t, [_c_int, _c_int, _c_int, _c_int]),
+    "swt_fwd": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "swt_inv": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "expenc_sigma_workspace_size": (ctypes.c_size_t, [_c_int, _c_int, _c_int, _c_int]),
+    "expenc_sigma_weights": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _vp, ctypes.c_double, _vp, _vp, _vp,
+                                            ctypes.c_size_t, _vp]),
+    "fista_balanced_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(ExpencOp), _c_int,
+                                                        ctypes.POINTER(BalancedOpts)]),
+    "fista_balanced_solve": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _vp, _vp, ctypes.POINTER(BalancedOpts),
                                             _vp, ctypes.c_size_t, _vp]),
     "expenc_set_tuning": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int, _c_int]),
     "expenc_plan_info": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int,

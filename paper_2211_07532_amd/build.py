@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libexpenc.so")
-SOURCES = ["encode.hip", "split.hip", "wavelet.hip", "api.hip", "fista.hip", "grad.hip", "coils.hip"]
+SOURCES = ["encode.hip", "split.hip", "wavelet.hip", "api.hip", "fista.hip", "grad.hip", "coils.hip", "balanced.hip"]
 ARCH = "gfx950"
 
 

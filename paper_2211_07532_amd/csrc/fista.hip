@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <mutex>
 #include <vector>
 
@@ -243,6 +244,12 @@ static int run_graph(uint64_t key, hipStream_t s, Body body) {
   g_graphs.push_back({key, dev, exec, s});
   return EXPENC_OK;
 }
+
+// Shared with the other graph-captured solvers.
+int run_captured(uint64_t key, hipStream_t s, const std::function<int(hipStream_t)> &body) {
+  return run_graph(key, s, body);
+}
+uint64_t hash_bytes(uint64_t h, const void *p, size_t n) { return fnv(h, p, n); }
 
 // ---------------------------------------------------------------------------
 // FISTA for a group of P problems of identical shape (P = 1 for

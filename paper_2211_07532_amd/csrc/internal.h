@@ -3,6 +3,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <functional>
+
 #include <cstddef>
 #include <cstdint>
 
@@ -119,6 +121,11 @@ struct EncBuffers {
 size_t enc_operand_bytes(const EncPlan &p);
 // Split-K partial-sum elements (float2) a plan needs.
 size_t enc_part_elems(const EncPlan &p);
+// Runs body(stream) captured into a cached HIP graph keyed by `key` (or
+// eagerly when graphs are disabled), launched on s.
+int run_captured(uint64_t key, hipStream_t s, const std::function<int(hipStream_t)> &body);
+uint64_t hash_bytes(uint64_t h, const void *p, size_t n);
+
 // Autotuner overrides of the contraction workgroup targets (0 = default).
 int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target);
 uint64_t tuning_generation();

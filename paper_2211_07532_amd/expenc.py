@@ -281,6 +281,97 @@ def coil_compress(y: torch.Tensor, nvirtual: int, smaps: Optional[torch.Tensor] 
     return yv, sv, w, v
 
 
+def _swt_ws(nx, ny, levels, batch, device):
+    n = _b.lib().expenc_swt_workspace_size(nx, ny, levels, batch)
+    if n == 0:
+        raise _b.ExpencError(_b.EXPENC_EINVAL, "expenc_swt_workspace_size")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def swt_fwd(x: torch.Tensor, levels: int, wavelet="db4") -> torch.Tensor:
+    """Undecimated wavelet coefficients [..., 3J+1, ny, nx] of x [..., ny, nx] (complex64)."""
+    xb = x.reshape((-1,) + tuple(x.shape[-2:]))
+    _need(xb, torch.complex64, "x", x.device)
+    B, ny, nx = xb.shape
+    w = torch.empty((B, 3 * levels + 1, ny, nx), dtype=torch.complex64, device=x.device)
+    ws = _swt_ws(nx, ny, levels, B, x.device)
+    check(_b.lib().swt_fwd(nx, ny, levels, _wav(wavelet), B, _ptr(xb), _ptr(w), _ptr(ws), ws.numel(),
+                           _stream(x.device)), "swt_fwd")
+    return w.reshape(tuple(x.shape[:-2]) + tuple(w.shape[1:]))
+
+
+def swt_inv(w: torch.Tensor, levels: int, wavelet="db4") -> torch.Tensor:
+    """W^H: image [..., ny, nx] from coefficients [..., 3J+1, ny, nx]."""
+    wb = w.reshape((-1,) + tuple(w.shape[-3:]))
+    _need(wb, torch.complex64, "w", w.device)
+    B, nb, ny, nx = wb.shape
+    if nb != 3 * levels + 1:
+        raise ValueError(f"expected {3 * levels + 1} bands, got {nb}")
+    x = torch.empty((B, ny, nx), dtype=torch.complex64, device=w.device)
+    ws = _swt_ws(nx, ny, levels, B, w.device)
+    check(_b.lib().swt_inv(nx, ny, levels, _wav(wavelet), B, _ptr(wb), _ptr(x), _ptr(ws), ws.numel(),
+                           _stream(w.device)), "swt_inv")
+    return x.reshape(tuple(w.shape[:-3]) + (ny, nx))
+
+
+def sigma_weights(w: torch.Tensor, levels: int, scale: float = 1.0, counts: bool = False):
+    """Per-band weights [B][3J+1] (float64) by the sigma/2 rule from undecimated
+    coefficients w [B][3J+1][ny][nx]; with counts=True also the histograms [B][J][256]."""
+    wb = w.reshape((-1,) + tuple(w.shape[-3:]))
+    _need(wb, torch.complex64, "w", w.device)
+    B, nb, ny, nx = wb.shape
+    lam = torch.empty((B, nb), dtype=torch.float64, device=w.device)
+    cnt = torch.empty((B, levels, 256), dtype=torch.int32, device=w.device) if counts else None
+    n = _b.lib().expenc_sigma_workspace_size(nx, ny, levels, B)
+    ws = torch.empty(n, dtype=torch.uint8, device=w.device)
+    check(_b.lib().expenc_sigma_weights(nx, ny, levels, B, _ptr(wb), float(scale), _ptr(lam), _ptr(cnt), _ptr(ws),
+                                        ws.numel(), _stream(w.device)), "expenc_sigma_weights")
+    return (lam, cnt) if counts else lam
+
+
+@dataclasses.dataclass
+class BalancedResult:
+    x: torch.Tensor           # [B][ny][nx] (or [ny][nx])
+    lipschitz_a: float        # L_A = 2 lambda_max(A^H A)
+    kappa: float
+    lam: torch.Tensor         # [B][3J+1]
+
+
+def fista_balanced(y: torch.Tensor, op: Operator, n_iter: int, levels: int = 1, wavelet="db4", precision="fp32",
+                   lipschitz: float = 0.0, kappa: float = -1.0, lam: Optional[torch.Tensor] = None,
+                   lambda_scale: float = 1.0, power_v0=None, n_power: int = 30, ista: bool = False,
+                   refine_every: int = 0) -> BalancedResult:
+    """Balanced FISTA with the undecimated wavelet (see fista_balanced_solve in include/expenc.h)."""
+    single = y.dim() == 2
+    yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
+    _need(yb, torch.complex64, "y", op.device)
+    B = yb.shape[0]
+    nb = 3 * levels + 1
+    if lipschitz <= 0 and power_v0 is None:
+        raise ValueError("lipschitz <= 0 needs power_v0 (the seeded start vector)")
+    x = torch.empty((B, op.ny, op.nx), dtype=torch.complex64, device=op.device)
+    sc = torch.zeros(3 + 2 * B * nb, dtype=torch.float64, device=op.device)
+    if lam is not None:
+        lam = _need(lam.reshape(B, nb).contiguous(), torch.float64, "lam", op.device)
+    opts = _b.BalancedOpts(n_iter, _prec(precision), _wav(wavelet), levels, refine_every, n_power, int(ista), 0,
+                           float(lipschitz), float(kappa), float(lambda_scale),
+                           None if power_v0 is None else _need(power_v0, torch.complex64, "power_v0",
+                                                               op.device).data_ptr(),
+                           None if lam is None else lam.data_ptr(), sc.data_ptr())
+    n = _b.lib().fista_balanced_workspace_size(ctypes.byref(op._c), B, ctypes.byref(opts))
+    if n == 0:
+        raise _b.ExpencError(_b.EXPENC_EINVAL, "fista_balanced_workspace_size")
+    key = ("balanced", B, _prec(precision), levels)
+    ws = op._ws.get(key)
+    if ws is None or ws.numel() < n:
+        ws = torch.empty(n, dtype=torch.uint8, device=op.device)
+        op._ws[key] = ws
+    check(_b.lib().fista_balanced_solve(ctypes.byref(op._c), B, _ptr(yb), _ptr(x), ctypes.byref(opts), _ptr(ws),
+                                        ws.numel(), _stream(op.device)), "fista_balanced_solve")
+    s = sc.cpu()
+    return BalancedResult(x[0] if single else x, float(s[0]), float(s[1]), s[3:3 + B * nb].reshape(B, nb))
+
+
 _batch_ws = {}
 
 

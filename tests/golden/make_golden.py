@@ -4,7 +4,8 @@ with a 3-level db4 wavelet; L from 20 power steps from the seeded start
 vector; lambda = 1e-3 max|A^H y|) to mm15_fista.npz.  Calls only the oracle
 and the seeded input generator.  Takes several minutes on 8 cores.
 
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py            # FISTA golden (mm15_fista.npz)
+    python tests/golden/make_golden.py balanced   # balanced-FISTA golden (mm15_balanced.npz)
 """
 import os
 import sys
@@ -39,5 +40,27 @@ def main():
     print(f"wrote mm15_fista.npz: L={L:.6e} lambda={lam:.6e} ({time.time() - t0:.0f} s)")
 
 
+def main_balanced():
+    """The paper's regulariser on the same problem: undecimated db4 with one
+    level, sigma/2 weights from W A^H y, balanced FISTA with kappa = L_A,
+    50 iterations; L_A from the FISTA golden file."""
+    from oracle import balanced as bal
+    w = synth.MM15
+    p = synth.make_problem(w)
+    basis = encoding.sh_basis(w.n, w.fov, w.z0, w.nbasis)
+    op = solve.Operator(c64(p.smaps), p.coef, p.time, basis, p.dw0, w.n)
+    t0 = time.time()
+    y = c64(op.A(c64(p.x_noisy)))
+    L_A = float(np.load(os.path.join(HERE, "mm15_fista.npz"))["lipschitz"])
+    lam = bal.sigma_weights(bal.swt2(op.AH(y).reshape(w.n, w.n), 1, "db4"), 1)
+    x = bal.fista(op, y, L_A, L_A, lam, 50, 1, "db4")
+    np.savez_compressed(os.path.join(HERE, "mm15_balanced.npz"), x_hat=x.astype(np.complex128), lipschitz=L_A,
+                        lam=lam, n_iter=50, levels=1)
+    print(f"wrote mm15_balanced.npz: L_A={L_A:.6e} lambda={lam} ({time.time() - t0:.0f} s)")
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "balanced":
+        main_balanced()
+    else:
+        main()
