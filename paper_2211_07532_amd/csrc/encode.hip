@@ -34,7 +34,6 @@
 
 namespace expenc {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 static constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
 
@@ -265,7 +264,6 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
   kap += pz * Tp * NT;
   bet += (int64_t)pz * Rp * NT;
   yop += pz * Tp * NCP;
-  part += pz * nsplit * (int64_t)Rp * NCP * 2;
 
   double bv[NT];
 #pragma unroll
@@ -313,17 +311,7 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
     }
   }
 
-  float *dst = part + (int64_t)split * Rp * NCP * 2;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int g = 0; g < GW; ++g)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) {
-        const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
-        const int col = (g0 + g) * 16 + c16;
-        dst[(row * NCP + col) * 2 + im] = acc[a][g][v];
-      }
+  adj_epilogue<GW>(part, nullptr, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -437,6 +425,43 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
   }
 }
 
+// Single image: x(r) = alpha * (sum over splits and column blocks of the
+// coil-combined partial images at row (r / nx) * nxq + r % nx), with the
+// same base / add terms as k_adj_reduce_out.  One thread per pixel.
+__global__ void k_adj_reduce_comb(const float2 *__restrict__ part, int nslice, int R, int Rp, int nx,
+                                  float2 *__restrict__ x, int x_row_stride, const double *__restrict__ alpha_dev,
+                                  const float2 *__restrict__ add, const float2 *__restrict__ base, int nxq,
+                                  int64_t x_pstride) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int pz = blockIdx.y;  // problem
+  part += (int64_t)pz * nslice * Rp;
+  x += pz * x_pstride;
+  if (alpha_dev) alpha_dev += pz;
+  if (add) add += pz * x_pstride;
+  if (base) base += pz * x_pstride;
+  const int yy = r / nx, xx = r % nx;
+  const int64_t rq = (int64_t)yy * nxq + xx;
+  double sx = 0.0, sy = 0.0;
+  for (int k = 0; k < nslice; ++k) {
+    const float2 v = part[(int64_t)k * Rp + rq];
+    sx += v.x;
+    sy += v.y;
+  }
+  const int64_t o = (int64_t)yy * x_row_stride + xx;
+  if (base) {
+    sx += base[o].x;
+    sy += base[o].y;
+  }
+  const double alpha = alpha_dev ? *alpha_dev : 1.0;
+  float2 v = make_float2((float)(alpha * sx), (float)(alpha * sy));
+  if (add) {
+    v.x += add[o].x;
+    v.y += add[o].y;
+  }
+  x[o] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -543,6 +568,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.G = (int32_t)ceil_div(q.NC, 16);
   q.GW = q.G >= 2 ? 2 : 1;
   q.NGY = (int32_t)ceil_div(q.G, q.GW);
+  q.comb = (batch == 1 && precision != EXPENC_FP32);
   q.NCP = q.NGY * q.GW * 16;  // every wave's column groups exist (zero-filled past NC)
   q.L = op->nbasis;
   q.NT = phase_terms(q.L);
@@ -581,7 +607,7 @@ size_t enc_operand_bytes(const EncPlan &p) {
 
 size_t enc_part_elems(const EncPlan &p) {
   const size_t pf = (size_t)p.fwd_split * p.Tp * p.NCP;
-  const size_t pa = (size_t)p.adj_split * p.Rp * p.NCP;
+  const size_t pa = (size_t)p.adj_split * p.Rp * (p.comb ? p.NGY : p.NCP);
   return std::max(pf, pa) * p.P;
 }
 
@@ -595,6 +621,7 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
   if (p.prec != EXPENC_FP32) {
     b->zs = a.take<char>(P * p.Rp * (p.NCP / 16) * 256);
     b->ys = a.take<char>(P * p.Tp * (p.NCP / 16) * 256);
+    if (p.comb) b->sq = a.take<float2>(P * p.Rp * p.NCP);
     if (p.sh) {
       b->pmono = a.take<double>(P * p.Tp * 12);
       b->dpa = a.take<float>(P * p.Tp * 16);
@@ -766,6 +793,7 @@ int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 }
 
 int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  if (p.comb && !b.sq) return fail(EXPENC_EINVAL, "coil table of a single-image split plan is not carved");
   timed(1, s, [&] {
     if (p.prec != EXPENC_FP32) {
       split_adjoint_launch(p, b, s);
@@ -798,6 +826,12 @@ int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_
 int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
                            int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
                            const float2 *add, hipStream_t s, const float2 *base, int64_t x_pstride) {
+  if (p.comb) {
+    k_adj_reduce_comb<<<grid_p(p.R, 256, p.P), 256, 0, s>>>(b.part, p.adj_split * p.NGY, p.R, p.Rp, p.nx, x,
+                                                            x_row_stride, alpha_dev, add, base, p.nxq, x_pstride);
+    EX_LAUNCHED("adjoint reduce");
+    return EXPENC_OK;
+  }
   k_adj_reduce_out<<<grid_p(p.R, 8, p.P), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
                                                        reinterpret_cast<const float2 *>(smaps), x, x_stride,
                                                        x_row_stride, alpha_dev, add, base, p.nxq, x_pstride);

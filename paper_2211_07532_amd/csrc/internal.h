@@ -74,6 +74,93 @@ __device__ inline bool split_tile(int nrb, int nsplit, int *split, int *rb) {
 }
 inline unsigned split_grid(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
 
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Coil combination in the epilogue of the split adjoint contractions (single
+// image per operator).  The adjoint of the multi-coil encoding ends in
+// x(r) = sum_c conj(S_c(r)) u_c(r); a workgroup holds u_c(r) of its sample
+// chunk for 256 pixel rows and its 16*GW coil columns in the MFMA output
+// layout (lane: column 16g + l%16, part l/16 & 1 = Re/Im; element v of block
+// a: row 32a + 8(v/4) + 4(l/32) + v%4).  sq holds S_c(r) in the same
+// [row][column] layout (zero on padding rows and columns), so each load
+// instruction reads two contiguous 128-byte row segments; a 32-row block's
+// loads are all issued before their first use, so the epilogue waits for
+// memory twice.  For each 32-row block a lane forms its share of conj(S) u (16 rows
+// x Re/Im), then the 32 lanes of each half-wave sum those 32 values by
+// recursive halving (xor 16, 8, 4, 2, 1: at each stage a lane keeps one half
+// of its values and adds the partner's copy of that half), so that lane l
+// ends with part l%2 of row element v = (l%32)/2, and the wave stores its 32
+// rows as one contiguous 256-byte segment.
+template <int GW>
+__device__ inline void store_combined(float *__restrict__ dst, const float2 *__restrict__ sq, int NCP, int64_t row0,
+                                      int g0, int lane, f32x16 (&acc)[2][GW]) {
+  const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    float2 sv[2][16][GW];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+#pragma unroll
+      for (int g = 0; g < GW; ++g) sv[a][v][g] = sq[row * NCP + (g0 + g) * 16 + c16];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    float val[32];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      float re = 0.f, ii = 0.f;
+#pragma unroll
+      for (int g = 0; g < GW; ++g) {
+        const float u = acc[a][g][v];
+        // conj(S) u: Re = Sr ur + Si ui, Im = Sr ui - Si ur
+        re = fmaf(im ? sv[a][v][g].y : sv[a][v][g].x, u, re);
+        ii = fmaf(im ? sv[a][v][g].x : -sv[a][v][g].y, u, ii);
+      }
+      val[2 * v] = re;
+      val[2 * v + 1] = ii;
+    }
+#pragma unroll
+    for (int o = 16, n = 32; o > 0; o >>= 1, n >>= 1) {
+      const bool up = (lane & o) != 0;
+#pragma unroll
+      for (int i = 0; i < n / 2; ++i) {
+        const float keep = up ? val[i + n / 2] : val[i];
+        const float send = up ? val[i] : val[i + n / 2];
+        val[i] = keep + __shfl_xor(send, o);
+      }
+    }
+    const int k = lane & 31, v = k >> 1;
+    const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+    dst[row * 2 + (k & 1)] = val[0];
+  }
+}
+
+// End of an adjoint contraction workgroup: with sq (single image, split
+// forms) the coil-combined partial image of (problem pz, split, column block
+// y) goes to part as float2 [P][nsplit][NGY][Rp]; without, the per-coil
+// accumulators go to [P][nsplit][Rp][NCP] complex.
+template <int GW>
+__device__ inline void adj_epilogue(float *part, const float2 *sq, int Rp, int NCP, int nsplit, int split, int pz,
+                                    int64_t row0, int g0, int lane, f32x16 (&acc)[2][GW]) {
+  if (sq) {
+    const int64_t slice = ((int64_t)pz * nsplit + split) * gridDim.y + blockIdx.y;
+    store_combined<GW>(part + slice * Rp * 2, sq + (int64_t)pz * Rp * NCP, NCP, row0, g0, lane, acc);
+    return;
+  }
+  const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+  float *dst = part + ((int64_t)pz * nsplit + split) * Rp * NCP * 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        const int col = (g0 + g) * 16 + c16;
+        dst[(row * NCP + col) * 2 + im] = acc[a][g][v];
+      }
+}
+
 struct EncPlan {
   int32_t nx = 0, ny = 0, R = 0, Rp = 0;  // pixels, padded to a multiple of 256
   int64_t T = 0, Tp = 0;                  // samples, padded to a multiple of 256
@@ -84,6 +171,10 @@ struct EncPlan {
   int32_t prec = 0;
   int32_t fwd_split = 1, fwd_chunk = 0;   // split-K over pixels
   int32_t adj_split = 1, adj_chunk = 0;   // split-K over samples
+  // split forms with a single image (B == 1): the adjoint contraction
+  // combines its coils in the epilogue and writes [adj_split][NGY][Rp]
+  // partial images instead of [adj_split][Rp][NCP] per-coil partials
+  bool comb = false;
   bool has_dw0 = false;
   // Solid-harmonic basis given by grid geometry (EXPENC_BASIS_SH).  Split
   // forms with it lay pixels out row-padded: r' = y*nxq + x, nxq = nx rounded
@@ -116,6 +207,7 @@ struct EncBuffers {
   float *dpa = nullptr;    // split + SH: [Tp/32][64][8] adjoint increment operand (FP32)
   double *dwq = nullptr;   // split + SH: [Rp] dw0/2pi in the row-padded pixel layout
   float *ddw = nullptr;    // split + SH: [Rp] dwq minus its 16-pixel tile centre (FP32)
+  float2 *sq = nullptr;    // split, single image: [Rp][NCP] S_c(r) in the partial-sum layout (0 on padding)
 };
 
 size_t enc_operand_bytes(const EncPlan &p);

@@ -22,7 +22,6 @@
 
 namespace expenc {
 
-typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
@@ -226,7 +225,7 @@ template <int NT, int GW, bool BF>
 __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ kap, const double *__restrict__ bet,
                                                    const float *__restrict__ dkap, const u32x4 *__restrict__ ys,
                                                    float *__restrict__ part, int Rp, int64_t Tp, int NCP, int chunk,
-                                                   int nsplit) {
+                                                   int nsplit, const float2 *__restrict__ sq) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
@@ -239,7 +238,6 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
   dkap += pz * Tp * NT;
   bet += (int64_t)pz * Rp * NT;
   ys += pz * Tp * NGP * 16;
-  part += pz * nsplit * (int64_t)Rp * NCP * 2;
   double bv[NT];
   float bf[NT];
 #pragma unroll
@@ -267,7 +265,7 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
       acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
     }
   }
-  store_partials<GW>(part + (int64_t)split * Rp * NCP * 2, row0, NCP, g0, lane, acc);
+  adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
 }
 
 
@@ -368,7 +366,8 @@ template <int GW, bool BF>
 __global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__ pmono, const float *__restrict__ dpa,
                                                       const double *__restrict__ dwq, const u32x4 *__restrict__ ys,
                                                       float *__restrict__ part, int Rp, int64_t Tp, int NCP, int chunk,
-                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy) {
+                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy,
+                                                      const float2 *__restrict__ sq) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int hl = lane >> 5, jl = lane & 31;
@@ -382,7 +381,6 @@ __global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__
   dpa += pz * Tp * 16;
   dwq += (int64_t)pz * Rp;
   ys += pz * Tp * NGP * 16;
-  part += pz * nsplit * (int64_t)Rp * NCP * 2;
   // this lane's pixel in each 32-row block, and its B operand of the
   // increment product: the monomial (or dw0) of term 2J + hl
   double xg[2], yg[2], wg[2];
@@ -471,7 +469,7 @@ __global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__
       }
     }
   }
-  store_partials<GW>(part + (int64_t)split * Rp * NCP * 2, row0, NCP, g0, lane, acc);
+  adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -684,8 +682,29 @@ __global__ void k_prep_dwq(const double *__restrict__ dw0, int nx, int ny, int n
   dwq[rq] = v;
 }
 
+// sq[row][col] = S_col(r) at pixel r = (row / nxq) * nx + row % nxq (the
+// adjoint partial-sum layout), zero on padding rows and columns.
+__global__ void k_prep_sq(const float2 *__restrict__ smaps, int nx, int ny, int nxq, int Rp, int C, int NCP,
+                          float2 *__restrict__ sq) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)Rp * NCP) return;
+  const int pz = blockIdx.y;  // problem
+  const int R = nx * ny;
+  const int row = (int)(i / NCP), col = (int)(i % NCP);
+  const int yy = row / nxq, xx = row % nxq;
+  float2 v = make_float2(0.f, 0.f);
+  if (col < C && xx < nx && yy < ny) v = smaps[((int64_t)pz * C + col) * R + yy * nx + xx];
+  sq[(int64_t)pz * Rp * NCP + i] = v;
+}
+
 int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
   auto gp = [&](int64_t n) { return dim3((unsigned)ceil_div(n, 256), (unsigned)p.P); };
+  if (p.comb) {
+    if (!b.sq) return fail(EXPENC_EINVAL, "coil table of a single-image split plan is not carved");
+    k_prep_sq<<<gp((int64_t)p.Rp * p.NCP), 256, 0, s>>>(reinterpret_cast<const float2 *>(op->smaps), p.nx, p.ny,
+                                                          p.nxq, p.Rp, p.C, p.NCP, b.sq);
+    EX_LAUNCHED("coil table");
+  }
   if (p.sh) {
     k_prep_pmono<<<gp(p.Tp), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), p.z0s, b.pmono);
     EX_LAUNCHED("monomial coefficients");
@@ -726,12 +745,13 @@ static void launch_adj_split(const EncPlan &p, const EncBuffers &b, hipStream_t 
   dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
+  const float2 *sm = p.comb ? b.sq : nullptr;
   if (p.GW == 2)
     k_adj_split<NT, 2, BF><<<grid, 256, 0, s>>>(b.kap, b.bet, b.dkap, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                                p.adj_split);
+                                                p.adj_split, sm);
   else
     k_adj_split<NT, 1, BF><<<grid, 256, 0, s>>>(b.kap, b.bet, b.dkap, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                                p.adj_split);
+                                                p.adj_split, sm);
 }
 
 template <bool BF>
@@ -770,12 +790,13 @@ static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
+  const float2 *sm = p.comb ? b.sq : nullptr;
   if (p.GW == 2)
     k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy, sm);
   else
     k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy, sm);
 }
 
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
