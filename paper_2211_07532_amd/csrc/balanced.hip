@@ -343,7 +343,7 @@ int check_bal(const expenc_balanced_opts *o, int *refine) {
     return fail(EXPENC_EINVAL, "lipschitz <= 0 requires power_v0 and n_power >= 1");
   if (!o->lambda && !(o->lambda_scale > 0)) return fail(EXPENC_EINVAL, "lambda_scale must be > 0");
   if (o->reserved != 0) return fail(EXPENC_EINVAL, "reserved field must be 0");
-  *refine = o->refine_every > 0 ? o->refine_every : 10;
+  *refine = o->refine_every > 0 ? o->refine_every : default_refine(o->precision);
   return EXPENC_OK;
 }
 
@@ -414,7 +414,7 @@ extern "C" size_t fista_balanced_workspace_size(const expenc_op *op, int32_t bat
 
 extern "C" int fista_balanced_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
                                     const expenc_balanced_opts *opts, void *ws, size_t ws_bytes, void *stream) {
-  int refine = 10;
+  int refine = 0;
   EX_TRY(check_bal(opts, &refine));
   if (!y || !x) return fail(EXPENC_EINVAL, "y or x is NULL");
   BalLayout L;

@@ -336,7 +336,7 @@ static int check_fista_opts(const expenc_fista_opts *o, int *eff_refine) {
   if (o->lipschitz <= 0 && (!o->power_v0 || o->n_power < 1))
     return fail(EXPENC_EINVAL, "lipschitz <= 0 requires power_v0 and n_power >= 1");
   if (o->lambda < 0 && !(o->lambda_factor > 0)) return fail(EXPENC_EINVAL, "lambda < 0 requires lambda_factor > 0");
-  *eff_refine = o->refine_every > 0 ? o->refine_every : 10;
+  *eff_refine = o->refine_every > 0 ? o->refine_every : default_refine(o->precision);
   return EXPENC_OK;
 }
 
@@ -348,7 +348,7 @@ struct FistaGroup {
   FilterSet f;
   const expenc_fista_opts *opts = nullptr;
   const float2 *y = nullptr;      // [P][B][T][C]
-  int refine = 10;
+  int refine = 0;
   std::vector<double> beta;
 
   int prologue(hipStream_t s) {
@@ -468,7 +468,7 @@ using namespace expenc;
 
 extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
                            const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream) {
-  int refine = 10;
+  int refine = 0;
   EX_TRY(check_fista_opts(opts, &refine));
   if (!y || !x) return fail(EXPENC_EINVAL, "y or x is NULL");
   FistaGroup G;
@@ -696,7 +696,7 @@ static hipStream_t fork_stream(int device, int k) {
 
 extern "C" size_t fista_batched_workspace_size(int32_t nprob, const expenc_op *ops, int32_t batch,
                                                const expenc_fista_opts *opts) {
-  int refine = 10;
+  int refine = 0;
   if (check_fista_opts(opts, &refine) != EXPENC_OK) return 0;
   Arena a;
   BatchPlan bp;
@@ -707,7 +707,7 @@ extern "C" size_t fista_batched_workspace_size(int32_t nprob, const expenc_op *o
 extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t batch, const float *const *y,
                                    float *const *x, const expenc_fista_opts *opts, void *ws, size_t ws_bytes,
                                    void *stream) {
-  int refine = 10;
+  int refine = 0;
   EX_TRY(check_fista_opts(opts, &refine));
   if (!y || !x) return fail(EXPENC_EINVAL, "y or x pointer array is NULL");
   for (int i = 0; i < nprob; ++i)

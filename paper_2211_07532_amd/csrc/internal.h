@@ -219,6 +219,11 @@ int run_captured(uint64_t key, hipStream_t s, const std::function<int(hipStream_
 uint64_t hash_bytes(uint64_t h, const void *p, size_t n);
 
 // Autotuner overrides of the contraction workgroup targets (0 = default).
+// Default FP32 anchor cadence of the split forms' anchored gradient: the
+// error of a split step scales with the form's product precision (fp16
+// halves: 22 bits, bf16 halves: 16 bits) times ||z - z_ref||, so the fp16
+// form refreshes its anchor less often.
+inline int default_refine(int32_t precision) { return precision == EXPENC_FP16_SPLIT ? 50 : 25; }
 int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target);
 uint64_t tuning_generation();
 // Carves the buffers of plan p; the partial-sum buffer gets at least
