@@ -1,7 +1,8 @@
 """Full-size solve parity: the 1.5 mm workload (148 x 148, 32 coils,
 T = 16384, 16 field terms + dB0, 50 FISTA iterations, db4 J = 3) on the GPU
 against the FP64 oracle's reconstruction stored in tests/golden/mm15_fista.npz
-(written by tests/golden/make_golden.py, which calls only the oracle).
+(written by tests/golden/make_golden.py, which calls only the oracle), and
+the balanced-FISTA solve with the paper's regulariser against mm15_balanced.npz.
 Bars: NRMSE <= 1e-5 for the FP32 form, <= 1e-4 for the split forms with FP32
 anchors; L and lambda from the device rules within 1e-5."""
 import os
@@ -41,4 +42,35 @@ def test_full_size_fista_matches_golden(mm15, prec):
           f"lambda {res.lam[0]:.6e} (ref {float(g['lam']):.6e})", flush=True)
     assert abs(res.lipschitz - float(g["lipschitz"])) <= 1e-5 * float(g["lipschitz"])
     assert abs(res.lam[0] - float(g["lam"])) <= 1e-5 * float(g["lam"])
+    assert e <= (1e-5 if prec == "fp32" else 1e-4)
+
+
+BALANCED = os.path.join(os.path.dirname(__file__), "golden", "mm15_balanced.npz")
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_full_size_balanced_matches_golden(mm15, prec):
+    """The paper's regulariser at full size: undecimated db4 (one level),
+    sigma/2 weights, balanced FISTA with kappa = L_A, 50 iterations, against
+    the FP64 oracle's solve in tests/golden/mm15_balanced.npz (L_A and the
+    weights passed in).  The device's own weight rule (FP32 W A^H y) must land
+    within one histogram bin of the oracle's."""
+    import torch
+    import paper_2211_07532_amd as ee
+    from oracle import balanced as bal
+    if not os.path.exists(BALANCED):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py balanced")
+    w, case, y, _ = mm15
+    g = np.load(BALANCED)
+    L_A, levels, n_iter = float(g["lipschitz"]), int(g["levels"]), int(g["n_iter"])
+    res = ee.fista_balanced(case.to_dev(y), case.op, n_iter, levels, "db4", precision=prec, lipschitz=L_A,
+                            lam=torch.from_numpy(np.ascontiguousarray(g["lam"])).cuda())
+    e = solve.nrmse(res.x.cpu().numpy().reshape(-1), g["x_hat"].reshape(-1))
+    op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
+    coefs = bal.swt2(op.AH(y).reshape(w.n, w.n), levels, "db4")
+    width = 4.0 * np.mean(np.abs(coefs[:3])) / 256
+    dev = ee.fista_balanced(case.to_dev(y), case.op, 0, levels, "db4", lipschitz=L_A)
+    dl = abs(dev.lam.numpy()[0][0] - float(g["lam"][0])) / (0.5 * width)
+    print(f"golden balanced {prec}: NRMSE {e:.2e}, device sigma/2 weight within {dl:.2f} bins", flush=True)
+    assert dl <= 1.0 + 1e-6
     assert e <= (1e-5 if prec == "fp32" else 1e-4)
