@@ -82,10 +82,11 @@ __global__ __launch_bounds__(256) void k_resid_norm_part(const float2 *__restric
   if (threadIdx.x == 0) part[b * gridDim.x + blockIdx.x] = red[0];
 }
 
-// objective[b*K + k] = data[b] + lambda[b] * sum_{level, blk} l1[level][b][blk]
-// (level j wrote ceil((nxp >> j)/16) block sums out of nblk slots)
+// objective[b*K + k] = data[b] + lambda[b] * sum_{level, tile} l1[level][b][tile]
+// (level j wrote ceil(hx_j/16) * ceil(hy_j/8) tile sums out of nblk slots,
+// hx_j = (nxp >> j)/2, hy_j = (nyp >> j)/2)
 __global__ __launch_bounds__(256) void k_objective(const double *__restrict__ data, const double *__restrict__ l1,
-                                                   int levels, int B, int nblk, int nxp,
+                                                   int levels, int B, int nblk, int nxp, int nyp,
                                                    const double *__restrict__ lam, double *__restrict__ obj, int K,
                                                    int k) {
   __shared__ double red[256];
@@ -93,7 +94,8 @@ __global__ __launch_bounds__(256) void k_objective(const double *__restrict__ da
   double s = 0.0;
   for (int i = threadIdx.x; i < levels * nblk; i += blockDim.x) {
     const int lev = i / nblk, blk = i % nblk;
-    if (blk < (((nxp >> lev) + 15) >> 4)) s += l1[((int64_t)lev * B + b) * nblk + blk];
+    const int tiles = (((nxp >> lev) / 2 + 15) / 16) * (((nyp >> lev) / 2 + 7) / 8);
+    if (blk < tiles) s += l1[((int64_t)lev * B + b) * nblk + blk];
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -312,7 +314,7 @@ static int layout_fista(const expenc_op *op, int32_t nprob, int32_t batch, int32
   L->ptmp = a.take<float2>((size_t)L->p.R * nprob);
   L->dpart = a.take<double>((size_t)nprob * batch * kRedBlocks);
   L->sc = a.take<double>((size_t)2 * nprob + 2 * nprob * batch + 3 * nprob + 8);
-  L->l1_blocks = (int)ceil_div(L->nxp, 16);
+  L->l1_blocks = dwt2_tiles(L->nxp, L->nyp, 0);
   if (objective) {
     L->l1 = a.take<double>((size_t)levels * batch * L->l1_blocks);
     L->data = a.take<double>((size_t)batch);
@@ -433,9 +435,10 @@ struct FistaGroup {
         if (padded) EX_TRY(copy_f2(L.z, L.v, all, cs));
         EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, L.gref, pimg));
       }
-      EX_TRY(dwt_forward_levels(f, nxp, nyp, opts->levels, P * B, L.v, L.w, L.tau(), with_obj ? L.l1 : nullptr,
-                                L.l1_blocks, cs));
-      EX_TRY(dwt_inverse_levels(f, nxp, nyp, opts->levels, P * B, L.w, xk, xprev, L.z, beta[k], cs));
+      // x_k = W^H S_tau(W v), z = x_k + beta_k (x_k - x_{k-1}); v and x_k serve
+      // as the transform's ping-pong buffers
+      EX_TRY(dwt2_prox(f, nxp, nyp, opts->levels, P * B, L.v, L.w, xk, xprev, L.z, beta[k], L.tau(),
+                       with_obj ? L.l1 : nullptr, L.l1_blocks, cs));
       if (with_obj) {
         EX_TRY(enc_build_z(pf, op->smaps, xk, img, nxp, L.eb, cs));
         EX_TRY(enc_forward_partials(pf, L.eb, cs));
@@ -443,7 +446,7 @@ struct FistaGroup {
         k_resid_norm_part<<<dim3(kRedBlocks, B), 256, 0, cs>>>(L.eb.yop, pf.Tp, pf.NCP, pf.C, L.dpart);
         EX_LAUNCHED("residual norm");
         EX_TRY(reduce_sum_parts(L.dpart, kRedBlocks, B, 1.0, L.data, cs));
-        k_objective<<<B, 256, 0, cs>>>(L.data, L.l1, opts->levels, B, L.l1_blocks, nxp, L.lam_of(0),
+        k_objective<<<B, 256, 0, cs>>>(L.data, L.l1, opts->levels, B, L.l1_blocks, nxp, nyp, L.lam_of(0),
                                         opts->objective, K, k);
         EX_LAUNCHED("objective");
       }

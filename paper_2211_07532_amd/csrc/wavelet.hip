@@ -262,6 +262,170 @@ __global__ __launch_bounds__(256) void k_idwt_cols(float2 *__restrict__ w, int n
   }
 }
 
+// ---------------------------------------------------------------------------
+// Fused-level kernels of the solver's proximal step.  A level's row and
+// column passes run in one launch over 2D tiles: the periodic input region
+// of a tile (its outputs' footprint plus taps - 2 rows and columns) is staged
+// in LDS, the row pass writes its FP32 results to LDS, and the column pass
+// produces the tile's outputs.  The arithmetic (FP64 sums over the taps in
+// the same order, FP32 between the passes) is that of the per-pass kernels
+// above.  Levels read and write different buffers, so tiles never race.
+// ---------------------------------------------------------------------------
+
+constexpr int kTapsMax = 8;
+constexpr int kFwdTX = 16, kFwdTY = 8;  // analysis tile: coefficient positions per band
+constexpr int kInvT = 16;               // synthesis tile: output pixels per side
+
+__device__ inline int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// Analysis of one level: in (mx x my, row stride istride, image pitch
+// ipitch) -> LL to ll (hx x hy, row stride lstride, pitch lpitch) and the
+// three detail bands into w's level block (row stride nx, pitch wpitch),
+// soft-thresholded with tau[image] when tau is given; l1_part[image][tile]
+// receives the FP64 sum of the thresholded detail moduli when given.
+// Block: 256 threads; grid (ceil(hx/16), ceil(hy/8), images).
+__global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ in, int istride, int64_t ipitch,
+                                                    float2 *__restrict__ ll, int lstride, int64_t lpitch,
+                                                    float2 *__restrict__ w, int nx, int64_t wpitch, int mx, int my,
+                                                    FilterSet f, const double *__restrict__ tau,
+                                                    double *__restrict__ l1_part, int l1_stride) {
+  constexpr int RY = 2 * kFwdTY + kTapsMax - 2, RX = 2 * kFwdTX + kTapsMax - 2;
+  __shared__ float2 sin_[RY][RX];
+  __shared__ float2 slo[RY][kFwdTX], shi[RY][kFwdTX];
+  __shared__ double red[256];
+  const int b = blockIdx.z;
+  const int hx = mx >> 1, hy = my >> 1;
+  const int tx0 = blockIdx.x * kFwdTX, ty0 = blockIdx.y * kFwdTY;
+  const int taps = f.taps;
+  const int ry = 2 * kFwdTY + taps - 2, rx = 2 * kFwdTX + taps - 2;
+  in += b * ipitch;
+  for (int i = threadIdx.x; i < ry * rx; i += blockDim.x) {
+    const int r = i / rx, c = i - (i / rx) * rx;
+    sin_[r][c] = in[(int64_t)wrap(2 * ty0 + r, my) * istride + wrap(2 * tx0 + c, mx)];
+  }
+  __syncthreads();
+  // rows: low and high outputs at tile column x for every staged row
+  for (int i = threadIdx.x; i < ry * kFwdTX; i += blockDim.x) {
+    const int r = i / kFwdTX, x = i % kFwdTX;
+    double ax = 0.0, ay = 0.0, dx = 0.0, dy = 0.0;
+    for (int k = 0; k < taps; ++k) {
+      const float2 v = sin_[r][2 * x + k];
+      ax += f.h[k] * v.x;
+      ay += f.h[k] * v.y;
+      dx += f.g[k] * v.x;
+      dy += f.g[k] * v.y;
+    }
+    slo[r][x] = make_float2((float)ax, (float)ay);
+    shi[r][x] = make_float2((float)dx, (float)dy);
+  }
+  __syncthreads();
+  // columns: thread = (x part: low/high, row y, column x) of the tile
+  const int part = threadIdx.x >> 7, y = (threadIdx.x >> 4) & 7, x = threadIdx.x & 15;
+  const int oy = ty0 + y, ox = tx0 + x;
+  double l1 = 0.0;
+  if (oy < hy && ox < hx) {
+    double ax = 0.0, ay = 0.0, dx = 0.0, dy = 0.0;
+    for (int k = 0; k < taps; ++k) {
+      const float2 v = part ? shi[2 * y + k][x] : slo[2 * y + k][x];
+      ax += f.h[k] * v.x;
+      ay += f.h[k] * v.y;
+      dx += f.g[k] * v.x;
+      dy += f.g[k] * v.y;
+    }
+    float2 a = make_float2((float)ax, (float)ay), dd = make_float2((float)dx, (float)dy);
+    if (tau) {
+      const double t = tau[b];
+      if (part) {
+        a = soft(a, t);
+        l1 += sqrt((double)a.x * a.x + (double)a.y * a.y);
+      }
+      dd = soft(dd, t);
+      l1 += sqrt((double)dd.x * dd.x + (double)dd.y * dd.y);
+    }
+    float2 *wb = w + b * wpitch;
+    if (part)
+      wb[(int64_t)oy * nx + hx + ox] = a;                  // x high, y low
+    else
+      ll[b * lpitch + (int64_t)oy * lstride + ox] = a;     // low / low
+    wb[(int64_t)(hy + oy) * nx + (part ? hx : 0) + ox] = dd;  // y high
+  }
+  if (l1_part) {
+    red[threadIdx.x] = l1;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) l1_part[(int64_t)b * l1_stride + blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+  }
+}
+
+// Synthesis of one level (columns, then rows): LL from ll (hx x hy, row
+// stride lstride, pitch lpitch) and the detail bands from w's level block
+// (row stride nx, pitch wpitch) -> out (mx x my, row stride ostride, pitch
+// opitch); with zout, also zout = out + beta (out - xprev) (out's layout).
+// A 16 x 16 output tile needs 8 + taps/2 coefficient rows and columns of
+// each half, from i0 = m0/2 - taps/2 + 1 (periodic).
+// Block: 256 threads; grid (ceil(mx/16), ceil(my/16), images).
+__global__ __launch_bounds__(256) void k_idwt2_level(const float2 *__restrict__ ll, int lstride, int64_t lpitch,
+                                                     const float2 *__restrict__ w, int nx, int64_t wpitch,
+                                                     float2 *__restrict__ out, int ostride, int64_t opitch, int mx,
+                                                     int my, FilterSet f, const float2 *__restrict__ xprev,
+                                                     float2 *__restrict__ zout, double beta) {
+  constexpr int NI = kInvT / 2 + kTapsMax / 2;
+  __shared__ float2 sc[2 * NI][2 * NI];  // [low | high rows][low | high columns]
+  __shared__ float2 cp[kInvT][2 * NI];   // column-pass output rows
+  const int b = blockIdx.z;
+  const int hx = mx >> 1, hy = my >> 1;
+  const int m0 = blockIdx.y * kInvT, n0 = blockIdx.x * kInvT;
+  const int taps = f.taps;
+  const int ni = kInvT / 2 + taps / 2;
+  const int i0 = m0 / 2 - taps / 2 + 1, j0 = n0 / 2 - taps / 2 + 1;
+  const float2 *wb = w + b * wpitch;
+  for (int i = threadIdx.x; i < 4 * ni * ni; i += blockDim.x) {
+    const int r = i / (2 * ni), c = i - (i / (2 * ni)) * (2 * ni);
+    const bool rh = r >= ni, ch = c >= ni;
+    const int gy = wrap(i0 + (rh ? r - ni : r), hy), gx = wrap(j0 + (ch ? c - ni : c), hx);
+    sc[r][c] = (!rh && !ch) ? ll[b * lpitch + (int64_t)gy * lstride + gx]
+                            : wb[(int64_t)(rh ? hy + gy : gy) * nx + (ch ? hx + gx : gx)];
+  }
+  __syncthreads();
+  // columns: output row ml of every staged column
+  for (int i = threadIdx.x; i < kInvT * 2 * ni; i += blockDim.x) {
+    const int ml = i / (2 * ni), c = i - (i / (2 * ni)) * (2 * ni);
+    double vx = 0.0, vy = 0.0;
+    for (int k = (ml & 1); k < taps; k += 2) {
+      const int il = (ml - k) / 2 + taps / 2 - 1;
+      const float2 a = sc[il][c], d = sc[ni + il][c];
+      vx += f.h[k] * a.x + f.g[k] * d.x;
+      vy += f.h[k] * a.y + f.g[k] * d.y;
+    }
+    cp[ml][c] = make_float2((float)vx, (float)vy);
+  }
+  __syncthreads();
+  const int ml = threadIdx.x >> 4, nl = threadIdx.x & 15;
+  const int m = m0 + ml, n = n0 + nl;
+  if (m < my && n < mx) {
+    double vx = 0.0, vy = 0.0;
+    for (int k = (nl & 1); k < taps; k += 2) {
+      const int jl = (nl - k) / 2 + taps / 2 - 1;
+      const float2 a = cp[ml][jl], d = cp[ml][ni + jl];
+      vx += f.h[k] * a.x + f.g[k] * d.x;
+      vy += f.h[k] * a.y + f.g[k] * d.y;
+    }
+    const float2 v = make_float2((float)vx, (float)vy);
+    const int64_t o = b * opitch + (int64_t)m * ostride + n;
+    out[o] = v;
+    if (zout) {
+      const float2 p = xprev[o];
+      zout[o] = make_float2((float)(v.x + beta * ((double)v.x - p.x)), (float)(v.y + beta * ((double)v.y - p.y)));
+    }
+  }
+}
+
 __global__ void k_soft(const float2 *__restrict__ in, float2 *__restrict__ out, int nx, int ny, int llx,
                        int lly, int64_t total, float tau) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -342,6 +506,53 @@ int dwt_inverse_levels(const FilterSet &f, int nx, int ny, int levels, int batch
                                                                    last ? xprev : nullptr,
                                                                    last ? zout : nullptr, beta);
     EX_LAUNCHED("idwt rows");
+  }
+  return EXPENC_OK;
+}
+
+int dwt2_tiles(int nx, int ny, int level) {
+  const int hx = (nx >> level) >> 1, hy = (ny >> level) >> 1;
+  return (int)(ceil_div(hx, kFwdTX) * ceil_div(hy, kFwdTY));
+}
+
+// Buffer roles: analysis level j reads LL_j (v for j = 0, else x_k for odd j
+// and v for even j) and writes LL_{j+1} to the other one (w's top-left block
+// for the last level); synthesis level j reads LL_{j+1} (w for the last
+// level, else v for odd j+1 and x_k for even j+1) and writes LL_j to the
+// other one, x_k itself for j = 0.  Every launch therefore reads and writes
+// different buffers.
+int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *v, float2 *w, float2 *xk,
+              const float2 *xprev, float2 *z, double beta, const double *tau, double *l1_part, int l1_stride,
+              hipStream_t s) {
+  if (f.taps > kTapsMax || (f.taps & 1)) return fail(EXPENC_EUNSUPPORTED, "filters of %d taps", f.taps);
+  if (nx % (1 << levels) || ny % (1 << levels)) return fail(EXPENC_EINVAL, "grid not a multiple of 2^levels");
+  const int64_t pitch = (int64_t)nx * ny;
+  auto fwd_buf = [&](int j) { return (j & 1) ? xk : v; };  // LL_j of the analysis, j >= 1
+  auto inv_buf = [&](int j) { return (j & 1) ? v : xk; };  // LL_j of the synthesis, j >= 1
+  for (int j = 0; j < levels; ++j) {
+    const int mx = nx >> j, my = ny >> j;
+    const float2 *in = j == 0 ? v : fwd_buf(j);
+    const int istride = j == 0 ? nx : mx;
+    const bool last = j + 1 == levels;
+    float2 *ll = last ? w : fwd_buf(j + 1);
+    const int lstride = last ? nx : mx >> 1;
+    dim3 grid((unsigned)ceil_div(mx >> 1, kFwdTX), (unsigned)ceil_div(my >> 1, kFwdTY), (unsigned)nimg);
+    double *lp = l1_part ? l1_part + (int64_t)j * nimg * l1_stride : nullptr;
+    k_dwt2_level<<<grid, 256, 0, s>>>(in, istride, pitch, ll, lstride, pitch, w, nx, pitch, mx, my, f, tau, lp,
+                                      l1_stride);
+    EX_LAUNCHED("dwt level");
+  }
+  for (int j = levels - 1; j >= 0; --j) {
+    const int mx = nx >> j, my = ny >> j;
+    const bool top = j + 1 == levels;
+    const float2 *ll = top ? w : inv_buf(j + 1);
+    const int lstride = top ? nx : mx >> 1;
+    float2 *out = j == 0 ? xk : inv_buf(j);
+    const int ostride = j == 0 ? nx : mx;
+    dim3 grid((unsigned)ceil_div(mx, kInvT), (unsigned)ceil_div(my, kInvT), (unsigned)nimg);
+    k_idwt2_level<<<grid, 256, 0, s>>>(ll, lstride, pitch, w, nx, pitch, out, ostride, pitch, mx, my, f,
+                                       j == 0 ? xprev : nullptr, j == 0 ? z : nullptr, beta);
+    EX_LAUNCHED("idwt level");
   }
   return EXPENC_OK;
 }

@@ -38,4 +38,19 @@ int dwt_forward_levels(const FilterSet &f, int nx, int ny, int levels, int batch
 int dwt_inverse_levels(const FilterSet &f, int nx, int ny, int levels, int batch, float2 *w, float2 *dst,
                        const float2 *xprev, float2 *zout, double beta, hipStream_t s);
 
+// One FISTA proximal step with its momentum, on the fused-level kernels
+// (each level's row and column passes in one launch over 2D tiles staged in
+// LDS): w = S_tau(W v) (thresholded detail bands), x_k = W^H w and
+// z = x_k + beta (x_k - x_prev), for nimg images of nx x ny ([nimg][ny][nx],
+// row stride nx).  The intermediate low-pass blocks ping-pong between v and
+// x_k, both of which are overwritten (x_k with the result); x_prev and z must
+// be other buffers.  l1_part (optional) receives per-tile FP64 sums of the
+// thresholded detail moduli at [level][image][tile] (l1_stride tiles, see
+// dwt2_tiles).
+int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *v, float2 *w, float2 *xk,
+              const float2 *xprev, float2 *z, double beta, const double *tau, double *l1_part, int l1_stride,
+              hipStream_t s);
+// Number of analysis tiles of level j (its l1 partial sums).
+int dwt2_tiles(int nx, int ny, int level);
+
 }  // namespace expenc
