@@ -148,7 +148,7 @@ __global__ void k_build_z_f32(const float2 *__restrict__ smaps, const float2 *__
 
 // Y operand [Tp][NCP] from y [B][T][C].
 __global__ void k_pack_y_f32(const float2 *__restrict__ y, int64_t T, int64_t Tp, int C, int NC,
-                             int NCP, float2 *__restrict__ yop) {
+                             int NCP, float2 *__restrict__ yop, float sign) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Tp * NCP) return;
   const int pz = blockIdx.y;
@@ -161,7 +161,7 @@ __global__ void k_pack_y_f32(const float2 *__restrict__ y, int64_t T, int64_t Tp
     int b = col / C, c = col % C;
     v = y[((int64_t)b * T + t) * C + c];
   }
-  yop[i] = v;
+  yop[i] = make_float2(sign * v.x, sign * v.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,10 +376,11 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
                                                         int x_row_stride, const double *__restrict__ alpha_dev,
                                                         const float2 *__restrict__ add,
                                                         const float2 *__restrict__ base, int nxq,
-                                                        int64_t x_pstride) {
+                                                        int64_t x_pstride, int pad_nx, int pad_ny) {
   const int sub = threadIdx.x & 31;
-  const int r = blockIdx.x * 8 + (threadIdx.x >> 5);
-  if (r >= R) return;  // uniform per 32-lane group
+  const int q = blockIdx.x * 8 + (threadIdx.x >> 5);  // pixel of x's grid
+  const int npx = pad_nx > 0 ? pad_nx * pad_ny : R;
+  if (q >= npx) return;  // uniform per 32-lane group
   const int pz = blockIdx.y;  // problem
   part += (int64_t)pz * nsplit * Rp * NCP;
   smaps += (int64_t)pz * C * R;
@@ -387,6 +388,19 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
   if (alpha_dev) alpha_dev += pz;
   if (add) add += pz * x_pstride;
   if (base) base += pz * x_pstride;
+  if (pad_nx > 0) {
+    // padded grid: outside the encoded nx x ny block x = add (or 0)
+    const int yy = q / pad_nx, xx = q % pad_nx;
+    if (yy >= R / nx || xx >= nx) {
+      if (sub == 0)
+        for (int b = 0; b < B; ++b) {
+          const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
+          x[o] = add ? add[o] : make_float2(0.f, 0.f);
+        }
+      return;
+    }
+  }
+  const int r = pad_nx > 0 ? (q / pad_nx) * nx + q % pad_nx : q;
   const int64_t rq = (int64_t)(r / nx) * nxq + (r % nx);  // row of the partial sums
   for (int b = 0; b < B; ++b) {
     double sx = 0.0, sy = 0.0;
@@ -427,34 +441,60 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
 
 // Single image: x(r) = alpha * (sum over splits and column blocks of the
 // coil-combined partial images at row (r / nx) * nxq + r % nx), with the
-// same base / add terms as k_adj_reduce_out.  One thread per pixel.
-__global__ void k_adj_reduce_comb(const float2 *__restrict__ part, int nslice, int R, int Rp, int nx,
-                                  float2 *__restrict__ x, int x_row_stride, const double *__restrict__ alpha_dev,
-                                  const float2 *__restrict__ add, const float2 *__restrict__ base, int nxq,
-                                  int64_t x_pstride) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
+// same base / add terms as k_adj_reduce_out.  Four lanes per pixel: lane j
+// sums slices j, j+4, j+8, ... in order (eight loads in flight), then the
+// four partial sums are added in lane order.  With pad_nx > 0 the pixels are
+// those of the pad_nx x pad_ny grid, and those outside the encoded block get
+// add (or 0).
+__global__ __launch_bounds__(256) void k_adj_reduce_comb(const float2 *__restrict__ part, int nslice, int Rp,
+                                                         int nx, int ny, float2 *__restrict__ x, int x_row_stride,
+                                                         const double *__restrict__ alpha_dev,
+                                                         const float2 *__restrict__ add,
+                                                         const float2 *__restrict__ base, int nxq, int64_t x_pstride,
+                                                         int pad_nx, int pad_ny) {
+  const int q = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 2), j = threadIdx.x & 3;
+  const int gx = pad_nx > 0 ? pad_nx : nx;
+  if (q >= (pad_nx > 0 ? pad_nx * pad_ny : nx * ny)) return;  // uniform per group of four lanes
   const int pz = blockIdx.y;  // problem
   part += (int64_t)pz * nslice * Rp;
   x += pz * x_pstride;
   if (alpha_dev) alpha_dev += pz;
   if (add) add += pz * x_pstride;
   if (base) base += pz * x_pstride;
-  const int yy = r / nx, xx = r % nx;
+  const int yy = q / gx, xx = q % gx;
+  const int64_t o = (int64_t)yy * x_row_stride + xx;
+  if (yy >= ny || xx >= nx) {
+    if (j == 0) x[o] = add ? add[o] : make_float2(0.f, 0.f);
+    return;
+  }
   const int64_t rq = (int64_t)yy * nxq + xx;
   double sx = 0.0, sy = 0.0;
-  for (int k = 0; k < nslice; ++k) {
-    const float2 v = part[(int64_t)k * Rp + rq];
-    sx += v.x;
-    sy += v.y;
+  for (int k0 = j; k0 < nslice; k0 += 32) {
+    float2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      v[u] = k0 + 4 * u < nslice ? part[(int64_t)(k0 + 4 * u) * Rp + rq] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sx += v[u].x;
+      sy += v[u].y;
+    }
   }
-  const int64_t o = (int64_t)yy * x_row_stride + xx;
+  // lane order: ((s0 + s1) + s2) + s3
+  const int l0 = (threadIdx.x & 63) & ~3;
+  double tx = __shfl(sx, l0), ty = __shfl(sy, l0);
+#pragma unroll
+  for (int u = 1; u < 4; ++u) {
+    tx += __shfl(sx, l0 + u);
+    ty += __shfl(sy, l0 + u);
+  }
+  if (j != 0) return;
   if (base) {
-    sx += base[o].x;
-    sy += base[o].y;
+    tx += base[o].x;
+    ty += base[o].y;
   }
   const double alpha = alpha_dev ? *alpha_dev : 1.0;
-  float2 v = make_float2((float)(alpha * sx), (float)(alpha * sy));
+  float2 v = make_float2((float)(alpha * tx), (float)(alpha * ty));
   if (add) {
     v.x += add[o].x;
     v.y += add[o].y;
@@ -666,9 +706,12 @@ int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x
   return EXPENC_OK;
 }
 
-int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s) {
-  if (p.prec != EXPENC_FP32) return split_pack_y(p, y, false, nullptr, b, s);
-  k_pack_y_f32<<<grid_p(p.Tp * p.NCP, 256, p.P), 256, 0, s>>>(y, p.T, p.Tp, p.C, p.NC, p.NCP, b.yop);
+int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s, float sign) {
+  if (p.prec != EXPENC_FP32) {
+    if (sign != 1.f) return fail(EXPENC_EUNSUPPORTED, "scaled operand packing is FP32 only");
+    return split_pack_y(p, y, false, nullptr, b, s);
+  }
+  k_pack_y_f32<<<grid_p(p.Tp * p.NCP, 256, p.P), 256, 0, s>>>(y, p.T, p.Tp, p.C, p.NC, p.NCP, b.yop, sign);
   EX_LAUNCHED("pack_y");
   return EXPENC_OK;
 }
@@ -825,16 +868,22 @@ int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_
 
 int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
                            int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
-                           const float2 *add, hipStream_t s, const float2 *base, int64_t x_pstride) {
+                           const float2 *add, hipStream_t s, const float2 *base, int64_t x_pstride,
+                           int32_t pad_nx, int32_t pad_ny) {
+  const int64_t npx = pad_nx > 0 ? (int64_t)pad_nx * pad_ny : p.R;
+  if (pad_nx > 0 && (pad_nx < p.nx || pad_ny < p.ny || x_row_stride < pad_nx))
+    return fail(EXPENC_EINVAL, "padded grid %dx%d smaller than the image", pad_nx, pad_ny);
   if (p.comb) {
-    k_adj_reduce_comb<<<grid_p(p.R, 256, p.P), 256, 0, s>>>(b.part, p.adj_split * p.NGY, p.R, p.Rp, p.nx, x,
-                                                            x_row_stride, alpha_dev, add, base, p.nxq, x_pstride);
+    k_adj_reduce_comb<<<grid_p(npx * 4, 256, p.P), 256, 0, s>>>(b.part, p.adj_split * p.NGY, p.Rp, p.nx, p.ny, x,
+                                                          x_row_stride, alpha_dev, add, base, p.nxq, x_pstride,
+                                                          pad_nx, pad_ny);
     EX_LAUNCHED("adjoint reduce");
     return EXPENC_OK;
   }
-  k_adj_reduce_out<<<grid_p(p.R, 8, p.P), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
+  k_adj_reduce_out<<<grid_p(npx, 8, p.P), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
                                                        reinterpret_cast<const float2 *>(smaps), x, x_stride,
-                                                       x_row_stride, alpha_dev, add, base, p.nxq, x_pstride);
+                                                       x_row_stride, alpha_dev, add, base, p.nxq, x_pstride,
+                                                       pad_nx, pad_ny);
   EX_LAUNCHED("adjoint reduce");
   return EXPENC_OK;
 }

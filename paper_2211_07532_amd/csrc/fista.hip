@@ -408,19 +408,22 @@ struct FistaGroup {
     for (int k = 0; k < K; ++k) {
       float2 *xk = (k % 2 == 0) ? L.x1 : L.x0;
       float2 *xprev = (k % 2 == 0) ? L.x0 : L.x1;
+      // z_0 = 0, so the first residual A z - y is -y without a forward product
+      auto residual_fp32 = [&](const EncPlan &q) -> int {
+        if (k == 0) return enc_pack_y(q, y, L.eb, cs, -1.f);
+        EX_TRY(enc_build_z(q, op->smaps, L.z, img, nxp, L.eb, cs, nullptr, pimg));
+        EX_TRY(enc_forward_partials(q, L.eb, cs));
+        return enc_forward_residual(q, L.eb, y, cs);
+      };
+      const int pnx = padded ? nxp : 0, pny = padded ? nyp : 0;
       if (!split) {
         // v = z - (2/L) A^H (A z - y)
-        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs, nullptr, pimg));
-        EX_TRY(enc_forward_partials(p, L.eb, cs));
-        EX_TRY(enc_forward_residual(p, L.eb, y, cs));
+        EX_TRY(residual_fp32(p));
         EX_TRY(enc_adjoint_partials(p, L.eb, cs));
-        if (padded) EX_TRY(copy_f2(L.z, L.v, all, cs));
-        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, nullptr, pimg));
+        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, nullptr, pimg, pnx, pny));
       } else if (k % refine == 0 || k == K - 1) {
         // anchor: exact FP32 gradient at z_ref = z
-        EX_TRY(enc_build_z(pf, op->smaps, L.z, img, nxp, L.eb, cs, nullptr, pimg));
-        EX_TRY(enc_forward_partials(pf, L.eb, cs));
-        EX_TRY(enc_forward_residual(pf, L.eb, y, cs));
+        EX_TRY(residual_fp32(pf));
         EX_TRY(enc_adjoint_partials(pf, L.eb, cs));
         EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.gref, img, nxp, nullptr, nullptr, cs, nullptr, pimg));
         k_grad_step<<<(unsigned)ceil_div(all, 256), 256, 0, cs>>>(L.v, L.z, L.gref, alpha, nxp, nyp, p.nx, p.ny, all, B);
@@ -432,8 +435,7 @@ struct FistaGroup {
         EX_TRY(enc_forward_partials(p, L.eb, cs));
         EX_TRY(enc_forward_residual(p, L.eb, nullptr, cs));
         EX_TRY(enc_adjoint_partials(p, L.eb, cs));
-        if (padded) EX_TRY(copy_f2(L.z, L.v, all, cs));
-        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, L.gref, pimg));
+        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, L.gref, pimg, pnx, pny));
       }
       // x_k = W^H S_tau(W v), z = x_k + beta_k (x_k - x_{k-1}); v and x_k serve
       // as the transform's ping-pong buffers

@@ -241,19 +241,21 @@ int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x
 int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // y[b][t][c] = sum_split partials (ABI layout)
 int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s);
-// Y operand from y [B][T][C]
-int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s);
+// Y operand from sign * y, y [B][T][C] (sign other than 1: FP32 plans only)
+int enc_pack_y(const EncPlan &p, const float2 *y, const EncBuffers &b, hipStream_t s, float sign = 1.f);
 int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // x_b(r) = alpha * sum_c conj(S_c(r)) sum_split partials (+ add_b(r)),
 // written to x [B] with x_stride between problems and row stride
 // x_row_stride (pixels); alpha = *alpha_dev (device FP64) or 1 if NULL.
 // If base is given (same layout as x) it is added to the sum before scaling:
 // x = add + alpha * (base + sum).
-// alpha_dev, if given, holds one value per problem.
+// alpha_dev, if given, holds one value per problem.  With pad_nx > 0, x is
+// a pad_nx x pad_ny grid (>= nx x ny) whose pixels outside the encoded
+// block are set to add (or 0).
 int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *smaps, float2 *x,
                            int64_t x_stride, int32_t x_row_stride, const double *alpha_dev,
                            const float2 *add, hipStream_t s, const float2 *base = nullptr,
-                           int64_t x_pstride = 0);
+                           int64_t x_pstride = 0, int32_t pad_nx = 0, int32_t pad_ny = 0);
 // Residual r = A z - y (y_meas [B][T][C], or NULL for r = A z) written
 // straight into the adjoint operand.
 int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_meas, hipStream_t s);

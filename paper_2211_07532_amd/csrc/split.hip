@@ -496,12 +496,14 @@ __device__ inline void write_record(u32x4 *out, int64_t q, int g, int NGP, int l
 }
 
 template <bool BF>
-__global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
+__global__ __launch_bounds__(256) void k_build_z_split(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
                                 const float2 *__restrict__ xsub, int64_t x_stride, int x_row_stride, int nx, int ny,
-                                int nxq, int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs, int64_t x_pstride) {
+                                int nxq, int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs, int64_t x_pstride,
+                                const float2 *__restrict__ sq) {
   const int R = nx * ny;
   const int pz = blockIdx.y;  // problem
   smaps += (int64_t)pz * C * R;
+  if (sq) sq += (int64_t)pz * Rp * NGP * 16;
   x += pz * x_pstride;
   if (xsub) xsub += pz * x_pstride;
   zs += (int64_t)pz * Rp * NGP * 16;
@@ -528,7 +530,8 @@ __global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *
         u.x -= w.x;
         u.y -= w.y;
       }
-      const float2 s = smaps[(int64_t)c * R + r];
+      // (the S table, when given, holds the same value in row-major order)
+      const float2 s = sq ? sq[(int64_t)rq * NGP * 16 + col] : smaps[(int64_t)c * R + r];
       z = make_float2(s.x * u.x - s.y * u.y, s.x * u.y + s.y * u.x);
     }
     b1[i] = im ? z.y : z.x;
@@ -542,9 +545,10 @@ __global__ void k_build_z_split(const float2 *__restrict__ smaps, const float2 *
 // With perm, K index 8h + i of a step holds sample 8(i/4) + 4h + i%4 of its
 // 16 (the order in which the polynomial adjoint produces its phase tile).
 template <bool BF>
-__global__ void k_pack_y_split(const float2 *__restrict__ src_abi, const float2 *__restrict__ src_part, int nsplit,
-                               const float2 *__restrict__ y_meas, int64_t T, int64_t Tp, int C, int NC, int NCP,
-                               u32x4 *__restrict__ ys, int perm) {
+__global__ __launch_bounds__(256) void k_pack_y_split(const float2 *__restrict__ src_abi,
+                                                      const float2 *__restrict__ src_part, int nsplit,
+                                                      const float2 *__restrict__ y_meas, int64_t T, int64_t Tp, int C,
+                                                      int NC, int NCP, u32x4 *__restrict__ ys, int perm) {
   const int NGP = NCP / 16;
   const int pz = blockIdx.y;  // problem
   if (src_abi) src_abi += pz * T * NC;
@@ -558,30 +562,63 @@ __global__ void k_pack_y_split(const float2 *__restrict__ src_abi, const float2 
   const int64_t q = (id >> 6) / NGP;
   const int col = 16 * g + (lane & 15);
   const int im = (lane >> 4) & 1;
+  const int b = col / C, c = col % C;
+  int64_t t[8];
+  bool ok[8];
+  float2 y[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    t[i] = 16 * q + (perm ? 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3) : 8 * (lane >> 5) + i);
+    ok[i] = t[i] < T && col < NC;
+    y[i] = make_float2(0.f, 0.f);
+  }
+  if (src_abi) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      if (ok[i]) y[i] = src_abi[((int64_t)b * T + t[i]) * C + c];
+  } else {
+    // split order per sample as in a plain loop; the loads of four splits x
+    // eight samples are independent and issue together
+    int k = 0;
+    for (; k + 4 <= nsplit; k += 4) {
+      float2 v[4][8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          v[u][i] = ok[i] ? src_part[((int64_t)(k + u) * Tp + t[i]) * NCP + col] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+          y[i].x += v[u][i].x;
+          y[i].y += v[u][i].y;
+        }
+    }
+    for (; k < nsplit; ++k) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (ok[i]) {
+          const float2 v = src_part[((int64_t)k * Tp + t[i]) * NCP + col];
+          y[i].x += v.x;
+          y[i].y += v.y;
+        }
+    }
+    if (y_meas) {
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+        if (ok[i]) {
+          const float2 m = y_meas[((int64_t)b * T + t[i]) * C + c];
+          y[i].x -= m.x;
+          y[i].y -= m.y;
+        }
+    }
+  }
   float b1[8], b2[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int64_t t = 16 * q + (perm ? 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3) : 8 * (lane >> 5) + i);
-    float2 y = make_float2(0.f, 0.f);
-    if (t < T && col < NC) {
-      const int b = col / C, c = col % C;
-      if (src_abi) {
-        y = src_abi[((int64_t)b * T + t) * C + c];
-      } else {
-        for (int k = 0; k < nsplit; ++k) {
-          const float2 v = src_part[((int64_t)k * Tp + t) * NCP + col];
-          y.x += v.x;
-          y.y += v.y;
-        }
-        if (y_meas) {
-          const float2 m = y_meas[((int64_t)b * T + t) * C + c];
-          y.x -= m.x;
-          y.y -= m.y;
-        }
-      }
-    }
-    b1[i] = im ? y.y : y.x;
-    b2[i] = im ? -y.x : y.y;
+    b1[i] = im ? y[i].y : y[i].x;
+    b2[i] = im ? -y[i].x : y[i].y;
   }
   write_record<BF>(ys, q, g, NGP, lane, b1, b2);
 }
@@ -830,10 +867,10 @@ int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const f
   u32x4 *zs = reinterpret_cast<u32x4 *>(b.zs);
   if (p.prec == EXPENC_BF16_SPLIT)
     k_build_z_split<true><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
-                                             p.NC, NGP, zs, x_pstride);
+                                             p.NC, NGP, zs, x_pstride, p.comb ? b.sq : nullptr);
   else
     k_build_z_split<false><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
-                                              p.NC, NGP, zs, x_pstride);
+                                              p.NC, NGP, zs, x_pstride, p.comb ? b.sq : nullptr);
   EX_LAUNCHED("build_z split");
   return EXPENC_OK;
 }
