@@ -42,15 +42,16 @@ N_POWER = 20
 # 256 MiB copy.  Valid only for the kernel source and launch shape they were
 # taken on: `sha` is the SHA-256 of the files the kernel is built from.
 TRAFFIC = {
-    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 407869645,
-             "sha": "0461502a2f440ed36dc943c0c94122f280ffadaea1e26ed5cb6d646c7dd9b14a"},
-    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 211471995,
-             "sha": "58134d0a28d25ef0d825d8978e8270ac089d3a596fbc0e3d12eb5e2ff6c24b0a"},
-    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 212124918,
-             "sha": "58134d0a28d25ef0d825d8978e8270ac089d3a596fbc0e3d12eb5e2ff6c24b0a"},
+    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 407080550,
+             "sha": "d033c03306bfb279816d2e19b309f25aa7b5e0352ca8a29a5dd7c982eab10893"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89604096,
+             "sha": "d900f76fd9868d965e49b17a5deb9f6fe66e7f6866213bec9861a74d1fac78b5"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89592627,
+             "sha": "d900f76fd9868d965e49b17a5deb9f6fe66e7f6866213bec9861a74d1fac78b5"},
 }
-TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h"], "bf16": ["split.hip", "internal.h"],
-                   "fp16": ["split.hip", "internal.h"]}
+TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
+                   "bf16": ["split_adj.hip", "split_dev.h", "internal.h", "../build.py"],
+                   "fp16": ["split_adj.hip", "split_dev.h", "internal.h", "../build.py"]}
 
 
 def source_sha(form):

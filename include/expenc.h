@@ -142,7 +142,8 @@ int expenc_adjoint(const expenc_op *op, int32_t batch, int32_t precision,
  * Lipschitz constant of the gradient of ||A x - y||^2: L = 2 lambda_max(A^H A),
  * by n_iter normalised power steps v <- A^H A v / ||A^H A v|| from the
  * caller's start vector v0 [R] complex64, then the Rayleigh quotient
- * (FP64 reductions).  Writes L to *lipschitz_out (a DEVICE float64 scalar).
+ * 2 <v, A^H A v> / <v, v> (FP64 reductions), with the operators of the given
+ * precision.  Writes L to *lipschitz_out (a DEVICE float64 scalar).
  */
 int expenc_lipschitz(const expenc_op *op, int32_t precision, int32_t n_iter, const float *v0,
                      double *lipschitz_out, void *ws, size_t ws_bytes, void *stream);
@@ -208,7 +209,8 @@ typedef struct expenc_fista_opts {
   int32_t nx_pad, ny_pad;  /* wavelet grid (>= nx, ny, multiples of 2^J); 0 = round up */
   int32_t ista;            /* 1: momentum off (t_k = 1), monotone ISTA               */
   int32_t refine_every;    /* split forms: exact FP32 gradient every m iterations (0 = 50 fp16, 25 bf16) */
-  int32_t n_power;         /* power steps when lipschitz <= 0                        */
+  int32_t n_power;         /* power steps when lipschitz <= 0 (in the solve's
+                              precision when batch == 1, else FP32)                  */
   int32_t reserved;
   double lipschitz;        /* > 0: L to use; <= 0: estimate from power_v0            */
   double lambda;           /* >= 0: lambda to use; < 0: lambda_factor * max|A^H y|   */
@@ -301,7 +303,8 @@ typedef struct expenc_balanced_opts {
   int32_t wavelet;       /* EXPENC_HAAR / EXPENC_DB4                               */
   int32_t levels;        /* J in [1, 8] (the paper: 1)                             */
   int32_t refine_every;  /* split forms: FP32 anchor cadence (0 = 50 fp16, 25 bf16) */
-  int32_t n_power;       /* power steps when lipschitz <= 0                        */
+  int32_t n_power;       /* power steps when lipschitz <= 0 (solve's precision at
+                            batch 1, else FP32)                                      */
   int32_t ista;          /* 1: momentum off                                        */
   int32_t reserved;      /* must be 0                                              */
   double lipschitz;      /* > 0: L_A to use; <= 0: power iteration from power_v0   */

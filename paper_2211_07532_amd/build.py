@@ -16,7 +16,13 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libexpenc.so")
-SOURCES = ["encode.hip", "split.hip", "wavelet.hip", "api.hip", "fista.hip", "grad.hip", "coils.hip", "balanced.hip"]
+SOURCES = ["encode.hip", "split.hip", "split_adj.hip", "wavelet.hip", "api.hip", "fista.hip", "grad.hip", "coils.hip",
+           "balanced.hip"]
+# Per-source code generation: the polynomial split adjoint keeps its matrix-
+# core results in the vector register file (no AGPR copies of the phase
+# tiles; 163 registers, three waves per SIMD instead of two).  The same
+# option slows the forward kernels, so it is not global.
+EXTRA_FLAGS = {"split_adj.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 ARCH = "gfx950"
 
 
@@ -44,7 +50,7 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
-        cmd = [cc, *common_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [cc, *common_flags(), *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}:\n{r.stderr[-6000:]}")

@@ -227,11 +227,18 @@ int lipschitz_run(const EncPlan &p1, const expenc_op *op, const EncBuffers &eb, 
     EX_TRY(scale_rsqrt(tmp, R, R, P, dsc, s));
     std::swap(vec, tmp);
   }
-  // Rayleigh quotient <v, A^H A v>/<v, v> = ||A v||^2 / ||v||^2
-  EX_TRY(enc_build_z(p1, op->smaps, vec, R, p1.nx, eb, s, nullptr, R));
-  EX_TRY(enc_forward_partials(p1, eb, s));
-  EX_TRY(enc_forward_residual(p1, eb, nullptr, s));
-  EX_TRY(reduce_dot(eb.yop, eb.yop, p1.Tp * p1.NCP, p1.Tp * p1.NCP, P, 1.0, dpart, dsc + P, s));
+  // Rayleigh quotient <v, A^H A v>/<v, v>: the FP32 form takes ||A v||^2 from
+  // its residual operand; the split forms pack their residual into MFMA
+  // records, so they apply A^H A once more
+  if (p1.prec == EXPENC_FP32) {
+    EX_TRY(enc_build_z(p1, op->smaps, vec, R, p1.nx, eb, s, nullptr, R));
+    EX_TRY(enc_forward_partials(p1, eb, s));
+    EX_TRY(enc_forward_residual(p1, eb, nullptr, s));
+    EX_TRY(reduce_dot(eb.yop, eb.yop, p1.Tp * p1.NCP, p1.Tp * p1.NCP, P, 1.0, dpart, dsc + P, s));
+  } else {
+    EX_TRY(normal_apply(p1, op, eb, vec, tmp, s));
+    EX_TRY(reduce_dot(vec, tmp, R, R, P, 1.0, dpart, dsc + P, s));
+  }
   EX_TRY(reduce_dot(vec, vec, R, R, P, 1.0, dpart, dsc + 2 * P, s));
   k_lipschitz_final<<<1, 256, 0, s>>>(dsc + P, dsc + 2 * P, L_out, P);
   EX_LAUNCHED("lipschitz final");

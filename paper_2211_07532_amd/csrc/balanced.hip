@@ -308,7 +308,9 @@ int layout_bal(const expenc_op *op, int32_t batch, const expenc_balanced_opts *o
   if (o->levels < 1 || o->levels > 8) return fail(EXPENC_EINVAL, "levels must be in [1, 8]");
   EX_TRY(make_plan(op, batch, o->precision, &L->p));
   EX_TRY(make_plan(op, batch, EXPENC_FP32, &L->pf));
-  EX_TRY(make_plan(op, 1, EXPENC_FP32, &L->p1));
+  // power iteration in the solve's precision when there is one image (p1 and
+  // p then share geometry and tables)
+  EX_TRY(make_plan(op, 1, batch == 1 ? o->precision : EXPENC_FP32, &L->p1));
   L->J = o->levels;
   L->nb = 3 * o->levels + 1;
   L->B = batch;

@@ -261,7 +261,7 @@ uint64_t hash_bytes(uint64_t h, const void *p, size_t n) { return fnv(h, p, n); 
 // ---------------------------------------------------------------------------
 
 struct FistaLayout {
-  EncPlan p, p1, pf;  // p: iteration precision (batch B); p1: FP32 batch 1; pf: FP32 batch B
+  EncPlan p, p1, pf;  // p: iteration precision (batch B); p1: batch 1 (power iteration); pf: FP32 batch B
   int P = 1, B = 1;
   int nxp = 0, nyp = 0;
   EncBuffers eb;
@@ -289,7 +289,9 @@ static int resolve_pad(int n, int given, int levels, int *out) {
 static int layout_fista(const expenc_op *op, int32_t nprob, int32_t batch, int32_t precision, int levels, int nx_pad,
                         int ny_pad, bool objective, Arena &a, FistaLayout *L) {
   EX_TRY(make_plan(op, batch, precision, &L->p, nprob));
-  EX_TRY(make_plan(op, 1, EXPENC_FP32, &L->p1, nprob));
+  // the power iteration runs in the solve's precision when each problem has
+  // one image (then p1 and p share geometry, tables and coil table)
+  EX_TRY(make_plan(op, 1, batch == 1 ? precision : EXPENC_FP32, &L->p1, nprob));
   EX_TRY(make_plan(op, batch, EXPENC_FP32, &L->pf, nprob));
   if (levels < 1 || levels > 12) return fail(EXPENC_EINVAL, "levels must be in [1, 12]");
   if (objective && nprob != 1) return fail(EXPENC_EUNSUPPORTED, "objective traces are per single problem");

@@ -72,6 +72,32 @@ __device__ inline bool split_tile(int nrb, int nsplit, int *split, int *rb) {
   *rb = bp - *split * nrb;
   return true;
 }
+// Variant for the coil-combining adjoint, whose epilogue also reads a table
+// over its pixel rows (the coil sensitivities): XCD x takes the contiguous
+// range [xQ, xQ + Q) of the row-major (row block, split) list, about one
+// eighth of the row blocks with all of their splits, and walks it
+// split-major.  Its slice of the row table then stays in its L2 across the
+// splits, and the workgroups in flight on an XCD still share the chunks of a
+// few splits of the streamed operand.  Same grid as split_tile.
+__device__ inline bool split_tile_rows(int nrb, int nsplit, int *split, int *rb) {
+  const int n = nrb * nsplit;
+  const int q = (n + 7) >> 3;
+  const int j = blockIdx.x >> 3;
+  const int lo = (blockIdx.x & 7) * q, hi = min(n, lo + q);
+  if (lo + j >= hi) return false;
+  // the range holds row block r of split s iff lo <= r * nsplit + s < hi
+  int cum = 0;
+  for (int s = 0; s < nsplit; ++s) {
+    const int r0 = (lo - s + nsplit - 1) / nsplit, r1 = (hi - s + nsplit - 1) / nsplit;
+    if (j < cum + r1 - r0) {
+      *split = s;
+      *rb = r0 + (j - cum);
+      return true;
+    }
+    cum += r1 - r0;
+  }
+  return false;
+}
 inline unsigned split_grid(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -264,6 +290,8 @@ int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_
 int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s);
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+// the polynomial (solid-harmonic) split adjoint, built in split_adj.hip
+void split_adjoint_sh_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
                   int32_t x_row_stride, const EncBuffers &b, hipStream_t s, int64_t x_pstride);
 int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, const float2 *y_meas,

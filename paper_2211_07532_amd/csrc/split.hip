@@ -19,46 +19,9 @@
 // exactly the per-lane order (four 16-byte records per lane and step: b1 hi,
 // b1 lo, b2 hi, b2 lo), so the inner loop loads it with dwordx4 loads.
 #include "internal.h"
+#include "split_dev.h"
 
 namespace expenc {
-
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-// Split two FP32 values into packed (hi, lo) 16-bit pairs.
-template <bool BF>
-__device__ inline void split_pair(float a, float b, uint32_t &hi, uint32_t &lo) {
-  if constexpr (BF) {
-    const bf16x2 h = {(__bf16)a, (__bf16)b};
-    hi = __builtin_bit_cast(uint32_t, h);
-    const float ah = __uint_as_float(hi << 16), bh = __uint_as_float(hi & 0xffff0000u);
-    const bf16x2 l = {(__bf16)(a - ah), (__bf16)(b - bh)};
-    lo = __builtin_bit_cast(uint32_t, l);
-  } else {
-    const f16x2 h = {(_Float16)a, (_Float16)b};
-    hi = __builtin_bit_cast(uint32_t, h);
-    // v - hi in one fused multiply-add that reads the 16-bit half directly
-    // (exact: hi is within a factor 2 of v), instead of converting hi back
-    float la, lb;
-    __asm__("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(la) : "v"(hi), "v"(a));
-    __asm__("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(lb) : "v"(hi), "v"(b));
-    const f16x2 l = {(_Float16)la, (_Float16)lb};
-    lo = __builtin_bit_cast(uint32_t, l);
-  }
-}
-
-template <bool BF>
-__device__ inline f32x16 mfma16(u32x4 a, u32x4 b, f32x16 c) {
-  if constexpr (BF)
-    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
-                                                   0, 0, 0);
-  else
-    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
-                                                  0, 0, 0);
-}
 
 __device__ inline uint32_t swap_lo(uint32_t a, uint32_t b, uint32_t &hi_out) {
   const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
@@ -142,19 +105,6 @@ __device__ inline void phase_tile16(const double (&pv)[NT], const float (&pf)[NT
   pack_tile16<BF>(c, sn, A);
 }
 
-// 6 MFMAs of one step for one 32-row block and one 32-column group:
-// cos against b1, sin against b2, each as hi*hi + hi*lo + lo*hi.
-template <bool BF>
-__device__ inline f32x16 step6(const u32x4 (&A)[4], const u32x4 *b, f32x16 acc) {
-  acc = mfma16<BF>(A[0], b[0], acc);
-  acc = mfma16<BF>(A[0], b[1], acc);
-  acc = mfma16<BF>(A[1], b[0], acc);
-  acc = mfma16<BF>(A[2], b[2], acc);
-  acc = mfma16<BF>(A[2], b[3], acc);
-  acc = mfma16<BF>(A[3], b[2], acc);
-  return acc;
-}
-
 template <int GW>
 __device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0, int lane, f32x16 (&acc)[2][GW]) {
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
@@ -229,7 +179,7 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!split_tile(Rp / 256, nsplit, &split, &rb)) return;
+  if (!(sq ? split_tile_rows(Rp / 256, nsplit, &split, &rb) : split_tile(Rp / 256, nsplit, &split, &rb))) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
@@ -360,116 +310,6 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__
     }
   }
   store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc);
-}
-
-template <int GW, bool BF>
-__global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__ pmono, const float *__restrict__ dpa,
-                                                      const double *__restrict__ dwq, const u32x4 *__restrict__ ys,
-                                                      float *__restrict__ part, int Rp, int64_t Tp, int NCP, int chunk,
-                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy,
-                                                      const float2 *__restrict__ sq) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int hl = lane >> 5, jl = lane & 31;
-  int split, rb;
-  if (!split_tile(Rp / 256, nsplit, &split, &rb)) return;
-  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
-  const int g0 = blockIdx.y * GW;
-  const int NGP = NCP / 16;
-  const int pz = blockIdx.z;  // problem
-  pmono += pz * Tp * 12;
-  dpa += pz * Tp * 16;
-  dwq += (int64_t)pz * Rp;
-  ys += pz * Tp * NGP * 16;
-  // this lane's pixel in each 32-row block, and its B operand of the
-  // increment product: the monomial (or dw0) of term 2J + hl
-  double xg[2], yg[2], wg[2];
-  float bm[2][6];
-#pragma unroll
-  for (int blk = 0; blk < 2; ++blk) {
-    const int rq = (int)(row0 + 32 * blk + jl);
-    const double x = (rq % nxq - 0.5 * nx) * dx, y = (rq / nxq - 0.5 * ny) * dy, w = dwq[rq];
-    xg[blk] = x;
-    yg[blk] = y;
-    wg[blk] = w;
-    // terms 0..11: 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3, dw0, anchor
-    bm[blk][0] = (float)(hl ? x : 1.0);
-    bm[blk][1] = (float)(hl ? x * x : y);
-    bm[blk][2] = (float)(hl ? y * y : x * y);
-    bm[blk][3] = (float)(hl ? x * x * y : x * x * x);
-    bm[blk][4] = (float)(hl ? y * y * y : x * y * y);
-    bm[blk][5] = (float)w;  // lanes 32..63 replace it by the anchor per step
-  }
-  f32x16 acc[2][GW];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int g = 0; g < GW; ++g)
-#pragma unroll
-      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
-  const int64_t t0 = (int64_t)split * chunk;
-  const int64_t t1 = min(Tp, t0 + chunk);
-  for (int64_t t = t0; t < t1; t += 32) {
-    // A operand of the increment product (this lane's sample, terms 2J + hl)
-    const float4 *ap = reinterpret_cast<const float4 *>(dpa + ((t >> 5) * 64 + lane) * 8);
-    const float4 a03 = ap[0], a47 = ap[1];
-    const float av[6] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y};
-    // anchor: FP64 phase of the tile's centre sample at this lane's pixels,
-    // reduced to turns; it enters the product as term 11 (A = 1)
-    const double *pc = pmono + (t + 16) * 12;
-    f32x16 ph[2];
-#pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-      const double y = yg[blk], x = xg[blk];
-      const double a0 = pc[0] + y * (pc[2] + y * (pc[5] + y * pc[9]));
-      const double a1 = pc[1] + y * (pc[4] + y * pc[8]);
-      const double a2 = pc[3] + y * pc[7];
-      const double pa = fma(pc[10], wg[blk], a0 + x * (a1 + x * (a2 + x * pc[6])));
-      const float anc = (float)__builtin_amdgcn_fract(pa);
-      const float b5 = hl ? anc : bm[blk][5];
-#pragma unroll
-      for (int v = 0; v < 16; ++v) ph[blk][v] = 0.f;
-#pragma unroll
-      for (int J = 0; J < 5; ++J) ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[J], bm[blk][J], ph[blk], 0, 0, 0);
-      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[5], b5, ph[blk], 0, 0, 0);
-    }
-    // two contraction steps of 16 samples; ph[blk][8h + i] is sample
-    // 16h + 8(i/4) + 4hl + i%4 of pixel jl, which is K index 8hl + i of
-    // step h in the permuted sample order of the adjoint records
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      u32x4 b[GW][4];
-#pragma unroll
-      for (int g = 0; g < GW; ++g) {
-        const u32x4 *yq = ys + (((t >> 4) + h) * NGP + (g0 + g)) * 256 + lane;
-        b[g][0] = yq[0];
-        b[g][1] = yq[64];
-        b[g][2] = yq[128];
-        b[g][3] = yq[192];
-      }
-#pragma unroll
-      for (int blk = 0; blk < 2; ++blk) {
-        uint32_t w[4][4];  // [kind: c hi, c lo, s hi, s lo][word]
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          float c2[2], s2[2];
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const float f = __builtin_amdgcn_fractf(ph[blk][8 * h + 2 * m + e]);
-            c2[e] = __builtin_amdgcn_cosf(f);
-            s2[e] = __builtin_amdgcn_sinf(f);
-          }
-          split_pair<BF>(c2[0], c2[1], w[0][m], w[1][m]);
-          split_pair<BF>(s2[0], s2[1], w[2][m], w[3][m]);
-        }
-        const u32x4 A[4] = {u32x4{w[0][0], w[0][1], w[0][2], w[0][3]}, u32x4{w[1][0], w[1][1], w[1][2], w[1][3]},
-                            u32x4{w[2][0], w[2][1], w[2][2], w[2][3]}, u32x4{w[3][0], w[3][1], w[3][2], w[3][3]}};
-#pragma unroll
-        for (int g = 0; g < GW; ++g) acc[blk][g] = step6<BF>(A, b[g], acc[blk][g]);
-      }
-    }
-  }
-  adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -822,20 +662,6 @@ static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
                                                p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
 }
 
-template <bool BF>
-static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
-  float *part = reinterpret_cast<float *>(b.part);
-  const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
-  const float2 *sm = p.comb ? b.sq : nullptr;
-  if (p.GW == 2)
-    k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy, sm);
-  else
-    k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy, sm);
-}
-
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   const bool bf = p.prec == EXPENC_BF16_SPLIT;
   if (p.sh) {
@@ -850,8 +676,7 @@ void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) 
 void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   const bool bf = p.prec == EXPENC_BF16_SPLIT;
   if (p.sh) {
-    if (bf) adj_split_sh<true>(p, b, s);
-    else adj_split_sh<false>(p, b, s);
+    split_adjoint_sh_launch(p, b, s);
   } else {
     if (bf) adj_split_nt<true>(p, b, s);
     else adj_split_nt<false>(p, b, s);

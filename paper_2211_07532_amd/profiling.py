@@ -27,7 +27,7 @@ COPY_BYTES = 256 << 20
 
 def short_name(name: str) -> str:
     """'void expenc::k_adj_split_sh<2, false>(double const*, ...)' -> 'k_adj_split_sh<2, false>'."""
-    n = re.sub(r"^void\s+", "", name.strip())
+    n = re.sub(r"^void\s+", "", name.strip()).replace("(anonymous namespace)::", "")
     depth, out = 0, []
     for ch in n:
         if ch == "<":
