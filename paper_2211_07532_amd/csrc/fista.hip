@@ -373,10 +373,13 @@ struct FistaGroup {
       k_fill_d<<<(unsigned)ceil_div(P * B, 256), 256, 0, s>>>(L.lam_of(0), P * B, opts->lambda);
       EX_LAUNCHED("fill");
     } else {
-      EX_TRY(enc_pack_y(pf, y, L.eb, s));
-      EX_TRY(enc_adjoint_partials(pf, L.eb, s));
-      EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.v, pf.R, pf.nx, nullptr, nullptr, s, nullptr,
-                                    (int64_t)B * pf.R));
+      // A^H y in the solve's precision at one image per problem (as the power
+      // iteration), else in FP32
+      const EncPlan &pl = B == 1 ? p : pf;
+      EX_TRY(enc_pack_y(pl, y, L.eb, s));
+      EX_TRY(enc_adjoint_partials(pl, L.eb, s));
+      EX_TRY(enc_adjoint_reduce_out(pl, L.eb, op->smaps, L.v, pl.R, pl.nx, nullptr, nullptr, s, nullptr,
+                                    (int64_t)B * pl.R));
       EX_TRY(reduce_maxabs(L.v, pf.R, pf.R, P * B, opts->lambda_factor, L.dpart, L.lam_of(0), s));
     }
     k_fista_scalars<<<(unsigned)ceil_div(P * B, 256), 256, 0, s>>>(L.sc, P, B);
