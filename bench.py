@@ -132,6 +132,52 @@ def run_coil_compression(prec, ee, torch, w, op, y, v0, x_ref, nv=20):
             "nrmse_vs_32_coil_reconstruction": float(f"{d:.3e}")}
 
 
+def prox_bytes_design(n, levels):
+    """HBM bytes per pixel the fused prox moves (tiles' halo re-reads not
+    counted): each analysis level reads its low-pass block and writes four
+    bands, each synthesis level reads four bands and writes a block, and the
+    last level also reads x_prev and writes z (complex64 = 8 bytes)."""
+    b = 0.0
+    for j in range(levels):
+        f = 4.0 ** -j
+        b += 16 * f + 16 * f
+    return b + 16
+
+
+def run_prox(ee, torch):
+    """The wavelet prox step of the iteration (W, soft-threshold, W^H and the
+    momentum; one launch per level and direction) at batch scale: 180 images
+    of 152^2 (db4, J = 3) and 1024 of 208^2 (db4, J = 4).  Time per step from
+    HIP events on the launch stream over 20 steps; GB/s counts 32 bytes per
+    pixel (v and x_prev read, x and z written) and, separately, the bytes the
+    design moves (its coefficient and low-pass intermediates)."""
+    out = []
+    for n, levels, nimg in [(152, 3, 180), (208, 4, 1024)]:
+        g = torch.Generator(device="cuda").manual_seed(5)
+        shape = (nimg, n, n)
+        v = torch.randn(shape, dtype=torch.complex64, device="cuda", generator=g)
+        xp = torch.randn(shape, dtype=torch.complex64, device="cuda", generator=g)
+        x, z, wc = torch.empty_like(v), torch.empty_like(v), torch.empty_like(v)
+        tau = torch.full((nimg,), 0.5, dtype=torch.float64, device="cuda")
+        for _ in range(3):     # v is the call's scratch; its later contents stay finite
+            ee.wavelet_prox(v, levels, tau, xp, 0.3, "db4", out=(x, z, wc))
+        reps = 20
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ee.wavelet_prox(v, levels, tau, xp, 0.3, "db4", out=(x, z, wc))
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        px = nimg * n * n
+        gbs = 32.0 * px / (ms * 1e-3) / 1e9
+        out.append({"images": nimg, "grid": f"{n}x{n}", "wavelet": f"db4 J={levels}", "ms_per_step": round(ms, 4),
+                    "gb_per_s_algorithmic": round(gbs, 1), "hbm_frac_algorithmic": round(gbs / 8000.0, 4),
+                    "gb_per_s_design_bytes": round(prox_bytes_design(n, levels) * px / (ms * 1e-3) / 1e9, 1)})
+        del v, xp, x, z, wc
+    return out
+
+
 def run_balanced(forms, ee, torch, w, op, y, v0):
     """The paper's own regulariser on the 1.5 mm problem: undecimated db4 with
     one level, sigma/2 weights, balanced FISTA (kappa = L_A), 50 iterations;
@@ -357,6 +403,8 @@ def main():
     xh = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=head, lipschitz=0.0, power_v0=v0,
                   n_power=N_POWER).x
     line["coil_compression"] = [run_coil_compression(head, ee, torch, w, op, y, v0, xh, nv) for nv in (16, 20)]
+    print("[bench] wavelet prox at batch scale", file=sys.stderr, flush=True)
+    line["prox"] = run_prox(ee, torch)
     if args.batch_nprob > 0:
         print(f"[bench] batch of {args.batch_nprob} problems ({head})", file=sys.stderr, flush=True)
         line["batch"] = run_batch(args, head, ee, torch)

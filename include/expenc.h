@@ -173,6 +173,20 @@ int soft_threshold(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const 
                    float *w_out, float tau, void *stream);
 
 /*
+ * One proximal step of the l1 term of eq. 1 with the FISTA momentum (the
+ * iteration's wavelet part, Methods 2.1): x = W^H S_tau(W v) and
+ * z = x + beta (x - x_prev), for batch images of nx x ny (nx, ny multiples of
+ * 2^levels; all arrays [B][ny][nx] complex64 on the device).  S_tau is the
+ * soft_threshold above with tau[b] (device float64 [B]) for image b.  w
+ * receives the thresholded coefficients (Mallat layout).  v is overwritten:
+ * it and x carry the transform's intermediate low-pass blocks, so the call
+ * needs no workspace; x_prev and z must be other buffers than v, w and x.
+ * One launch per level and direction (rows and columns fused).
+ */
+int wavelet_prox(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch, float *v, float *w,
+                 float *x, const float *x_prev, float *z, double beta, const double *tau, void *stream);
+
+/*
  * Vector-Jacobian product of the soft-threshold (for differentiating through
  * the prox of eq. 1's l1 term).  With u = w/|w|, a = 1 - tau/|w|, b = tau/|w|,
  * the real-linear derivative of S_tau at |w| > tau is dw -> a dw + b u Re(conj(u) dw)

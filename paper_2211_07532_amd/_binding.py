@@ -75,6 +75,8 @@ SIGNATURES = {
     "wavelet_fwd": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp]),
     "wavelet_inv": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp]),
     "soft_threshold": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _vp, _vp, ctypes.c_float, _vp]),
+    "wavelet_prox": (ctypes.c_int, [_c_int, _c_int, _c_int, _c_int, _c_int, _vp, _vp, _vp, _vp, _vp,
+                                    ctypes.c_double, _vp, _vp]),
     "fista_solve": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _vp, _vp, ctypes.POINTER(FistaOpts), _vp,
                                    ctypes.c_size_t, _vp]),
     "cg_solve": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _vp, _vp, ctypes.POINTER(FistaOpts), _vp,

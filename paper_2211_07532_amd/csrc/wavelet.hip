@@ -276,9 +276,16 @@ constexpr int kTapsMax = 8;
 constexpr int kFwdTX = 16, kFwdTY = 8;  // analysis tile: coefficient positions per band
 constexpr int kInvT = 16;               // synthesis tile: output pixels per side
 
+// i mod n for i in [-n, 2n) with two compares; other i (a level narrower
+// than a tile's footprint) take the general remainder.
 __device__ inline int wrap(int i, int n) {
-  i %= n;
-  return i < 0 ? i + n : i;
+  if (i < 0) i += n;
+  if (i >= n) i -= n;
+  if (i < 0 || i >= n) {
+    i %= n;
+    if (i < 0) i += n;
+  }
+  return i;
 }
 
 // Analysis of one level: in (mx x my, row stride istride, image pitch
@@ -286,32 +293,33 @@ __device__ inline int wrap(int i, int n) {
 // three detail bands into w's level block (row stride nx, pitch wpitch),
 // soft-thresholded with tau[image] when tau is given; l1_part[image][tile]
 // receives the FP64 sum of the thresholded detail moduli when given.
-// Block: 256 threads; grid (ceil(hx/16), ceil(hy/8), images).
+// Block: 256 threads; grid (ceil(hx/16), ceil(hy/8), images).  TAPS (2 or 8)
+// fixes the tile's footprint at compile time.
+template <int TAPS>
 __global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ in, int istride, int64_t ipitch,
                                                     float2 *__restrict__ ll, int lstride, int64_t lpitch,
                                                     float2 *__restrict__ w, int nx, int64_t wpitch, int mx, int my,
                                                     FilterSet f, const double *__restrict__ tau,
                                                     double *__restrict__ l1_part, int l1_stride) {
-  constexpr int RY = 2 * kFwdTY + kTapsMax - 2, RX = 2 * kFwdTX + kTapsMax - 2;
+  constexpr int RY = 2 * kFwdTY + TAPS - 2, RX = 2 * kFwdTX + TAPS - 2;
   __shared__ float2 sin_[RY][RX];
   __shared__ float2 slo[RY][kFwdTX], shi[RY][kFwdTX];
   __shared__ double red[256];
   const int b = blockIdx.z;
   const int hx = mx >> 1, hy = my >> 1;
   const int tx0 = blockIdx.x * kFwdTX, ty0 = blockIdx.y * kFwdTY;
-  const int taps = f.taps;
-  const int ry = 2 * kFwdTY + taps - 2, rx = 2 * kFwdTX + taps - 2;
   in += b * ipitch;
-  for (int i = threadIdx.x; i < ry * rx; i += blockDim.x) {
-    const int r = i / rx, c = i - (i / rx) * rx;
+  for (int i = threadIdx.x; i < RY * RX; i += blockDim.x) {
+    const int r = i / RX, c = i % RX;
     sin_[r][c] = in[(int64_t)wrap(2 * ty0 + r, my) * istride + wrap(2 * tx0 + c, mx)];
   }
   __syncthreads();
   // rows: low and high outputs at tile column x for every staged row
-  for (int i = threadIdx.x; i < ry * kFwdTX; i += blockDim.x) {
+  for (int i = threadIdx.x; i < RY * kFwdTX; i += blockDim.x) {
     const int r = i / kFwdTX, x = i % kFwdTX;
     double ax = 0.0, ay = 0.0, dx = 0.0, dy = 0.0;
-    for (int k = 0; k < taps; ++k) {
+#pragma unroll
+    for (int k = 0; k < TAPS; ++k) {
       const float2 v = sin_[r][2 * x + k];
       ax += f.h[k] * v.x;
       ay += f.h[k] * v.y;
@@ -328,7 +336,8 @@ __global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ i
   double l1 = 0.0;
   if (oy < hy && ox < hx) {
     double ax = 0.0, ay = 0.0, dx = 0.0, dy = 0.0;
-    for (int k = 0; k < taps; ++k) {
+#pragma unroll
+    for (int k = 0; k < TAPS; ++k) {
       const float2 v = part ? shi[2 * y + k][x] : slo[2 * y + k][x];
       ax += f.h[k] * v.x;
       ay += f.h[k] * v.y;
@@ -367,39 +376,40 @@ __global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ i
 // stride lstride, pitch lpitch) and the detail bands from w's level block
 // (row stride nx, pitch wpitch) -> out (mx x my, row stride ostride, pitch
 // opitch); with zout, also zout = out + beta (out - xprev) (out's layout).
-// A 16 x 16 output tile needs 8 + taps/2 coefficient rows and columns of
-// each half, from i0 = m0/2 - taps/2 + 1 (periodic).
+// A 16 x 16 output tile needs 8 + TAPS/2 coefficient rows and columns of
+// each half, from i0 = m0/2 - TAPS/2 + 1 (periodic).
 // Block: 256 threads; grid (ceil(mx/16), ceil(my/16), images).
+template <int TAPS>
 __global__ __launch_bounds__(256) void k_idwt2_level(const float2 *__restrict__ ll, int lstride, int64_t lpitch,
                                                      const float2 *__restrict__ w, int nx, int64_t wpitch,
                                                      float2 *__restrict__ out, int ostride, int64_t opitch, int mx,
                                                      int my, FilterSet f, const float2 *__restrict__ xprev,
                                                      float2 *__restrict__ zout, double beta) {
-  constexpr int NI = kInvT / 2 + kTapsMax / 2;
+  constexpr int NI = kInvT / 2 + TAPS / 2;
   __shared__ float2 sc[2 * NI][2 * NI];  // [low | high rows][low | high columns]
   __shared__ float2 cp[kInvT][2 * NI];   // column-pass output rows
   const int b = blockIdx.z;
   const int hx = mx >> 1, hy = my >> 1;
   const int m0 = blockIdx.y * kInvT, n0 = blockIdx.x * kInvT;
-  const int taps = f.taps;
-  const int ni = kInvT / 2 + taps / 2;
-  const int i0 = m0 / 2 - taps / 2 + 1, j0 = n0 / 2 - taps / 2 + 1;
+  const int i0 = m0 / 2 - TAPS / 2 + 1, j0 = n0 / 2 - TAPS / 2 + 1;
   const float2 *wb = w + b * wpitch;
-  for (int i = threadIdx.x; i < 4 * ni * ni; i += blockDim.x) {
-    const int r = i / (2 * ni), c = i - (i / (2 * ni)) * (2 * ni);
-    const bool rh = r >= ni, ch = c >= ni;
-    const int gy = wrap(i0 + (rh ? r - ni : r), hy), gx = wrap(j0 + (ch ? c - ni : c), hx);
+  for (int i = threadIdx.x; i < 4 * NI * NI; i += blockDim.x) {
+    const int r = i / (2 * NI), c = i % (2 * NI);
+    const bool rh = r >= NI, ch = c >= NI;
+    const int gy = wrap(i0 + (rh ? r - NI : r), hy), gx = wrap(j0 + (ch ? c - NI : c), hx);
     sc[r][c] = (!rh && !ch) ? ll[b * lpitch + (int64_t)gy * lstride + gx]
                             : wb[(int64_t)(rh ? hy + gy : gy) * nx + (ch ? hx + gx : gx)];
   }
   __syncthreads();
   // columns: output row ml of every staged column
-  for (int i = threadIdx.x; i < kInvT * 2 * ni; i += blockDim.x) {
-    const int ml = i / (2 * ni), c = i - (i / (2 * ni)) * (2 * ni);
+  for (int i = threadIdx.x; i < kInvT * 2 * NI; i += blockDim.x) {
+    const int ml = i / (2 * NI), c = i % (2 * NI);
     double vx = 0.0, vy = 0.0;
-    for (int k = (ml & 1); k < taps; k += 2) {
-      const int il = (ml - k) / 2 + taps / 2 - 1;
-      const float2 a = sc[il][c], d = sc[ni + il][c];
+#pragma unroll
+    for (int kk = 0; kk < TAPS / 2; ++kk) {
+      const int k = 2 * kk + (ml & 1);
+      const int il = (ml - k) / 2 + TAPS / 2 - 1;
+      const float2 a = sc[il][c], d = sc[NI + il][c];
       vx += f.h[k] * a.x + f.g[k] * d.x;
       vy += f.h[k] * a.y + f.g[k] * d.y;
     }
@@ -410,9 +420,11 @@ __global__ __launch_bounds__(256) void k_idwt2_level(const float2 *__restrict__ 
   const int m = m0 + ml, n = n0 + nl;
   if (m < my && n < mx) {
     double vx = 0.0, vy = 0.0;
-    for (int k = (nl & 1); k < taps; k += 2) {
-      const int jl = (nl - k) / 2 + taps / 2 - 1;
-      const float2 a = cp[ml][jl], d = cp[ml][ni + jl];
+#pragma unroll
+    for (int kk = 0; kk < TAPS / 2; ++kk) {
+      const int k = 2 * kk + (nl & 1);
+      const int jl = (nl - k) / 2 + TAPS / 2 - 1;
+      const float2 a = cp[ml][jl], d = cp[ml][NI + jl];
       vx += f.h[k] * a.x + f.g[k] * d.x;
       vy += f.h[k] * a.y + f.g[k] * d.y;
     }
@@ -524,7 +536,7 @@ int dwt2_tiles(int nx, int ny, int level) {
 int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *v, float2 *w, float2 *xk,
               const float2 *xprev, float2 *z, double beta, const double *tau, double *l1_part, int l1_stride,
               hipStream_t s) {
-  if (f.taps > kTapsMax || (f.taps & 1)) return fail(EXPENC_EUNSUPPORTED, "filters of %d taps", f.taps);
+  if (f.taps != 2 && f.taps != kTapsMax) return fail(EXPENC_EUNSUPPORTED, "filters of %d taps", f.taps);
   if (nx % (1 << levels) || ny % (1 << levels)) return fail(EXPENC_EINVAL, "grid not a multiple of 2^levels");
   const int64_t pitch = (int64_t)nx * ny;
   auto fwd_buf = [&](int j) { return (j & 1) ? xk : v; };  // LL_j of the analysis, j >= 1
@@ -538,8 +550,12 @@ int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *
     const int lstride = last ? nx : mx >> 1;
     dim3 grid((unsigned)ceil_div(mx >> 1, kFwdTX), (unsigned)ceil_div(my >> 1, kFwdTY), (unsigned)nimg);
     double *lp = l1_part ? l1_part + (int64_t)j * nimg * l1_stride : nullptr;
-    k_dwt2_level<<<grid, 256, 0, s>>>(in, istride, pitch, ll, lstride, pitch, w, nx, pitch, mx, my, f, tau, lp,
-                                      l1_stride);
+    if (f.taps == 2)
+      k_dwt2_level<2><<<grid, 256, 0, s>>>(in, istride, pitch, ll, lstride, pitch, w, nx, pitch, mx, my, f, tau, lp,
+                                           l1_stride);
+    else
+      k_dwt2_level<8><<<grid, 256, 0, s>>>(in, istride, pitch, ll, lstride, pitch, w, nx, pitch, mx, my, f, tau, lp,
+                                           l1_stride);
     EX_LAUNCHED("dwt level");
   }
   for (int j = levels - 1; j >= 0; --j) {
@@ -550,8 +566,14 @@ int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *
     float2 *out = j == 0 ? xk : inv_buf(j);
     const int ostride = j == 0 ? nx : mx;
     dim3 grid((unsigned)ceil_div(mx, kInvT), (unsigned)ceil_div(my, kInvT), (unsigned)nimg);
-    k_idwt2_level<<<grid, 256, 0, s>>>(ll, lstride, pitch, w, nx, pitch, out, ostride, pitch, mx, my, f,
-                                       j == 0 ? xprev : nullptr, j == 0 ? z : nullptr, beta);
+    const float2 *xp = j == 0 ? xprev : nullptr;
+    float2 *zo = j == 0 ? z : nullptr;
+    if (f.taps == 2)
+      k_idwt2_level<2><<<grid, 256, 0, s>>>(ll, lstride, pitch, w, nx, pitch, out, ostride, pitch, mx, my, f, xp, zo,
+                                            beta);
+    else
+      k_idwt2_level<8><<<grid, 256, 0, s>>>(ll, lstride, pitch, w, nx, pitch, out, ostride, pitch, mx, my, f, xp, zo,
+                                            beta);
     EX_LAUNCHED("idwt level");
   }
   return EXPENC_OK;
@@ -586,6 +608,22 @@ extern "C" int wavelet_inv(int32_t nx, int32_t ny, int32_t levels, int32_t wavel
   }
   float2 *xx = reinterpret_cast<float2 *>(x);
   return dwt_inverse_levels(f, nx, ny, levels, batch, xx, xx, nullptr, nullptr, 0.0, s);
+}
+
+extern "C" int wavelet_prox(int32_t nx, int32_t ny, int32_t levels, int32_t wavelet, int32_t batch, float *v,
+                            float *w, float *x, const float *x_prev, float *z, double beta, const double *tau,
+                            void *stream) {
+  EX_TRY(check_grid(nx, ny, levels, batch));
+  if (batch > 65535) return fail(EXPENC_EINVAL, "batch %d > 65535", batch);
+  if (!v || !w || !x || !x_prev || !z || !tau) return fail(EXPENC_EINVAL, "NULL array");
+  if (v == w || v == x || w == x || x_prev == v || x_prev == w || x_prev == x || z == v || z == w || z == x ||
+      z == x_prev)
+    return fail(EXPENC_EINVAL, "v, w, x, x_prev and z must be distinct buffers");
+  FilterSet f;
+  EX_TRY(make_filter_set(wavelet, &f));
+  return dwt2_prox(f, nx, ny, levels, batch, reinterpret_cast<float2 *>(v), reinterpret_cast<float2 *>(w),
+                   reinterpret_cast<float2 *>(x), reinterpret_cast<const float2 *>(x_prev),
+                   reinterpret_cast<float2 *>(z), beta, tau, nullptr, 0, (hipStream_t)stream);
 }
 
 extern "C" int soft_threshold(int32_t nx, int32_t ny, int32_t levels, int32_t batch, const float *w_in,

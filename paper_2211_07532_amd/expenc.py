@@ -192,6 +192,26 @@ def soft_threshold(w: torch.Tensor, tau: float, levels: int, out: Optional[torch
     return o.reshape(w.shape)
 
 
+def wavelet_prox(v: torch.Tensor, levels: int, tau: torch.Tensor, x_prev: torch.Tensor, beta: float,
+                 wavelet="db4", out=None):
+    """One prox step with momentum: x = W^H S_tau(W v), z = x + beta (x - x_prev)
+    for v, x_prev [B][ny][nx] complex64 and tau [B] float64 (device).  v is
+    overwritten (the transform's scratch).  Returns (x, z, w); out may give
+    preallocated (x, z, w)."""
+    vb = v.reshape((-1,) + tuple(v.shape[-2:]))
+    _need(vb, torch.complex64, "v", None)
+    pb = x_prev.reshape(vb.shape)
+    _need(pb, torch.complex64, "x_prev", v.device)
+    _need(tau, torch.float64, "tau", v.device)
+    if tau.numel() != vb.shape[0]:
+        raise ValueError("tau needs one value per image")
+    x, z, w = out if out is not None else (torch.empty_like(vb), torch.empty_like(vb), torch.empty_like(vb))
+    check(_b.lib().wavelet_prox(vb.shape[2], vb.shape[1], levels, _wav(wavelet), vb.shape[0], _ptr(vb), _ptr(w),
+                                _ptr(x), _ptr(pb), _ptr(z), float(beta), _ptr(tau), _stream(v.device)),
+          "wavelet_prox")
+    return x.reshape(v.shape), z.reshape(v.shape), w.reshape(v.shape)
+
+
 @dataclasses.dataclass
 class FistaResult:
     x: torch.Tensor                      # [B][ny][nx]
