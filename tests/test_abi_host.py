@@ -119,3 +119,19 @@ def test_coil_arguments_rejected():
     assert lib.expenc_coil_compress(8, 9, 10, ctypes.c_void_p(1), 0, None, None, None, None, None, None, 0,
                                     None) == b.EXPENC_EINVAL
     assert lib.expenc_prewhiten(8, None, 0, None, 0, None, None, 0, None) == b.EXPENC_EINVAL
+
+
+def test_wavelet_prox_arguments_rejected():
+    """The prox entry point validates on the host before any launch: grid not
+    a multiple of 2^levels, NULL arrays, aliased buffers, unknown wavelet."""
+    b, lib = _lib()
+    p = [ctypes.c_void_p(0x1000 * (i + 1)) for i in range(6)]   # distinct, never dereferenced
+    v, w, x, xp, z, tau = p
+    assert lib.wavelet_prox(30, 32, 2, 1, 1, v, w, x, xp, z, 0.5, tau, None) == b.EXPENC_EINVAL
+    assert lib.wavelet_prox(32, 32, 2, 1, 1, None, w, x, xp, z, 0.5, tau, None) == b.EXPENC_EINVAL
+    assert lib.wavelet_prox(32, 32, 2, 1, 1, v, w, x, xp, z, 0.5, None, None) == b.EXPENC_EINVAL
+    assert lib.wavelet_prox(32, 32, 2, 1, 1, v, w, v, xp, z, 0.5, tau, None) == b.EXPENC_EINVAL
+    assert b"distinct" in lib.expenc_last_error()
+    assert lib.wavelet_prox(32, 32, 2, 1, 1, v, w, x, xp, xp, 0.5, tau, None) == b.EXPENC_EINVAL
+    assert lib.wavelet_prox(32, 32, 2, 7, 1, v, w, x, xp, z, 0.5, tau, None) == b.EXPENC_EINVAL
+    assert lib.wavelet_prox(32, 32, 2, 1, 0, v, w, x, xp, z, 0.5, tau, None) == b.EXPENC_EINVAL
