@@ -33,7 +33,23 @@ namespace {
 
 constexpr int kBins = 256;
 
-__global__ void k_swt_level(const float2 *__restrict__ u, int64_t ustride, float2 *__restrict__ bands,
+// i mod n for i within one period of [0, n) with two compares; others (taps
+// spanning more than the image) take the general remainder
+__device__ inline int wrap_i(int i, int n) {
+  if (i >= n) i -= n;
+  if (i < 0) i += n;
+  if (i < 0 || i >= n) {
+    i %= n;
+    if (i < 0) i += n;
+  }
+  return i;
+}
+
+// One analysis level at tap spacing d: the four bands of pixel i from its
+// TAPS x TAPS neighbourhood (FP64 sums in the same order for every band).
+// The wrapped row and column indices are formed once per pixel.
+template <int TAPS>
+__global__ __launch_bounds__(256) void k_swt_level(const float2 *__restrict__ u, int64_t ustride, float2 *__restrict__ bands,
                             int64_t bstride, float2 *__restrict__ llout, int64_t lstride, int nx, int ny, int d,
                             FilterSet f) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -44,13 +60,17 @@ __global__ void k_swt_level(const float2 *__restrict__ u, int64_t ustride, float
   bands += b * bstride;
   llout += b * lstride;
   const int yy = (int)(i / nx), xx = (int)(i % nx);
+  int cols[TAPS];
+#pragma unroll
+  for (int k = 0; k < TAPS; ++k) cols[k] = wrap_i(xx + d * k, nx);
   double s0x = 0, s0y = 0, s1x = 0, s1y = 0, s2x = 0, s2y = 0, slx = 0, sly = 0;
-  for (int ky = 0; ky < f.taps; ++ky) {
-    const int row = (int)(((int64_t)yy + (int64_t)d * ky) % ny);
+#pragma unroll 1
+  for (int ky = 0; ky < TAPS; ++ky) {
+    const float2 *urow = u + (int64_t)wrap_i(yy + d * ky, ny) * nx;
     const double hy = f.h[ky], gy = f.g[ky];
-    for (int kx = 0; kx < f.taps; ++kx) {
-      const int col = (int)(((int64_t)xx + (int64_t)d * kx) % nx);
-      const float2 v = u[(int64_t)row * nx + col];
+#pragma unroll
+    for (int kx = 0; kx < TAPS; ++kx) {
+      const float2 v = urow[cols[kx]];
       const double hx = f.h[kx], gx = f.g[kx];
       const double w0 = gx * hy, w1 = hx * gy, w2 = gx * gy, wl = hx * hy;
       s0x += w0 * v.x, s0y += w0 * v.y;
@@ -65,7 +85,10 @@ __global__ void k_swt_level(const float2 *__restrict__ u, int64_t ustride, float
   llout[i] = make_float2((float)(0.5 * slx), (float)(0.5 * sly));
 }
 
-__global__ void k_iswt_level(const float2 *__restrict__ bands, int64_t bstride, const float2 *__restrict__ ll,
+// The adjoint of one level: pixel i from the four bands at the TAPS x TAPS
+// neighbours i - d k.
+template <int TAPS>
+__global__ __launch_bounds__(256) void k_iswt_level(const float2 *__restrict__ bands, int64_t bstride, const float2 *__restrict__ ll,
                              int64_t lstride, float2 *__restrict__ u, int64_t ustride, int nx, int ny, int d,
                              FilterSet f) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -76,15 +99,17 @@ __global__ void k_iswt_level(const float2 *__restrict__ bands, int64_t bstride, 
   ll += b * lstride;
   u += b * ustride;
   const int yy = (int)(i / nx), xx = (int)(i % nx);
+  int cols[TAPS];
+#pragma unroll
+  for (int k = 0; k < TAPS; ++k) cols[k] = wrap_i(xx - d * k, nx);
   double sx = 0.0, sy = 0.0;
-  for (int ky = 0; ky < f.taps; ++ky) {
-    int64_t row = ((int64_t)yy - (int64_t)d * ky) % ny;
-    if (row < 0) row += ny;
+#pragma unroll 1
+  for (int ky = 0; ky < TAPS; ++ky) {
+    const int64_t row = (int64_t)wrap_i(yy - d * ky, ny) * nx;
     const double hy = f.h[ky], gy = f.g[ky];
-    for (int kx = 0; kx < f.taps; ++kx) {
-      int64_t col = ((int64_t)xx - (int64_t)d * kx) % nx;
-      if (col < 0) col += nx;
-      const int64_t o = row * nx + col;
+#pragma unroll
+    for (int kx = 0; kx < TAPS; ++kx) {
+      const int64_t o = row + cols[kx];
       const double hx = f.h[kx], gx = f.g[kx];
       const float2 a0 = bands[o], a1 = bands[N + o], a2 = bands[2 * N + o], al = ll[o];
       const double w0 = gx * hy, w1 = hx * gy, w2 = gx * gy, wl = hx * hy;
@@ -240,7 +265,10 @@ int swt_forward(const FilterSet &f, int nx, int ny, int J, int B, const float2 *
   for (int j = 0; j < J; ++j) {
     float2 *ll = (j == J - 1) ? w + (int64_t)3 * J * N : tmp + (int64_t)(j % 2) * B * N;
     const int64_t ls = (j == J - 1) ? nb * N : N;
-    k_swt_level<<<grid, 256, 0, s>>>(u, us, w + (int64_t)3 * j * N, nb * N, ll, ls, nx, ny, 1 << j, f);
+    if (f.taps == 2)
+      k_swt_level<2><<<grid, 256, 0, s>>>(u, us, w + (int64_t)3 * j * N, nb * N, ll, ls, nx, ny, 1 << j, f);
+    else
+      k_swt_level<8><<<grid, 256, 0, s>>>(u, us, w + (int64_t)3 * j * N, nb * N, ll, ls, nx, ny, 1 << j, f);
     EX_LAUNCHED("undecimated analysis");
     u = ll;
     us = ls;
@@ -258,7 +286,10 @@ int swt_adjoint(const FilterSet &f, int nx, int ny, int J, int B, const float2 *
   int64_t ls = nb * N;
   for (int j = J - 1; j >= 0; --j) {
     float2 *u = (j == 0) ? x : tmp + (int64_t)(j % 2) * B * N;
-    k_iswt_level<<<grid, 256, 0, s>>>(w + (int64_t)3 * j * N, nb * N, ll, ls, u, N, nx, ny, 1 << j, f);
+    if (f.taps == 2)
+      k_iswt_level<2><<<grid, 256, 0, s>>>(w + (int64_t)3 * j * N, nb * N, ll, ls, u, N, nx, ny, 1 << j, f);
+    else
+      k_iswt_level<8><<<grid, 256, 0, s>>>(w + (int64_t)3 * j * N, nb * N, ll, ls, u, N, nx, ny, 1 << j, f);
     EX_LAUNCHED("undecimated synthesis");
     ll = u;
     ls = N;
@@ -477,16 +508,20 @@ extern "C" int fista_balanced_solve(const expenc_op *op, int32_t batch, const fl
       float2 *aprev = (k % 2 == 0) ? L.a0 : L.a1;
       float2 *anew = (k % 2 == 0) ? L.a1 : L.a0;
       EX_TRY(swt_adjoint(f, op->nx, op->ny, J, B, L.beta, L.xb, L.tmp, cs));
+      // beta_0 = 0, so the first residual A W^H beta - y is -y without a
+      // forward product
+      auto residual_fp32 = [&](const EncPlan &q) -> int {
+        if (k == 0) return enc_pack_y(q, y2, L.eb, cs, -1.f);
+        EX_TRY(enc_build_z(q, op->smaps, L.xb, N, op->nx, L.eb, cs));
+        EX_TRY(enc_forward_partials(q, L.eb, cs));
+        return enc_forward_residual(q, L.eb, y2, cs);
+      };
       if (!split) {
-        EX_TRY(enc_build_z(p, op->smaps, L.xb, N, op->nx, L.eb, cs));
-        EX_TRY(enc_forward_partials(p, L.eb, cs));
-        EX_TRY(enc_forward_residual(p, L.eb, y2, cs));
+        EX_TRY(residual_fp32(p));
         EX_TRY(enc_adjoint_partials(p, L.eb, cs));
         EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.r, N, op->nx, nullptr, nullptr, cs));
       } else if (k % refine == 0 || k == K - 1) {
-        EX_TRY(enc_build_z(pf, op->smaps, L.xb, N, op->nx, L.eb, cs));
-        EX_TRY(enc_forward_partials(pf, L.eb, cs));
-        EX_TRY(enc_forward_residual(pf, L.eb, y2, cs));
+        EX_TRY(residual_fp32(pf));
         EX_TRY(enc_adjoint_partials(pf, L.eb, cs));
         EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.rref, N, op->nx, nullptr, nullptr, cs));
         EX_TRY(copy_f2(L.rref, L.r, img, cs));
