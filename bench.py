@@ -199,6 +199,28 @@ def run_balanced(forms, ee, torch, w, op, y, v0):
             "fista_iters": w.n_iter, "forms": out}
 
 
+def run_ls_vs_cs(forms, ee, torch, y, op, fista_rates):
+    """Least squares by CG stopped at 20 iterations (the paper's LS
+    reconstruction) against CS at 100 FISTA iterations, on the 1.5 mm problem:
+    CG iter/s per form and the CS / LS time ratio (the Discussion puts CS at
+    5-10x the LS time)."""
+    out = {}
+    n_ls, n_cs = 20, 100
+    for prec in forms:
+        ee.cg(y, op, n_ls, precision=prec)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ee.cg(y, op, n_ls, precision=prec)
+        torch.cuda.synchronize()
+        t_ls = (time.perf_counter() - t0) / reps
+        t_cs = n_cs / fista_rates[prec]
+        out[prec] = {"cg_iter_per_s": round(n_ls / t_ls, 2), "ls_ms": round(t_ls * 1e3, 3),
+                     "cs_ms": round(t_cs * 1e3, 3), "cs_over_ls_time": round(t_cs / t_ls, 2)}
+    return {"ls_iters": n_ls, "cs_iters": n_cs, "forms": out}
+
+
 def run_batch(args, prec, ee, torch):
     """The mixed-size batch (148 px / R=4, 170 px / R=5, 200 px / R=6 in turn,
     per-problem fields, dB0, coil maps and slice positions; 100 FISTA
@@ -399,6 +421,9 @@ def main():
         line["split_vs_fp32_fista_iter_ratio"] = round(h["fista_iter_per_s"] / out["fp32"]["fista_iter_per_s"], 3)
     print("[bench] balanced FISTA with the undecimated wavelet", file=sys.stderr, flush=True)
     line["balanced_fista"] = run_balanced(sorted({"fp32", head}), ee, torch, w, op, y, v0)
+    print("[bench] least squares (CG) against CS", file=sys.stderr, flush=True)
+    line["ls_vs_cs"] = run_ls_vs_cs([p for p in sorted({"fp32", head}) if p in out], ee, torch, y, op,
+                                    {p: out[p]["fista_iter_per_s"] for p in out})
     print(f"[bench] coil compression ({head})", file=sys.stderr, flush=True)
     xh = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=head, lipschitz=0.0, power_v0=v0,
                   n_power=N_POWER).x
