@@ -204,10 +204,10 @@ def run_ls_vs_cs(forms, ee, torch, y, op, fista_rates):
     reconstruction) against CS at 100 FISTA iterations, on the 1.5 mm problem:
     CG iter/s per form and the CS / LS time ratio (the Discussion puts CS at
     5-10x the LS time)."""
-    out = {}
+    out, xs = {}, {}
     n_ls, n_cs = 20, 100
     for prec in forms:
-        ee.cg(y, op, n_ls, precision=prec)
+        xs[prec] = ee.cg(y, op, n_ls, precision=prec)
         torch.cuda.synchronize()
         reps = 3
         t0 = time.perf_counter()
@@ -218,6 +218,10 @@ def run_ls_vs_cs(forms, ee, torch, y, op, fista_rates):
         t_cs = n_cs / fista_rates[prec]
         out[prec] = {"cg_iter_per_s": round(n_ls / t_ls, 2), "ls_ms": round(t_ls * 1e3, 3),
                      "cs_ms": round(t_cs * 1e3, 3), "cs_over_ls_time": round(t_cs / t_ls, 2)}
+        if prec != "fp32" and "fp32" in xs:
+            # the split CG has no anchors: its 20-iteration image against the FP32 one
+            d = float((xs[prec] - xs["fp32"]).norm() / xs["fp32"].norm())
+            out[prec]["x_rel_diff_vs_fp32"] = float(f"{d:.3e}")
     return {"ls_iters": n_ls, "cs_iters": n_cs, "forms": out}
 
 
@@ -422,7 +426,7 @@ def main():
     print("[bench] balanced FISTA with the undecimated wavelet", file=sys.stderr, flush=True)
     line["balanced_fista"] = run_balanced(sorted({"fp32", head}), ee, torch, w, op, y, v0)
     print("[bench] least squares (CG) against CS", file=sys.stderr, flush=True)
-    line["ls_vs_cs"] = run_ls_vs_cs([p for p in sorted({"fp32", head}) if p in out], ee, torch, y, op,
+    line["ls_vs_cs"] = run_ls_vs_cs([p for p in dict.fromkeys(("fp32", head)) if p in out], ee, torch, y, op,
                                     {p: out[p]["fista_iter_per_s"] for p in out})
     print(f"[bench] coil compression ({head})", file=sys.stderr, flush=True)
     xh = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=head, lipschitz=0.0, power_v0=v0,

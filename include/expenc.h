@@ -53,11 +53,17 @@ enum {
   EXPENC_ENONFINITE = -5     /* a solve produced NaN/Inf (reported after sync)   */
 };
 
-/* Arithmetic form of the encoding contraction. */
+/* Arithmetic form of the encoding contraction.  The fp16 form multiplies
+ * each operand it packs by a power of two chosen on the device from a bound
+ * on the operand's magnitudes (one extra pre-pass launch for an image
+ * operand or boundary data), and its reductions divide it out, so inputs of
+ * any magnitude within the FP32 range keep the form's accuracy; the fp16
+ * halves alone cover only ~2^-3 .. 65504 at full pair precision. */
 enum {
   EXPENC_FP32 = 0,        /* FP32 phase tile x FP32 operand on FP32 MFMA              */
   EXPENC_BF16_SPLIT = 1,  /* both operands split hi+lo in bf16, 3 MFMA products      */
-  EXPENC_FP16_SPLIT = 2   /* both operands split hi+lo in fp16, 3 MFMA products      */
+  EXPENC_FP16_SPLIT = 2   /* both operands split hi+lo in fp16, 3 MFMA products,
+                             operands scaled by powers of two (above)               */
 };
 
 /* Wavelet families (periodised, orthonormal, separable 2D). */

@@ -318,8 +318,10 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
 // Split-K reductions (fixed summation order)
 // ---------------------------------------------------------------------------
 
+// scl: the scaled form's operand powers of two ([P][2]), or NULL.
 __global__ void k_fwd_reduce_out(const float2 *__restrict__ part, int nsplit, int64_t T,
-                                 int64_t Tp, int C, int NC, int NCP, float2 *__restrict__ y) {
+                                 int64_t Tp, int C, int NC, int NCP, float2 *__restrict__ y,
+                                 const float *__restrict__ scl) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= T * NC) return;
   const int pz = blockIdx.y;
@@ -332,6 +334,11 @@ __global__ void k_fwd_reduce_out(const float2 *__restrict__ part, int nsplit, in
     float2 v = part[((int64_t)k * Tp + t) * NCP + col];
     sx += v.x;
     sy += v.y;
+  }
+  if (scl) {
+    const double inv = 1.0 / scl[2 * pz];
+    sx *= inv;
+    sy *= inv;
   }
   int b = col / C, c = col % C;
   y[((int64_t)b * T + t) * C + c] = make_float2((float)sx, (float)sy);
@@ -376,7 +383,8 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
                                                         int x_row_stride, const double *__restrict__ alpha_dev,
                                                         const float2 *__restrict__ add,
                                                         const float2 *__restrict__ base, int nxq,
-                                                        int64_t x_pstride, int pad_nx, int pad_ny) {
+                                                        int64_t x_pstride, int pad_nx, int pad_ny,
+                                                        const float *__restrict__ scl) {
   const int sub = threadIdx.x & 31;
   const int q = blockIdx.x * 8 + (threadIdx.x >> 5);  // pixel of x's grid
   const int npx = pad_nx > 0 ? pad_nx * pad_ny : R;
@@ -422,6 +430,11 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
       sy += __shfl_xor(sy, o, 32);
     }
     if (sub == 0) {
+      if (scl) {
+        const double inv = 1.0 / scl[2 * pz + 1];
+        sx *= inv;
+        sy *= inv;
+      }
       const int yy = r / nx, xx = r % nx;
       const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
       const double alpha = alpha_dev ? *alpha_dev : 1.0;
@@ -451,7 +464,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce_comb(const float2 *__restric
                                                          const double *__restrict__ alpha_dev,
                                                          const float2 *__restrict__ add,
                                                          const float2 *__restrict__ base, int nxq, int64_t x_pstride,
-                                                         int pad_nx, int pad_ny) {
+                                                         int pad_nx, int pad_ny, const float *__restrict__ scl) {
   const int q = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 2), j = threadIdx.x & 3;
   const int gx = pad_nx > 0 ? pad_nx : nx;
   if (q >= (pad_nx > 0 ? pad_nx * pad_ny : nx * ny)) return;  // uniform per group of four lanes
@@ -489,6 +502,11 @@ __global__ __launch_bounds__(256) void k_adj_reduce_comb(const float2 *__restric
     ty += __shfl(sy, l0 + u);
   }
   if (j != 0) return;
+  if (scl) {
+    const double inv = 1.0 / scl[2 * pz + 1];
+    tx *= inv;
+    ty *= inv;
+  }
   if (base) {
     tx += base[o].x;
     ty += base[o].y;
@@ -615,6 +633,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.prec = precision;
   q.has_dw0 = op->dw0 != nullptr;
   q.P = nprob;
+  q.scaled = precision == EXPENC_FP16_SPLIT;
   int tgt_fwd = target_workgroups(), tgt_adj = tgt_fwd;
   tuned_targets(op, batch, precision, &tgt_fwd, &tgt_adj);
   // forward: 256 sample rows per workgroup, split over pixels
@@ -624,6 +643,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Rp / 16));
     q.fwd_chunk = (int32_t)round_up(ceil_div(q.Rp, want), 16);
     q.fwd_split = (int32_t)ceil_div(q.Rp, q.fwd_chunk);
+    q.nwmax = (int32_t)split_grid(q.Tp / 256 * q.fwd_split) * q.NGY * 4;
   }
   // adjoint: 256 pixel rows per workgroup, split over samples
   {
@@ -662,6 +682,11 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
     b->zs = a.take<char>(P * p.Rp * (p.NCP / 16) * 256);
     b->ys = a.take<char>(P * p.Tp * (p.NCP / 16) * 256);
     if (p.comb) b->sq = a.take<float2>(P * p.Rp * p.NCP);
+    if (p.scaled) {
+      b->scl = a.take<float>(P * 2);
+      b->amax = a.take<float>(P * 3 * kAmaxBlocks);
+      b->wmax = a.take<float>(P * p.nwmax);
+    }
     if (p.sh) {
       b->pmono = a.take<double>(P * p.Tp * 12);
       b->dpa = a.take<float>(P * p.Tp * 16);
@@ -853,7 +878,8 @@ int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 }
 
 int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s) {
-  k_fwd_reduce_out<<<grid_p(p.T * p.NC, 256, p.P), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC, p.NCP, y);
+  k_fwd_reduce_out<<<grid_p(p.T * p.NC, 256, p.P), 256, 0, s>>>(b.part, p.fwd_split, p.T, p.Tp, p.C, p.NC, p.NCP, y,
+                                                                  p.scaled ? b.scl : nullptr);
   EX_LAUNCHED("forward reduce");
   return EXPENC_OK;
 }
@@ -876,14 +902,14 @@ int enc_adjoint_reduce_out(const EncPlan &p, const EncBuffers &b, const float *s
   if (p.comb) {
     k_adj_reduce_comb<<<grid_p(npx * 4, 256, p.P), 256, 0, s>>>(b.part, p.adj_split * p.NGY, p.Rp, p.nx, p.ny, x,
                                                           x_row_stride, alpha_dev, add, base, p.nxq, x_pstride,
-                                                          pad_nx, pad_ny);
+                                                          pad_nx, pad_ny, p.scaled ? b.scl : nullptr);
     EX_LAUNCHED("adjoint reduce");
     return EXPENC_OK;
   }
   k_adj_reduce_out<<<grid_p(npx, 8, p.P), 256, 0, s>>>(b.part, p.adj_split, p.R, p.Rp, p.nx, p.C, p.B, p.NCP,
                                                        reinterpret_cast<const float2 *>(smaps), x, x_stride,
                                                        x_row_stride, alpha_dev, add, base, p.nxq, x_pstride,
-                                                       pad_nx, pad_ny);
+                                                       pad_nx, pad_ny, p.scaled ? b.scl : nullptr);
   EX_LAUNCHED("adjoint reduce");
   return EXPENC_OK;
 }

@@ -214,7 +214,17 @@ struct EncPlan {
   // every kernel takes the problem index as an extra grid dimension.
   int32_t P = 1;
   const double *z0s = nullptr;            // [P] slice positions (SH basis), or NULL: z0 for all
+  // fp16 split form: every packed operand is multiplied by a power of two
+  // chosen on the device from a bound on its magnitudes (the fp16 halves
+  // overflow above 65504 and lose the lo half's precision below ~2^-3), and
+  // the reductions divide it out.  nwmax: per-problem slots of the forward
+  // contraction's per-wave output maxima (the residual operand's bound).
+  bool scaled = false;
+  int32_t nwmax = 0;
 };
+
+// Workgroups (per problem) of the magnitude pre-pass of the scaled form.
+constexpr int kAmaxBlocks = 64;
 
 int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p, int32_t nprob = 1);
 
@@ -234,6 +244,10 @@ struct EncBuffers {
   double *dwq = nullptr;   // split + SH: [Rp] dw0/2pi in the row-padded pixel layout
   float *ddw = nullptr;    // split + SH: [Rp] dwq minus its 16-pixel tile centre (FP32)
   float2 *sq = nullptr;    // split, single image: [Rp][NCP] S_c(r) in the partial-sum layout (0 on padding)
+  float *scl = nullptr;    // scaled form: [P][2] powers of two of the forward (0) and adjoint (1) operands
+  float *amax = nullptr;   // scaled form: [3][P][kAmaxBlocks] per-workgroup bounds of pre-passes (operand,
+                           // measured data, coil maps)
+  float *wmax = nullptr;   // scaled form: [P][nwmax] per-wave max |partial sum| of the forward contraction
 };
 
 size_t enc_operand_bytes(const EncPlan &p);

@@ -105,9 +105,18 @@ __device__ inline void phase_tile16(const double (&pv)[NT], const float (&pf)[NT
   pack_tile16<BF>(c, sn, A);
 }
 
+// Slot of this wave in the per-problem maxima array of a forward launch.
+__device__ inline int wave_slot() { return (int)((blockIdx.y * gridDim.x + blockIdx.x) * 4 + (threadIdx.x >> 6)); }
+
+// Writes a wave's forward partial sums; with wmax (scaled form) also the
+// wave's max |value| into its slot (a bound for the residual operand).  Per
+// wave, with no workgroup barrier: a barrier in the epilogue would hold every
+// workgroup until its slowest wave ends (measured +3 % kernel time).
 template <int GW>
-__device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0, int lane, f32x16 (&acc)[2][GW]) {
+__device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0, int lane, f32x16 (&acc)[2][GW],
+                                      float *wmax) {
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+  float m = 0.f;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -117,7 +126,13 @@ __device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0,
         const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
         const int col = (g0 + g) * 16 + c16;
         dst[(row * NCP + col) * 2 + im] = acc[a][g][v];
+        m = fmaxf(m, fabsf(acc[a][g][v]));
       }
+  if (wmax) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if (lane == 0) wmax[wave_slot()] = m;
+  }
 }
 
 // Forward, split form: rows = samples, reduction over pixels (16 per step).
@@ -166,7 +181,7 @@ __global__ __launch_bounds__(256) void k_fwd_split(const double *__restrict__ ka
       acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
     }
   }
-  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc);
+  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc, nullptr);
 }
 
 // Adjoint, split form: rows = pixels, reduction over samples (16 per step).
@@ -248,11 +263,16 @@ template <int GW, bool BF>
 __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__ pmono, const double *__restrict__ dwq,
                                                       const float *__restrict__ ddw, const u32x4 *__restrict__ zs,
                                                       float *__restrict__ part, int64_t Tp, int Rp, int NCP, int chunk,
-                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy) {
+                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy,
+                                                      float *__restrict__ wmax) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  if (wmax) wmax += (int64_t)blockIdx.z * gridDim.y * gridDim.x * 4;
+  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) {
+    if (wmax && lane == 0) wmax[wave_slot()] = 0.f;
+    return;
+  }
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
@@ -309,7 +329,7 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__
       acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
     }
   }
-  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc);
+  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc, wmax);
 }
 
 // ---------------------------------------------------------------------------
@@ -335,13 +355,123 @@ __device__ inline void write_record(u32x4 *out, int64_t q, int g, int NGP, int l
   o[192] = u32x4{l2[0], l2[1], l2[2], l2[3]};
 }
 
+// ---------------------------------------------------------------------------
+// Operand scaling of the fp16 form.  An fp16 hi/lo pair represents |v| up to
+// 65504 and keeps its ~22-bit precision only while the lo half is normal,
+// i.e. for |v| above ~2^-3.  The fp16 form therefore multiplies each packed
+// operand by a power of two s = 2^(14 - e), where M < 2^e bounds the
+// operand's magnitudes, so that every value lies below 2^14 and values down
+// to 2^-17 of the largest keep full precision; the reductions that read the
+// contraction's output divide s out again (exact for powers of two).
+// M comes from a pre-pass over the operand (image operand, or data given at
+// the boundary) or from the forward contraction's per-wave output maxima
+// (the residual operand, summed over nsplit partial sums).
+// ---------------------------------------------------------------------------
+
+__device__ inline float pow2_scale(float m) {
+  if (!(m > 0.f) || !(m <= 3.0e38f)) return 1.f;  // zero, NaN or infinite: unscaled
+  int e;
+  (void)frexpf(m, &e);
+  return ldexpf(1.f, min(126, max(-126, 14 - e)));
+}
+
+// Max of v[0..n) over a 256-thread workgroup; every thread returns it.
+__device__ inline float block_max(const float *__restrict__ v, int n) {
+  __shared__ float wm[4];
+  float m = 0.f;
+  int i = threadIdx.x;
+  for (; i + 768 < n; i += 1024) {  // four independent loads in flight
+    const float a = v[i], b = v[i + 256], c = v[i + 512], d = v[i + 768];
+    m = fmaxf(m, fmaxf(fmaxf(a, b), fmaxf(c, d)));
+  }
+  for (; i < n; i += 256) m = fmaxf(m, v[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  __syncthreads();  // an earlier call's readers are done with wm
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  return fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+}
+
+__device__ inline void write_block_max(float m, float *__restrict__ out) {
+  __shared__ float wm[4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+  if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]));
+}
+
+// Pre-pass of the image operand: per-workgroup max of |Re u| + |Im u| over
+// the encoded pixels and images, u = x - xsub.  With the same bound of the
+// coil maps (taken once per preparation), their product bounds the
+// components of Z = S u.  Grid (kAmaxBlocks, P), 256 threads.
+__global__ __launch_bounds__(256) void k_amax_z(const float2 *__restrict__ x, const float2 *__restrict__ xsub,
+                                                int64_t x_stride, int x_row_stride, int nx, int ny, int B,
+                                                int64_t x_pstride, float *__restrict__ amax) {
+  const int pz = blockIdx.y;
+  const int R = nx * ny;
+  x += pz * x_pstride;
+  if (xsub) xsub += pz * x_pstride;
+  float m = 0.f;
+  for (int r = blockIdx.x * 256 + threadIdx.x; r < R; r += gridDim.x * 256) {
+    const int yy = r / nx, xx = r % nx;
+    for (int b = 0; b < B; ++b) {
+      const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
+      float2 u = x[o];
+      if (xsub) {
+        u.x -= xsub[o].x;
+        u.y -= xsub[o].y;
+      }
+      m = fmaxf(m, fabsf(u.x) + fabsf(u.y));
+    }
+  }
+  write_block_max(m, amax + pz * kAmaxBlocks + blockIdx.x);
+}
+
+// Pre-pass of the coil maps [P][n]: per-workgroup max of |Re S| + |Im S|.
+__global__ __launch_bounds__(256) void k_amax_l1(const float2 *__restrict__ v, int64_t n, float *__restrict__ amax) {
+  const int pz = blockIdx.y;
+  v += pz * n;
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float2 a = v[i];
+    m = fmaxf(m, fabsf(a.x) + fabsf(a.y));
+  }
+  write_block_max(m, amax + pz * kAmaxBlocks + blockIdx.x);
+}
+
+// Pre-pass of a complex array [P][n] (stride pstride): per-workgroup max of
+// the component magnitudes.  Grid (kAmaxBlocks, P), 256 threads.
+__global__ __launch_bounds__(256) void k_amax_c(const float2 *__restrict__ v, int64_t n, int64_t pstride,
+                                                float *__restrict__ amax) {
+  const int pz = blockIdx.y;
+  v += pz * pstride;
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float2 a = v[i];
+    m = fmaxf(m, fmaxf(fabsf(a.x), fabsf(a.y)));
+  }
+  write_block_max(m, amax + pz * kAmaxBlocks + blockIdx.x);
+}
+
 template <bool BF>
 __global__ __launch_bounds__(256) void k_build_z_split(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
                                 const float2 *__restrict__ xsub, int64_t x_stride, int x_row_stride, int nx, int ny,
                                 int nxq, int Rp, int C, int NC, int NGP, u32x4 *__restrict__ zs, int64_t x_pstride,
-                                const float2 *__restrict__ sq) {
+                                const float2 *__restrict__ sq, const float *__restrict__ amax,
+                                float *__restrict__ scl) {
   const int R = nx * ny;
   const int pz = blockIdx.y;  // problem
+  // scaled form: every workgroup derives the same power of two from the pre-pass
+  float sc = 1.f;
+  if (scl) {
+    const int P = gridDim.y;
+    const float mu = block_max(amax + pz * kAmaxBlocks, kAmaxBlocks);
+    const float ms = block_max(amax + (2 * P + pz) * kAmaxBlocks, kAmaxBlocks);
+    sc = pow2_scale(mu * ms);
+    if (blockIdx.x == 0 && threadIdx.x == 0) scl[2 * pz] = sc;
+  }
   smaps += (int64_t)pz * C * R;
   if (sq) sq += (int64_t)pz * Rp * NGP * 16;
   x += pz * x_pstride;
@@ -372,7 +502,7 @@ __global__ __launch_bounds__(256) void k_build_z_split(const float2 *__restrict_
       }
       // (the S table, when given, holds the same value in row-major order)
       const float2 s = sq ? sq[(int64_t)rq * NGP * 16 + col] : smaps[(int64_t)c * R + r];
-      z = make_float2(s.x * u.x - s.y * u.y, s.x * u.y + s.y * u.x);
+      z = make_float2((s.x * u.x - s.y * u.y) * sc, (s.x * u.y + s.y * u.x) * sc);
     }
     b1[i] = im ? z.y : z.x;
     b2[i] = im ? z.x : -z.y;
@@ -388,9 +518,25 @@ template <bool BF>
 __global__ __launch_bounds__(256) void k_pack_y_split(const float2 *__restrict__ src_abi,
                                                       const float2 *__restrict__ src_part, int nsplit,
                                                       const float2 *__restrict__ y_meas, int64_t T, int64_t Tp, int C,
-                                                      int NC, int NCP, u32x4 *__restrict__ ys, int perm) {
+                                                      int NC, int NCP, u32x4 *__restrict__ ys, int perm,
+                                                      const float *__restrict__ bnd, int nbnd,
+                                                      const float *__restrict__ bnd_meas, float *__restrict__ scl) {
   const int NGP = NCP / 16;
   const int pz = blockIdx.y;  // problem
+  // scaled form: the bound of the operand is max(bnd) (src_abi: its pre-pass;
+  // src_part: the forward's per-wave maxima, in units of the forward operand's
+  // scale, times nsplit) plus max(bnd_meas) (the pre-pass of y_meas, if any)
+  float sc = 1.f, inv_z = 1.f;
+  if (scl) {
+    float m = block_max(bnd + (int64_t)pz * nbnd, nbnd);
+    if (src_part) {
+      inv_z = 1.f / scl[2 * pz];
+      m = m * (float)nsplit * inv_z;
+    }
+    if (bnd_meas) m += block_max(bnd_meas + pz * kAmaxBlocks, kAmaxBlocks);
+    sc = pow2_scale(m);
+    if (blockIdx.x == 0 && threadIdx.x == 0) scl[2 * pz + 1] = sc;
+  }
   if (src_abi) src_abi += pz * T * NC;
   if (src_part) src_part += pz * nsplit * Tp * NCP;
   if (y_meas) y_meas += pz * T * NC;
@@ -444,6 +590,11 @@ __global__ __launch_bounds__(256) void k_pack_y_split(const float2 *__restrict__
           y[i].y += v.y;
         }
     }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      y[i].x *= inv_z;
+      y[i].y *= inv_z;
+    }
     if (y_meas) {
 #pragma unroll
       for (int i = 0; i < 8; ++i)
@@ -453,6 +604,11 @@ __global__ __launch_bounds__(256) void k_pack_y_split(const float2 *__restrict__
           y[i].y -= m.y;
         }
     }
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    y[i].x *= sc;
+    y[i].y *= sc;
   }
   float b1[8], b2[8];
 #pragma unroll
@@ -576,6 +732,13 @@ __global__ void k_prep_sq(const float2 *__restrict__ smaps, int nx, int ny, int 
 
 int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
   auto gp = [&](int64_t n) { return dim3((unsigned)ceil_div(n, 256), (unsigned)p.P); };
+  if (p.scaled) {
+    // bound of the coil maps for the fp16 operand scaling (third amax section)
+    if (!b.scl || !b.amax || !b.wmax) return fail(EXPENC_EINVAL, "scale buffers of an fp16 plan are not carved");
+    k_amax_l1<<<dim3(kAmaxBlocks, (unsigned)p.P), 256, 0, s>>>(reinterpret_cast<const float2 *>(op->smaps),
+                                                               (int64_t)p.C * p.R, b.amax + (size_t)2 * p.P * kAmaxBlocks);
+    EX_LAUNCHED("coil-map bound");
+  }
   if (p.comb) {
     if (!b.sq) return fail(EXPENC_EINVAL, "coil table of a single-image split plan is not carved");
     k_prep_sq<<<gp((int64_t)p.Rp * p.NCP), 256, 0, s>>>(reinterpret_cast<const float2 *>(op->smaps), p.nx, p.ny,
@@ -654,12 +817,13 @@ static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   dim3 grid(split_grid(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
   float *part = reinterpret_cast<float *>(b.part);
   const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
+  float *wmax = p.scaled ? b.wmax : nullptr;
   if (p.GW == 2)
     k_fwd_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.ddw, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
-                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy, wmax);
   else
     k_fwd_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.ddw, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
-                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy);
+                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy, wmax);
 }
 
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
@@ -690,12 +854,19 @@ int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const f
   const dim3 nb((unsigned)ceil_div(n, 256), (unsigned)p.P);
   const float2 *sm = reinterpret_cast<const float2 *>(smaps);
   u32x4 *zs = reinterpret_cast<u32x4 *>(b.zs);
+  if (p.scaled) {
+    if (!b.scl || !b.amax || !b.wmax) return fail(EXPENC_EINVAL, "scale buffers of an fp16 plan are not carved");
+    k_amax_z<<<dim3(kAmaxBlocks, (unsigned)p.P), 256, 0, s>>>(x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.B,
+                                                              x_pstride, b.amax);
+    EX_LAUNCHED("operand bound");
+  }
+  float *scl = p.scaled ? b.scl : nullptr;
   if (p.prec == EXPENC_BF16_SPLIT)
     k_build_z_split<true><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
-                                             p.NC, NGP, zs, x_pstride, p.comb ? b.sq : nullptr);
+                                             p.NC, NGP, zs, x_pstride, p.comb ? b.sq : nullptr, b.amax, scl);
   else
     k_build_z_split<false><<<nb, 256, 0, s>>>(sm, x, xsub, x_stride, x_row_stride, p.nx, p.ny, p.nxq, p.Rp, p.C,
-                                              p.NC, NGP, zs, x_pstride, p.comb ? b.sq : nullptr);
+                                              p.NC, NGP, zs, x_pstride, p.comb ? b.sq : nullptr, b.amax, scl);
   EX_LAUNCHED("build_z split");
   return EXPENC_OK;
 }
@@ -707,12 +878,45 @@ int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, cons
   const dim3 nb((unsigned)ceil_div(n, 256), (unsigned)p.P);
   u32x4 *ys = reinterpret_cast<u32x4 *>(b.ys);
   const float2 *part = from_partials ? b.part : nullptr;
+  const float *bnd = nullptr, *bnd_meas = nullptr;
+  int nbnd = 0;
+  if (p.scaled) {
+    if (!b.scl || !b.amax || !b.wmax) return fail(EXPENC_EINVAL, "scale buffers of an fp16 plan are not carved");
+    const dim3 ng(kAmaxBlocks, (unsigned)p.P);
+    const int64_t ny_el = p.T * p.NC;  // [B][T][C] per problem
+    if (!from_partials) {
+      k_amax_c<<<ng, 256, 0, s>>>(y_abi, ny_el, ny_el, b.amax);
+      EX_LAUNCHED("operand bound");
+      bnd = b.amax;
+      nbnd = kAmaxBlocks;
+    } else {
+      if (p.sh) {
+        // the polynomial forward writes its per-wave output maxima
+        bnd = b.wmax;
+        nbnd = p.nwmax;
+      } else {
+        // (the maps-kind forward does not: a pre-pass over its partial sums)
+        const int64_t np = (int64_t)p.fwd_split * p.Tp * p.NCP;
+        k_amax_c<<<ng, 256, 0, s>>>(b.part, np, np, b.amax);
+        EX_LAUNCHED("operand bound");
+        bnd = b.amax;
+        nbnd = kAmaxBlocks;
+      }
+      if (y_meas) {
+        float *am = b.amax + (size_t)p.P * kAmaxBlocks;
+        k_amax_c<<<ng, 256, 0, s>>>(y_meas, ny_el, ny_el, am);
+        EX_LAUNCHED("operand bound");
+        bnd_meas = am;
+      }
+    }
+  }
+  float *scl = p.scaled ? b.scl : nullptr;
   if (p.prec == EXPENC_BF16_SPLIT)
     k_pack_y_split<true><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys,
-                                            p.sh ? 1 : 0);
+                                            p.sh ? 1 : 0, bnd, nbnd, bnd_meas, scl);
   else
     k_pack_y_split<false><<<nb, 256, 0, s>>>(y_abi, part, p.fwd_split, y_meas, p.T, p.Tp, p.C, p.NC, p.NCP, ys,
-                                             p.sh ? 1 : 0);
+                                             p.sh ? 1 : 0, bnd, nbnd, bnd_meas, scl);
   EX_LAUNCHED("pack_y split");
   return EXPENC_OK;
 }

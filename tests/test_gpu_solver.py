@@ -202,3 +202,25 @@ def test_cg_matches_oracle():
     x2 = ee.cg(case.to_dev(np.stack([y, 0.5 * y])), case.op, 3).cpu().numpy()
     assert solve.nrmse(x2[0], ref2) <= 1e-5
     assert solve.nrmse(x2[1], 0.5 * ref2) <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
+def test_cg_split_matches_oracle(prec, sh):
+    """CG in the split forms (no FP32 anchors).  Their operator error (about
+    4e-6 bf16, 1e-6 fp16 relative) is amplified by CG like any rounding (see
+    the FP32 test), so 3 and 10 iterations are compared at 2e-4 / 3e-3 and 20
+    iterations by the normal-equation residual within 10 % of the oracle's."""
+    ee = _ee()
+    w = synth.TINY
+    case = Case(w, sh=sh)
+    op = _oracle_op(case)
+    y = c64(op.A(case.x_noisy))
+    for n, bar in ((3, 2e-4), (10, 3e-3)):
+        x = ee.cg(case.to_dev(y), case.op, n, precision=prec).cpu().numpy()
+        assert solve.nrmse(x, solve.cg_ls(op, y, n)) <= bar, n
+    ref = solve.cg_ls(op, y, 20)
+    x = ee.cg(case.to_dev(y), case.op, 20, precision=prec).cpu().numpy().astype(np.complex128)
+    res = np.linalg.norm(op.AH(op.A(x) - y))
+    res_ref = np.linalg.norm(op.AH(op.A(ref) - y))
+    assert abs(res - res_ref) <= 0.1 * res_ref + 1e-6 * np.linalg.norm(op.AH(y))

@@ -112,3 +112,54 @@ def test_split_fista_with_anchors(prec, variant, sh):
     print(f"split FISTA {prec} {variant} sh={sh}: NRMSE {e:.2e} (anchored every 10), {e0:.2e} (no intermediate anchor)",
           flush=True)
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_split_operators_scale_invariant(prec, sh):
+    """The split forms keep their accuracy on inputs of any magnitude: the
+    fp16 halves alone would flush values below ~6e-8 to zero and overflow
+    above 65504, so the fp16 form scales every operand by a power of two
+    chosen on the device.  Inputs scaled by 1e-12 ... 1e6 (bf16 has the FP32
+    exponent range) must meet the unscaled case's error level."""
+    ee = _ee()
+    w = synth.TINY
+    case = Case(w, sh=sh)
+    x0 = c64(synth.random_complex((2, w.npix), 63))
+    x0[0] = case.x_noisy
+    g0 = c64(synth.random_complex((2, w.nsamples, w.ncoils), 64))
+    errs = {}
+    for s in (1.0, 1e-12, 1e-4, 1e6):
+        x = c64(x0 * s)
+        g = c64(g0 * s)
+        e_f = rel(ee.forward(case.to_dev(x), case.op, precision=prec).cpu().numpy(),
+                  encoding.forward(x, *case.oracle_args()))
+        e_a = rel(ee.adjoint(case.to_dev(g), case.op, precision=prec).cpu().numpy(),
+                  encoding.adjoint(g, *case.oracle_args()))
+        errs[s] = (e_f, e_a)
+    print(f"split {prec} sh={sh} errors by input scale: {errs}", flush=True)
+    e1f, e1a = errs[1.0]
+    for s, (e_f, e_a) in errs.items():
+        assert e_f <= 3 * e1f + 1e-6 and e_a <= 3 * e1a + 1e-6, s
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+def test_split_fista_on_scaled_data(prec):
+    """The anchored split FISTA is equivariant in the data scale: with y and
+    lambda scaled by s the solution scales by s.  Data scaled by 2^-23 and
+    2^17 (outside the fp16 range either way) against the oracle's unscaled
+    solve."""
+    ee = _ee()
+    w = synth.TINY
+    case = Case(w, sh=True)
+    op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
+    y = c64(op.A(case.x_noisy))
+    L = solve.power_lipschitz(op, c64(synth.power_start(w.npix, 4)), 30)
+    lam = solve.lambda_rule(op, y)
+    ref = solve.fista(op, y, L, lam, w.n_iter, w.levels, w.wavelet, w.n_pad)
+    for s in (2.0 ** -23, 2.0 ** 17):  # powers of two: the scaled data are exact
+        res = ee.fista(case.to_dev(y * s), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L,
+                       lam=lam * s, refine_every=10)
+        e = solve.nrmse(res.x.cpu().numpy().reshape(-1) / s, ref)
+        print(f"split FISTA {prec} data scale {s:.1e}: NRMSE {e:.2e}", flush=True)
+        assert e <= 1e-4, s
