@@ -6,6 +6,7 @@ and the seeded input generator.  Takes several minutes on 8 cores.
 
     python tests/golden/make_golden.py            # FISTA golden (mm15_fista.npz)
     python tests/golden/make_golden.py balanced   # balanced-FISTA golden (mm15_balanced.npz)
+    python tests/golden/make_golden.py mm11       # 1.1 mm FISTA golden (mm11_fista.npz; ~1 h on 8 cores)
 """
 import os
 import sys
@@ -40,6 +41,27 @@ def main():
     print(f"wrote mm15_fista.npz: L={L:.6e} lambda={lam:.6e} ({time.time() - t0:.0f} s)")
 
 
+def main_mm11():
+    """The 1.1 mm workload (200 x 200, 32 coils, T = 40000, 3rd-order field
+    + dB0, diffusion-weighted phantom): 100 FISTA iterations with a 4-level
+    db4 wavelet on the 208 x 208 grid, L from 20 power steps from the seeded
+    start vector, lambda = 1e-3 max|A^H y|."""
+    w = synth.MM11
+    p = synth.make_problem(w)
+    basis = encoding.sh_basis(w.n, w.fov, w.z0, w.nbasis)
+    op = solve.Operator(c64(p.smaps), p.coef, p.time, basis, p.dw0, w.n)
+    t0 = time.time()
+    y = c64(op.A(c64(p.x_noisy)))
+    v0 = c64(synth.power_start(w.npix, 7))
+    L = solve.power_lipschitz(op, v0, 20)
+    lam = solve.lambda_rule(op, y)
+    print(f"L={L:.6e} lambda={lam:.6e} ({time.time() - t0:.0f} s)", flush=True)
+    x = solve.fista(op, y, L, lam, w.n_iter, w.levels, w.wavelet, w.n_pad)
+    np.savez_compressed(os.path.join(HERE, "mm11_fista.npz"), x_hat=x.astype(np.complex128), lipschitz=L,
+                        lam=lam, n_iter=w.n_iter, n_power=20, power_seed=7)
+    print(f"wrote mm11_fista.npz: L={L:.6e} lambda={lam:.6e} ({time.time() - t0:.0f} s)")
+
+
 def main_balanced():
     """The paper's regulariser on the same problem: undecimated db4 with one
     level, sigma/2 weights from W A^H y, balanced FISTA with kappa = L_A,
@@ -62,5 +84,7 @@ def main_balanced():
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "balanced":
         main_balanced()
+    elif len(sys.argv) > 1 and sys.argv[1] == "mm11":
+        main_mm11()
     else:
         main()

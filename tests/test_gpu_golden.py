@@ -2,7 +2,9 @@
 T = 16384, 16 field terms + dB0, 50 FISTA iterations, db4 J = 3) on the GPU
 against the FP64 oracle's reconstruction stored in tests/golden/mm15_fista.npz
 (written by tests/golden/make_golden.py, which calls only the oracle), and
-the balanced-FISTA solve with the paper's regulariser against mm15_balanced.npz.
+the balanced-FISTA solve with the paper's regulariser against mm15_balanced.npz,
+and the 1.1 mm workload (200 x 200, T = 40000, 100 iterations, db4 J = 4)
+against mm11_fista.npz.
 Bars: NRMSE <= 1e-5 for the FP32 form, <= 1e-4 for the split forms with FP32
 anchors; L and lambda from the device rules within 1e-5."""
 import os
@@ -73,4 +75,36 @@ def test_full_size_balanced_matches_golden(mm15, prec):
     dl = abs(dev.lam.numpy()[0][0] - float(g["lam"][0])) / (0.5 * width)
     print(f"golden balanced {prec}: NRMSE {e:.2e}, device sigma/2 weight within {dl:.2f} bins", flush=True)
     assert dl <= 1.0 + 1e-6
+    assert e <= (1e-5 if prec == "fp32" else 1e-4)
+
+
+GOLDEN11 = os.path.join(os.path.dirname(__file__), "golden", "mm11_fista.npz")
+
+
+@pytest.fixture(scope="module")
+def mm11():
+    if not os.path.exists(GOLDEN11):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py mm11")
+    g = np.load(GOLDEN11)
+    w = synth.MM11
+    case = Case(w, sh=True)
+    op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
+    y = c64(op.A(case.x_noisy))
+    return w, case, y, g
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_full_size_1p1mm_fista_matches_golden(mm11, prec):
+    """The 1.1 mm configuration: FP32 against the FP16-split form with FP32
+    anchors, 100 iterations, final NRMSE against the FP64 oracle's solve."""
+    import paper_2211_07532_amd as ee
+    w, case, y, g = mm11
+    v0 = case.to_dev(c64(synth.power_start(w.npix, int(g["power_seed"]))))
+    res = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0,
+                   power_v0=v0, n_power=int(g["n_power"]), lam=-1.0, lambda_factor=1e-3)
+    e = solve.nrmse(res.x.cpu().numpy().reshape(-1), g["x_hat"])
+    print(f"golden 1.1 mm {prec}: NRMSE {e:.2e}  L {res.lipschitz:.6e} (ref {float(g['lipschitz']):.6e})  "
+          f"lambda {res.lam[0]:.6e} (ref {float(g['lam']):.6e})", flush=True)
+    assert abs(res.lipschitz - float(g["lipschitz"])) <= 1e-5 * float(g["lipschitz"])
+    assert abs(res.lam[0] - float(g["lam"])) <= 1e-5 * float(g["lam"])
     assert e <= (1e-5 if prec == "fp32" else 1e-4)
