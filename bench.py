@@ -225,6 +225,49 @@ def run_ls_vs_cs(forms, ee, torch, y, op, fista_rates):
     return {"ls_iters": n_ls, "cs_iters": n_cs, "forms": out}
 
 
+def run_mm11(forms, ee, torch, no_tune, retune):
+    """The 1.1 mm configuration (200 x 200, 32 coils, T = 40000, 3rd-order
+    field + dB0, 100 FISTA iterations, db4 J = 4): FISTA iter/s per form with
+    L and lambda given, and the whole solve (20 power steps, lambda rule,
+    100 iterations) against the FP64 oracle's solve (tests/golden/mm11_fista.npz)."""
+    from paper_2211_07532_amd import autotune
+    w = synth.MM11
+    dev = torch.device("cuda:0")
+    prob = synth.make_problem(w)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    op = ee.Operator(w.n, w.n, t(prob.smaps.astype(np.complex64)), t(prob.coef), t(prob.time), None, t(prob.dw0),
+                     sh_grid=(w.fov, w.fov, w.z0))
+    y = ee.forward(t(prob.x_noisy.astype(np.complex64)), op)
+    v0 = t(synth.power_start(w.npix, 7).astype(np.complex64))
+    gpath = os.path.join(ROOT, "tests", "golden", "mm11_fista.npz")
+    golden = np.load(gpath)["x_hat"].reshape(-1) if os.path.exists(gpath) else None
+    out = {}
+    for prec in forms:
+        if not no_tune:
+            for f in dict.fromkeys(("fp32", prec)):
+                autotune.tune(op, 1, f, use_cache=not retune)
+        res = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0,
+                       n_power=N_POWER)
+        nrmse = None
+        if golden is not None:
+            xr = res.x.cpu().numpy().reshape(-1).astype(np.complex128)
+            nrmse = float(np.linalg.norm(xr - golden) / np.linalg.norm(golden))
+        L, lam = res.lipschitz, res.lam[0]
+        ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam, sync_scalars=False)
+        torch.cuda.synchronize()
+        out[prec] = {"fista_iter_per_s": round(w.n_iter / (time.perf_counter() - t0), 2),
+                     "nrmse_vs_fp64": None if nrmse is None else float(f"{nrmse:.3e}")}
+    line = {"workload": w.name, "fista_iters": w.n_iter, "wavelet": f"{w.wavelet} J={w.levels}", "forms": out}
+    if "fp32" in out and len(out) > 1:
+        other = [p for p in out if p != "fp32"][0]
+        line["split_vs_fp32_fista_iter_ratio"] = round(out[other]["fista_iter_per_s"] /
+                                                       out["fp32"]["fista_iter_per_s"], 3)
+    return line
+
+
 def run_batch(args, prec, ee, torch):
     """The mixed-size batch (148 px / R=4, 170 px / R=5, 200 px / R=6 in turn,
     per-problem fields, dB0, coil maps and slice positions; 100 FISTA
@@ -432,6 +475,9 @@ def main():
     xh = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=head, lipschitz=0.0, power_v0=v0,
                   n_power=N_POWER).x
     line["coil_compression"] = [run_coil_compression(head, ee, torch, w, op, y, v0, xh, nv) for nv in (16, 20)]
+    print(f"[bench] 1.1 mm reconstruction (fp32, {head})", file=sys.stderr, flush=True)
+    line["mm11"] = run_mm11([p for p in dict.fromkeys(("fp32", head)) if p in out], ee, torch, args.no_tune,
+                            args.retune)
     print("[bench] wavelet prox at batch scale", file=sys.stderr, flush=True)
     line["prox"] = run_prox(ee, torch)
     if args.batch_nprob > 0:
