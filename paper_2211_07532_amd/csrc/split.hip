@@ -109,9 +109,8 @@ __device__ inline void phase_tile16(const double (&pv)[NT], const float (&pf)[NT
 __device__ inline int wave_slot() { return (int)((blockIdx.y * gridDim.x + blockIdx.x) * 4 + (threadIdx.x >> 6)); }
 
 // Writes a wave's forward partial sums; with wmax (scaled form) also the
-// wave's max |value| into its slot (a bound for the residual operand).  Per
-// wave, with no workgroup barrier: a barrier in the epilogue would hold every
-// workgroup until its slowest wave ends (measured +3 % kernel time).
+// wave's max |value| into its slot (a bound for the residual operand), per
+// wave and without a workgroup barrier.
 template <int GW>
 __device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0, int lane, f32x16 (&acc)[2][GW],
                                       float *wmax) {
