@@ -141,6 +141,9 @@ def test_split_operators_scale_invariant(prec, sh):
     e1f, e1a = errs[1.0]
     for s, (e_f, e_a) in errs.items():
         assert e_f <= 3 * e1f + 1e-6 and e_a <= 3 * e1a + 1e-6, s
+    # all-zero inputs (a zero magnitude bound: unscaled) give exact zeros
+    assert not ee.forward(case.to_dev(0 * x0), case.op, precision=prec).cpu().numpy().any()
+    assert not ee.adjoint(case.to_dev(0 * g0), case.op, precision=prec).cpu().numpy().any()
 
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
