@@ -234,7 +234,8 @@ typedef struct expenc_fista_opts {
   int32_t reserved;
   double lipschitz;        /* > 0: L to use; <= 0: estimate from power_v0            */
   double lambda;           /* >= 0: lambda to use; < 0: lambda_factor * max|A^H y|
-                              (A^H y in the solve's precision when batch == 1)       */
+                              (A^H y in FP32; it also gives the first iteration's
+                              gradient)                                              */
   double lambda_factor;    /* used when lambda < 0 (e.g. 1e-3)                       */
   const float *power_v0;   /* device [R] complex64 power-iteration start (lipschitz <= 0) */
   double *objective;       /* device [B][n_iter] float64 objective trace, or NULL    */

@@ -266,7 +266,9 @@ struct FistaLayout {
   int nxp = 0, nyp = 0;
   EncBuffers eb;
   float2 *z = nullptr, *v = nullptr, *w = nullptr, *x0 = nullptr, *x1 = nullptr;
-  float2 *zref = nullptr, *gref = nullptr;   // split forms: anchor z_ref and A^H(A z_ref - y)
+  // zref (split forms): the anchor z_ref; gref: A^H(A z_ref - y) (split
+  // forms), and the lambda rule's -A^H y, the gradient at z_0 = 0 (all forms)
+  float2 *zref = nullptr, *gref = nullptr;
   float2 *pvec = nullptr, *ptmp = nullptr;
   double *dpart = nullptr;   // [P * B * kRedBlocks]
   double *sc = nullptr;      // [2P + 2PB + 3P]
@@ -308,10 +310,8 @@ static int layout_fista(const expenc_op *op, int32_t nprob, int32_t batch, int32
   L->w = a.take<float2>(img);
   L->x0 = a.take<float2>(img);
   L->x1 = a.take<float2>(img);
-  if (precision != EXPENC_FP32) {
-    L->zref = a.take<float2>(img);
-    L->gref = a.take<float2>(img);
-  }
+  if (precision != EXPENC_FP32) L->zref = a.take<float2>(img);
+  L->gref = a.take<float2>(img);
   L->pvec = a.take<float2>((size_t)L->p.R * nprob);
   L->ptmp = a.take<float2>((size_t)L->p.R * nprob);
   L->dpart = a.take<double>((size_t)nprob * batch * kRedBlocks);
@@ -354,6 +354,7 @@ struct FistaGroup {
   const float2 *y = nullptr;      // [P][B][T][C]
   int refine = 0;
   std::vector<double> beta;
+  bool gref_at_zero = false;  // gref holds -A^H y (FP32) from the lambda rule
 
   int prologue(hipStream_t s) {
     const EncPlan &p = L.p, &pf = L.pf;
@@ -373,14 +374,17 @@ struct FistaGroup {
       k_fill_d<<<(unsigned)ceil_div(P * B, 256), 256, 0, s>>>(L.lam_of(0), P * B, opts->lambda);
       EX_LAUNCHED("fill");
     } else {
-      // A^H y in the solve's precision at one image per problem (as the power
-      // iteration), else in FP32
-      const EncPlan &pl = B == 1 ? p : pf;
-      EX_TRY(enc_pack_y(pl, y, L.eb, s));
-      EX_TRY(enc_adjoint_partials(pl, L.eb, s));
-      EX_TRY(enc_adjoint_reduce_out(pl, L.eb, op->smaps, L.v, pl.R, pl.nx, nullptr, nullptr, s, nullptr,
-                                    (int64_t)B * pl.R));
-      EX_TRY(reduce_maxabs(L.v, pf.R, pf.R, P * B, opts->lambda_factor, L.dpart, L.lam_of(0), s));
+      // -A^H y in FP32 on the wavelet grid (zero padding): lambda =
+      // factor * max|A^H y|, and the first iteration's gradient at z_0 = 0
+      // (2/L times it), so that iteration needs no contraction of its own
+      k_zero_f2<<<(unsigned)ceil_div(img * P * B, 256), 256, 0, s>>>(L.gref, img * P * B);
+      EX_LAUNCHED("zero");
+      EX_TRY(enc_pack_y(pf, y, L.eb, s, -1.f));
+      EX_TRY(enc_adjoint_partials(pf, L.eb, s));
+      EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.gref, img, L.nxp, nullptr, nullptr, s, nullptr,
+                                    img * B));
+      EX_TRY(reduce_maxabs(L.gref, img, img, P * B, opts->lambda_factor, L.dpart, L.lam_of(0), s));
+      gref_at_zero = true;
     }
     k_fista_scalars<<<(unsigned)ceil_div(P * B, 256), 256, 0, s>>>(L.sc, P, B);
     EX_LAUNCHED("scalars");
@@ -421,7 +425,13 @@ struct FistaGroup {
         return enc_forward_residual(q, L.eb, y, cs);
       };
       const int pnx = padded ? nxp : 0, pny = padded ? nyp : 0;
-      if (!split) {
+      if (k == 0 && gref_at_zero) {
+        // v = z_0 - (2/L) A^H y from the prologue's FP32 -A^H y (also the
+        // split forms' first anchor: z_ref = z_0)
+        k_grad_step<<<(unsigned)ceil_div(all, 256), 256, 0, cs>>>(L.v, L.z, L.gref, alpha, nxp, nyp, p.nx, p.ny, all, B);
+        EX_LAUNCHED("gradient step");
+        if (split) EX_TRY(copy_f2(L.z, L.zref, all, cs));
+      } else if (!split) {
         // v = z - (2/L) A^H (A z - y)
         EX_TRY(residual_fp32(p));
         EX_TRY(enc_adjoint_partials(p, L.eb, cs));
