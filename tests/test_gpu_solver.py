@@ -158,6 +158,31 @@ def test_fista_with_device_power_iteration():
     assert np.array_equal(res.x.cpu().numpy().view(np.uint32), res2.x.cpu().numpy().view(np.uint32))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_fista_graph_replay_with_new_data(prec):
+    """A second solve on the same device buffers replays the cached graph;
+    the data are read at replay time and the lambda rule (with its FP32
+    A^H y, also the first gradient) is recomputed, so new contents of y give
+    the new solution, bit for bit the same as a solve from a fresh buffer."""
+    import torch
+    ee = _ee()
+    w = synth.TINY
+    case = Case(w, sh=True)
+    op = _oracle_op(case)
+    y1 = c64(op.A(case.x_noisy))
+    y2 = c64(op.A(case.x_true))
+    L = solve.power_lipschitz(op, c64(synth.power_start(w.npix, 5)), 30)
+    yt = case.to_dev(y1)
+    kw = dict(precision=prec, lipschitz=L, lam=-1.0, lambda_factor=1e-3)
+    ee.fista(yt, case.op, w.n_iter, w.levels, w.wavelet, **kw)
+    yt.copy_(torch.from_numpy(y2.astype(np.complex64)).to(yt.device))
+    res = ee.fista(yt, case.op, w.n_iter, w.levels, w.wavelet, **kw)
+    ref = solve.fista(op, y2, L, solve.lambda_rule(op, y2), w.n_iter, w.levels, w.wavelet, w.n_pad)
+    assert solve.nrmse(res.x.cpu().numpy().reshape(-1), ref) <= (1e-5 if prec == "fp32" else 1e-4)
+    fresh = ee.fista(case.to_dev(y2), case.op, w.n_iter, w.levels, w.wavelet, **kw)
+    assert np.array_equal(res.x.cpu().numpy().view(np.uint32), fresh.x.cpu().numpy().view(np.uint32))
+
+
 def test_ista_objective_monotone_and_matches_oracle():
     ee = _ee()
     w = synth.TINY
