@@ -76,6 +76,30 @@ def test_mixed_batch_matches_oracle_and_single_solves(prec):
         assert e <= bar
 
 
+def test_batched_fp16_scales_per_problem():
+    """The fp16 form's operand scales are per problem: the problems of one
+    launch (two per size class here) get data scaled by very different powers
+    of two, and each solution must be its unscaled single solve times that
+    factor (the scaling is exact, so to within rounding)."""
+    ee = _ee()
+    ws = _mixed_workloads(n_per=2, n_iter=8)
+    cases = [Case(w, sh=True) for w in ws]
+    ops = [_oracle_op(c) for c in cases]
+    ys = [c64(o.A(c.x_noisy)) for o, c in zip(ops, cases)]
+    factors = [2.0 ** e for e in (-20, 10, 0, -5, 15, -10)]
+    v0 = c64(synth.power_start(max(w.npix for w in ws), 13))
+    kw = dict(precision="fp16", lipschitz=0.0, power_v0=cases[0].to_dev(v0), n_power=20, lam=-1.0,
+              lambda_factor=1e-3)
+    xs = ee.fista_batched([c.to_dev(y * f) for c, y, f in zip(cases, ys, factors)], [c.op for c in cases],
+                          ws[0].n_iter, ws[0].levels, "db4", **kw)
+    for k, (c, y, f) in enumerate(zip(cases, ys, factors)):
+        single = ee.fista(c.to_dev(y), c.op, ws[k].n_iter, ws[k].levels, "db4",
+                          **dict(kw, power_v0=c.to_dev(v0[:ws[k].npix])))
+        e = rel(xs[k].cpu().numpy() / f, single.x.cpu().numpy())
+        print(f"  problem {k} (n={ws[k].n}, data x{f:g}): batched / factor vs single unscaled {e:.2e}", flush=True)
+        assert e <= 1e-6
+
+
 def test_batched_fixed_scalars_and_repeat_is_bitwise():
     ee = _ee()
     ws = _mixed_workloads(n_per=1, n_iter=6)
