@@ -117,3 +117,36 @@ def test_invalid_arguments_raise():
     bad = torch.zeros(5, dtype=torch.complex64, device="cuda")
     with pytest.raises((ValueError, RuntimeError)):
         ee.forward(bad, case.op)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1, 1, 1), (1, 7, 17, 3, 4, 2), (5, 3, 300, 2, 0, 1),
+                                   (17, 2, 5, 17, 2, 1)],
+                         ids=["1x1-T1-C1", "1x7-T17-C3-B2", "5x3-nofield", "17x2-T5-C17"])
+def test_degenerate_shapes(shape, prec):
+    """Degenerate geometries against the oracle: a single pixel and sample,
+    a one-column image, no field terms, more coils than samples (basis given
+    as maps, so any nx x ny)."""
+    import torch
+    ee = _ee()
+    nx, ny, T, C, L, B = shape
+    R = nx * ny
+    rng = np.random.default_rng(7 + nx + 10 * ny + T)
+    smaps = c64(synth.random_complex((C, R), 41 + C))
+    coef = rng.normal(0.0, 2.0, (T, L))
+    basis = rng.uniform(-1.0, 1.0, (L, R))
+    time = np.arange(T, dtype=np.float64) * 2e-6
+    dw0 = rng.uniform(-600.0, 600.0, R)
+    x = c64(synth.random_complex((B, R), 43))
+    dev = torch.device("cuda")
+    op = ee.Operator(nx, ny, torch.from_numpy(smaps.astype(np.complex64)).to(dev), torch.from_numpy(coef).to(dev),
+                     torch.from_numpy(time).to(dev), torch.from_numpy(basis).to(dev), torch.from_numpy(dw0).to(dev))
+    print(f"[case] degenerate {nx}x{ny} T={T} C={C} L={L} B={B} {prec}", flush=True)
+    bar = TOL if prec == "fp32" else 1e-3
+    y_ref = encoding.forward(x, smaps, coef, time, basis, dw0)
+    y = ee.forward(torch.from_numpy(x.astype(np.complex64)).to(dev), op, precision=prec).cpu().numpy()
+    assert y.shape == y_ref.shape and rel(y, y_ref) <= bar
+    g = c64(synth.random_complex(y_ref.shape, 44))
+    xa = ee.adjoint(torch.from_numpy(g.astype(np.complex64)).to(dev), op, precision=prec).cpu().numpy()
+    x_ref = encoding.adjoint(g, smaps, coef, time, basis, dw0)
+    assert xa.shape == x_ref.shape and rel(xa, x_ref) <= bar
