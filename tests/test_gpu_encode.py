@@ -150,3 +150,38 @@ def test_degenerate_shapes(shape, prec):
     xa = ee.adjoint(torch.from_numpy(g.astype(np.complex64)).to(dev), op, precision=prec).cpu().numpy()
     x_ref = encoding.adjoint(g, smaps, coef, time, basis, dw0)
     assert xa.shape == x_ref.shape and rel(xa, x_ref) <= bar
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+@pytest.mark.parametrize("shape", [(1, 1, 1, 1, 1), (3, 17, 40, 2, 1), (17, 3, 33, 5, 2), (33, 20, 100, 4, 1)],
+                         ids=["1x1-T1", "3x17", "17x3-B2", "33x20"])
+def test_degenerate_shapes_sh(shape, prec):
+    """The solid-harmonic kind (the library evaluates the basis from the grid
+    geometry and, in the split forms, runs the polynomial kernels) on
+    degenerate and non-square grids with rectangular fields of view, 16 terms
+    and dB0, against the oracle's basis on the same geometry."""
+    import torch
+    ee = _ee()
+    nx, ny, T, C, B = shape
+    fx, fy, z0, L = 0.1, 0.07, 0.003, 16
+    R = nx * ny
+    rng = np.random.default_rng(100 + nx + 10 * ny + T)
+    basis = encoding.sh_basis(nx, fx, z0, L, ny=ny, fov_y=fy)
+    scale = 3.0 / np.maximum(np.abs(basis).max(axis=1), 1e-12)   # a few radians per term at most
+    coef = rng.normal(0.0, 1.0, (T, L)) * scale[None, :]
+    time = np.arange(T, dtype=np.float64) * 2e-6
+    dw0 = rng.uniform(-600.0, 600.0, R)
+    smaps = c64(synth.random_complex((C, R), 51 + C))
+    x = c64(synth.random_complex((B, R), 52))
+    dev = torch.device("cuda")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)  # noqa: E731
+    op = ee.Operator(nx, ny, t(smaps.astype(np.complex64)), t(coef), t(time), None, t(dw0), sh_grid=(fx, fy, z0))
+    print(f"[case] degenerate sh {nx}x{ny} T={T} C={C} B={B} {prec}", flush=True)
+    bar = TOL if prec == "fp32" else 1e-3
+    y_ref = encoding.forward(x, smaps, coef, time, basis, dw0)
+    y = ee.forward(t(x.astype(np.complex64)), op, precision=prec).cpu().numpy()
+    assert y.shape == y_ref.shape and rel(y, y_ref) <= bar
+    g = c64(synth.random_complex(y_ref.shape, 53))
+    xa = ee.adjoint(t(g.astype(np.complex64)), op, precision=prec).cpu().numpy()
+    x_ref = encoding.adjoint(g, smaps, coef, time, basis, dw0)
+    assert xa.shape == x_ref.shape and rel(xa, x_ref) <= bar
