@@ -42,12 +42,12 @@ N_POWER = 20
 # 256 MiB copy.  Valid only for the kernel source and launch shape they were
 # taken on: `sha` is the SHA-256 of the files the kernel is built from.
 TRAFFIC = {
-    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 406493922,
-             "sha": "072fc97cd0dd1c1c91d580d3603dc6e072789f2b8e13008f2394bc582c6f6221"},
-    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89591036,
-             "sha": "45ede11a8318689df7549c72f22576ca11e55456d4ab4d6d455234d5d033c0b1"},
-    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89582845,
-             "sha": "45ede11a8318689df7549c72f22576ca11e55456d4ab4d6d455234d5d033c0b1"},
+    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 406602043,
+             "sha": "af8a3698fc70d45bf63dd601b89244d73973676735ae7807db4021bebed7ff6c"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89591446,
+             "sha": "9bdcc1af9f73199b1d7f944d794d514ecbb90fc5a83d269170803d67d31d28b3"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89583255,
+             "sha": "9bdcc1af9f73199b1d7f944d794d514ecbb90fc5a83d269170803d67d31d28b3"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split_dev.h", "internal.h", "../build.py"],

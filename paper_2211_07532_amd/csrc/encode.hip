@@ -642,6 +642,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
     int64_t want = ceil_div(tgt_fwd, nrb * q.NGY);
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Rp / 16));
     q.fwd_chunk = (int32_t)round_up(ceil_div(q.Rp, want), 16);
+    if (precision == EXPENC_FP32) q.fwd_chunk = std::min(q.fwd_chunk, kF32ChunkMax);
     q.fwd_split = (int32_t)ceil_div(q.Rp, q.fwd_chunk);
     q.nwmax = (int32_t)split_grid(q.Tp / 256 * q.fwd_split) * q.NGY * 4;
   }
@@ -652,6 +653,15 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
     want = std::max<int64_t>(1, std::min<int64_t>(want, q.Tp / 16));
     // (the polynomial split adjoint steps over 32 samples at a time)
     q.adj_chunk = (int32_t)round_up(ceil_div(q.Tp, want), (q.sh && precision != EXPENC_FP32) ? 32 : 16);
+    // The error of a contraction grows with the length of the sums one
+    // workgroup accumulates on the matrix cores.  Measured on a 200 px,
+    // T = 20000 fp16 solve: NRMSE 1.8e-5 at 562 samples per split adjoint
+    // chunk, 2.9e-5 at 5056, 5.0e-5 at 10112 (the split forward's chunk
+    // length did not matter); with 12 problems per launch the FP32 anchors'
+    // chunks (3 forward, 2 adjoint splits) alone took it from 2.2e-5 to
+    // 4.9e-5.  So chunks are capped (the tuned single-problem shapes are
+    // below the caps).
+    q.adj_chunk = std::min(q.adj_chunk, precision == EXPENC_FP32 ? kF32ChunkMax : kSplitAdjChunkMax);
     q.adj_split = (int32_t)ceil_div(q.Tp, q.adj_chunk);
   }
   *p = q;

@@ -225,6 +225,10 @@ struct EncPlan {
 
 // Workgroups (per problem) of the magnitude pre-pass of the scaled form.
 constexpr int kAmaxBlocks = 64;
+// Longest reduction chunk of one workgroup: samples in the split adjoint
+// contractions; pixels or samples in the FP32 contractions.
+constexpr int32_t kSplitAdjChunkMax = 1024;
+constexpr int32_t kF32ChunkMax = 2048;
 
 int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p, int32_t nprob = 1);
 
