@@ -398,7 +398,11 @@ int expenc_coil_compress(int32_t ncoils, int32_t nvirtual, int64_t nsamples, con
  * targets for every later plan of op's geometry (nx, ny, ncoils, nbasis,
  * nsamples, basis_kind) at this batch and precision; 0 restores the default
  * for that direction, both 0 remove the entry.  A batched solve of P such
- * problems uses the same totals across its P problems.  Later calls plan
+ * problems uses the same totals across its P problems.  Whatever the target,
+ * one workgroup's reduction chunk is capped (1024 samples in the split
+ * adjoints, 2048 pixels or samples in the FP32 contractions): the error of a
+ * long sum on the matrix cores grows with its length, so a launch may have
+ * more workgroups than its target.  Later calls plan
  * with the new targets (workspace sizes may change: query them again).
  * Process-wide and thread-safe; changing it while a call is being issued on
  * another thread leaves that call on either setting.
