@@ -42,12 +42,12 @@ N_POWER = 20
 # 256 MiB copy.  Valid only for the kernel source and launch shape they were
 # taken on: `sha` is the SHA-256 of the files the kernel is built from.
 TRAFFIC = {
-    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 406602043,
-             "sha": "af8a3698fc70d45bf63dd601b89244d73973676735ae7807db4021bebed7ff6c"},
-    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89591446,
-             "sha": "9bdcc1af9f73199b1d7f944d794d514ecbb90fc5a83d269170803d67d31d28b3"},
-    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89583255,
-             "sha": "9bdcc1af9f73199b1d7f944d794d514ecbb90fc5a83d269170803d67d31d28b3"},
+    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 406555149,
+             "sha": "fe71e959be039acb51007d73d4435f9a4807ac211b33e3545f44f9cd54bc3760"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89591036,
+             "sha": "8cde22e9aa231bc5ad02759c51c0115c93d4a9b09f1c4490342b1bb2497c6283"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89583460,
+             "sha": "8cde22e9aa231bc5ad02759c51c0115c93d4a9b09f1c4490342b1bb2497c6283"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split_dev.h", "internal.h", "../build.py"],

@@ -228,7 +228,7 @@ typedef struct expenc_fista_opts {
   int32_t levels;          /* J >= 1                                                 */
   int32_t nx_pad, ny_pad;  /* wavelet grid (>= nx, ny, multiples of 2^J); 0 = round up */
   int32_t ista;            /* 1: momentum off (t_k = 1), monotone ISTA               */
-  int32_t refine_every;    /* split forms: exact FP32 gradient every m iterations (0 = 50 fp16, 25 bf16) */
+  int32_t refine_every;    /* split forms: exact FP32 gradient every m iterations (0 = 25 fp16, 17 bf16) */
   int32_t n_power;         /* power steps when lipschitz <= 0 (in the solve's
                               precision when batch == 1, else FP32)                  */
   int32_t reserved;
@@ -324,7 +324,7 @@ typedef struct expenc_balanced_opts {
   int32_t precision;     /* EXPENC_FP32 / EXPENC_BF16_SPLIT / EXPENC_FP16_SPLIT    */
   int32_t wavelet;       /* EXPENC_HAAR / EXPENC_DB4                               */
   int32_t levels;        /* J in [1, 8] (the paper: 1)                             */
-  int32_t refine_every;  /* split forms: FP32 anchor cadence (0 = 50 fp16, 25 bf16) */
+  int32_t refine_every;  /* split forms: FP32 anchor cadence (0 = 25 fp16, 17 bf16) */
   int32_t n_power;       /* power steps when lipschitz <= 0 (solve's precision at
                             batch 1, else FP32)                                      */
   int32_t ista;          /* 1: momentum off                                        */
