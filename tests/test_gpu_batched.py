@@ -165,7 +165,7 @@ def test_full_size_problem_inside_batch_matches_golden(prec):
     torch.cuda.synchronize()
     e = solve.nrmse(xs[0].cpu().numpy().reshape(-1), g["x_hat"])
     print(f"  golden NRMSE {e:.2e}", flush=True)
-    assert e <= (1e-5 if prec == "fp32" else 1e-4)
+    assert e <= 1e-5
     for p, yp, x in zip(partners, yps, xs[1:]):
         single = ee.fista(yp, p.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0,
                           power_v0=main.to_dev(v0[:p.w.npix]), n_power=int(g["n_power"]), lam=-1.0,

@@ -5,8 +5,8 @@ against the FP64 oracle's reconstruction stored in tests/golden/mm15_fista.npz
 the balanced-FISTA solve with the paper's regulariser against mm15_balanced.npz,
 and the 1.1 mm workload (200 x 200, T = 40000, 100 iterations, db4 J = 4)
 against mm11_fista.npz.
-Bars: NRMSE <= 1e-5 for the FP32 form, <= 1e-4 for the split forms with FP32
-anchors; L and lambda from the device rules within 1e-5."""
+Bars: NRMSE <= 1e-5 in every form (the split forms with their default FP32
+anchor cadences); L and lambda from the device rules within 1e-5."""
 import os
 
 import numpy as np
@@ -44,7 +44,7 @@ def test_full_size_fista_matches_golden(mm15, prec):
           f"lambda {res.lam[0]:.6e} (ref {float(g['lam']):.6e})", flush=True)
     assert abs(res.lipschitz - float(g["lipschitz"])) <= 1e-5 * float(g["lipschitz"])
     assert abs(res.lam[0] - float(g["lam"])) <= 1e-5 * float(g["lam"])
-    assert e <= (1e-5 if prec == "fp32" else 1e-4)
+    assert e <= 1e-5
 
 
 BALANCED = os.path.join(os.path.dirname(__file__), "golden", "mm15_balanced.npz")
@@ -75,7 +75,7 @@ def test_full_size_balanced_matches_golden(mm15, prec):
     dl = abs(dev.lam.numpy()[0][0] - float(g["lam"][0])) / (0.5 * width)
     print(f"golden balanced {prec}: NRMSE {e:.2e}, device sigma/2 weight within {dl:.2f} bins", flush=True)
     assert dl <= 1.0 + 1e-6
-    assert e <= (1e-5 if prec == "fp32" else 1e-4)
+    assert e <= 1e-5
 
 
 GOLDEN11 = os.path.join(os.path.dirname(__file__), "golden", "mm11_fista.npz")
@@ -107,4 +107,4 @@ def test_full_size_1p1mm_fista_matches_golden(mm11, prec):
           f"lambda {res.lam[0]:.6e} (ref {float(g['lam']):.6e})", flush=True)
     assert abs(res.lipschitz - float(g["lipschitz"])) <= 1e-5 * float(g["lipschitz"])
     assert abs(res.lam[0] - float(g["lam"])) <= 1e-5 * float(g["lam"])
-    assert e <= (1e-5 if prec == "fp32" else 1e-4)
+    assert e <= 1e-5
