@@ -231,6 +231,21 @@ def test_cg_matches_oracle():
 
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
+def test_cg_split_forty_coils_matches_oracle(prec, sh):
+    """Forty coils (three 16-column groups, two workgroup rows per launch):
+    the split residual operand's magnitude bound then spans both rows of the
+    forward launch.  Three CG iterations against the oracle."""
+    ee = _ee()
+    w = synth.Workload("c40", 20, 0.2, 40, 700, 2e-6, 2.0, 9, 80.0, 20.0, 5, "haar", 1, 23)
+    case = Case(w, sh=sh)
+    op = _oracle_op(case)
+    y = c64(op.A(case.x_noisy))
+    x = ee.cg(case.to_dev(y), case.op, 3, precision=prec).cpu().numpy()
+    assert solve.nrmse(x, solve.cg_ls(op, y, 3)) <= 2e-4
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp16"])
+@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 def test_cg_split_matches_oracle(prec, sh):
     """CG in the split forms (no FP32 anchors).  Their operator error (about
     4e-6 bf16, 1e-6 fp16 relative) is amplified by CG like any rounding (see
