@@ -78,9 +78,9 @@ def parse():
     ap.add_argument("--precision", default="all", choices=["all", "fp32", "bf16", "fp16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=10)
-    ap.add_argument("--batch-nprob", type=int, default=36,
+    ap.add_argument("--batch-nprob", type=int, default=180,
                     help="problems of the mixed-size batch measured beside the headline (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--batch-steps", type=int, default=1)
     ap.add_argument("--no-tune", action="store_true", help="use the built-in launch shapes")
     ap.add_argument("--retune", action="store_true", help="time the launch shapes instead of using cached ones")
     return ap.parse_args()

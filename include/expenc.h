@@ -50,7 +50,8 @@ enum {
   EXPENC_EWORKSPACE = -2,    /* workspace missing or smaller than required       */
   EXPENC_EHIP = -3,          /* a HIP runtime call or kernel launch failed       */
   EXPENC_EUNSUPPORTED = -4,  /* valid but unsupported combination                */
-  EXPENC_ENONFINITE = -5     /* a solve produced NaN/Inf (reported after sync)   */
+  EXPENC_ENONFINITE = -5,    /* a solve produced NaN/Inf (expenc_solve_status)   */
+  EXPENC_EDIVERGED = -6      /* a solve's objective diverged (expenc_solve_status) */
 };
 
 /* Arithmetic form of the encoding contraction.  The fp16 form multiplies
@@ -427,6 +428,27 @@ int expenc_plan_info(const expenc_op *op, int32_t batch, int32_t precision, int3
  * out[2] = total adjoint-contraction ms, out[3] = adjoint launches (host array).
  */
 int expenc_kernel_timing(int32_t mode, double *out);
+
+/*
+ * Outcome of the last call that used the workspace ws (the iterations of
+ * eq. 1 by FISTA or CG, Methods 2.1; also the coil calls).  The solvers
+ * (fista_solve, fista_solve_batched, fista_balanced_solve, cg_solve) and the
+ * coil calls (expenc_prewhiten, expenc_coil_compress) keep a status word in
+ * the first 256 bytes of their workspace: it is cleared at the start of each
+ * call and set on the device when
+ *   - an iterate x_k of a solve (any problem of a batched call), the
+ *     Cholesky factor of expenc_prewhiten (a noise covariance that is not
+ *     positive definite) or an eigenvalue of expenc_coil_compress holds NaN
+ *     or Inf -> EXPENC_ENONFINITE;
+ *   - with an objective trace requested (fista_solve), F(x_k) of eq. 1 rises
+ *     above F(0) = ||y||^2, the value at the zero start image, at any
+ *     iteration (e.g. an underestimated Lipschitz constant) -> EXPENC_EDIVERGED.
+ * Non-finite takes precedence.  This call waits for `stream` (the stream of
+ * the call that used ws) and returns EXPENC_OK, EXPENC_ENONFINITE or
+ * EXPENC_EDIVERGED (with a message in expenc_last_error), or EXPENC_EINVAL /
+ * EXPENC_EHIP.  ws is the caller's device workspace of that call.
+ */
+int expenc_solve_status(const void *ws, void *stream);
 
 /* Thread-local text of the last non-OK status of this thread. */
 const char *expenc_last_error(void);

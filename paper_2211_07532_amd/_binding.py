@@ -17,6 +17,7 @@ EXPENC_EWORKSPACE = -2
 EXPENC_EHIP = -3
 EXPENC_EUNSUPPORTED = -4
 EXPENC_ENONFINITE = -5
+EXPENC_EDIVERGED = -6
 
 FP32, BF16_SPLIT, FP16_SPLIT = 0, 1, 2
 HAAR, DB4 = 0, 1
@@ -107,6 +108,7 @@ SIGNATURES = {
     "expenc_plan_info": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int,
                                         ctypes.POINTER(ctypes.c_int64)]),
     "expenc_kernel_timing": (ctypes.c_int, [_c_int, ctypes.POINTER(ctypes.c_double)]),
+    "expenc_solve_status": (ctypes.c_int, [_vp, _vp]),
     "expenc_last_error": (ctypes.c_char_p, []),
 }
 

@@ -175,7 +175,7 @@ __global__ void k_copy_f2(const float2 *__restrict__ in, float2 *__restrict__ ou
 
 // L[p] = 2 * num[p]/den[p] for each problem
 __global__ void k_lipschitz_final(const double *__restrict__ num, const double *__restrict__ den, double *out, int P) {
-  const int p = threadIdx.x;
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p < P) out[p] = den[p] > 0.0 ? 2.0 * num[p] / den[p] : 0.0;
 }
 
@@ -240,7 +240,7 @@ int lipschitz_run(const EncPlan &p1, const expenc_op *op, const EncBuffers &eb, 
     EX_TRY(reduce_dot(vec, tmp, R, R, P, 1.0, dpart, dsc + P, s));
   }
   EX_TRY(reduce_dot(vec, vec, R, R, P, 1.0, dpart, dsc + 2 * P, s));
-  k_lipschitz_final<<<1, 256, 0, s>>>(dsc + P, dsc + 2 * P, L_out, P);
+  k_lipschitz_final<<<(unsigned)ceil_div(P, 256), 256, 0, s>>>(dsc + P, dsc + 2 * P, L_out, P);
   EX_LAUNCHED("lipschitz final");
   return EXPENC_OK;
 }
@@ -342,6 +342,18 @@ extern "C" int expenc_lipschitz(const expenc_op *op, int32_t precision, int32_t 
 }
 
 extern "C" int expenc_kernel_timing(int32_t mode, double *out) { return kernel_timing(mode, out); }
+
+extern "C" int expenc_solve_status(const void *ws, void *stream) {
+  if (!ws) return fail(EXPENC_EINVAL, "workspace is NULL");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned flags = 0u;
+  EX_HIP(hipMemcpyAsync(&flags, ws, sizeof(flags), hipMemcpyDeviceToHost, s));
+  EX_HIP(hipStreamSynchronize(s));
+  if (flags & kStatusNonFinite) return fail(EXPENC_ENONFINITE, "the call produced NaN or Inf values");
+  if (flags & kStatusDiverged)
+    return fail(EXPENC_EDIVERGED, "the objective rose above its value at the zero image (step 1/L too large?)");
+  return EXPENC_OK;
+}
 
 extern "C" int expenc_set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target,
                                  int32_t adj_target) {

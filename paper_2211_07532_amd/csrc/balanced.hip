@@ -223,7 +223,7 @@ __global__ void k_bal_combine(const float2 *__restrict__ r, const float2 *__rest
 __global__ void k_bal_update(float2 *__restrict__ beta, const float2 *__restrict__ gw,
                              const float2 *__restrict__ alpha_prev, float2 *__restrict__ alpha,
                              const double *__restrict__ sc, const double *__restrict__ tau, int nb, int64_t N,
-                             int64_t total, double m) {
+                             int64_t total, double m, unsigned *status) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const int64_t bb = i / N;  // (image, band)
@@ -240,6 +240,7 @@ __global__ void k_bal_update(float2 *__restrict__ beta, const float2 *__restrict
   }
   const float2 na = make_float2((float)ax, (float)ay);
   alpha[i] = na;
+  flag_nonfinite(status, na);
   const float2 ap = alpha_prev[i];
   beta[i] = make_float2((float)(na.x + m * ((double)na.x - ap.x)), (float)(na.y + m * ((double)na.y - ap.y)));
 }
@@ -328,6 +329,7 @@ struct BalLayout {
   float2 *pvec = nullptr, *ptmp = nullptr;
   double *dpart = nullptr, *sc = nullptr;  // sc: L_A, kappa, L, pad, lam[B nb], tau[B nb], mean[B J], 3 scratch
   unsigned *counts = nullptr;
+  unsigned *status = nullptr;  // the call's status word (start of the workspace)
   double *lam() const { return sc + 4; }
   double *tau() const { return sc + 4 + B * nb; }
   double *mean() const { return sc + 4 + 2 * B * nb; }
@@ -337,6 +339,7 @@ struct BalLayout {
 int layout_bal(const expenc_op *op, int32_t batch, const expenc_balanced_opts *o, Arena &a, BalLayout *L) {
   if (!o) return fail(EXPENC_EINVAL, "options are NULL");
   if (o->levels < 1 || o->levels > 8) return fail(EXPENC_EINVAL, "levels must be in [1, 8]");
+  L->status = take_status(a);
   EX_TRY(make_plan(op, batch, o->precision, &L->p));
   EX_TRY(make_plan(op, batch, EXPENC_FP32, &L->pf));
   // power iteration in the solve's precision when there is one image (p1 and
@@ -466,6 +469,7 @@ extern "C" int fista_balanced_solve(const expenc_op *op, int32_t batch, const fl
   const float2 *y2 = reinterpret_cast<const float2 *>(y);
   const bool split = opts->precision != EXPENC_FP32;
   // prologue: tables, L_A, kappa, L, weights, thresholds, zero state
+  EX_TRY(clear_status(L.status, s));
   EX_TRY(enc_prepare(pf, op, L.eb, s));
   if (split) EX_TRY(enc_prepare(p, op, L.eb, s));
   if (opts->lipschitz > 0) {
@@ -537,7 +541,7 @@ extern "C" int fista_balanced_solve(const expenc_op *op, int32_t batch, const fl
       EX_LAUNCHED("combine");
       EX_TRY(swt_forward(f, op->nx, op->ny, J, B, L.c, L.gw, L.tmp, cs));
       k_bal_update<<<(unsigned)ceil_div(coef, 256), 256, 0, cs>>>(L.beta, L.gw, aprev, anew, L.sc, L.tau(), nb, N,
-                                                                   coef, mom[k]);
+                                                                   coef, mom[k], L.status);
       EX_LAUNCHED("balanced update");
     }
     return EXPENC_OK;

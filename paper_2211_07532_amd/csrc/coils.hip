@@ -61,7 +61,8 @@ __global__ void k_gram_sum(const double2 *__restrict__ part, int nblk, int C, do
 // Eigen-decomposition of the Hermitian C x C matrix g: eigenvalues
 // descending to w, eigenvectors as the columns of v ([C][C] row-major).
 __global__ __launch_bounds__(256) void k_jacobi(const double2 *__restrict__ g, int C, int max_sweeps,
-                                                double2 *__restrict__ v_out, double *__restrict__ w_out) {
+                                                double2 *__restrict__ v_out, double *__restrict__ w_out,
+                                                unsigned *status) {
   extern __shared__ double2 sh[];
   double2 *A = sh;          // [C][C]
   double2 *V = sh + C * C;  // [C][C]
@@ -178,8 +179,12 @@ __global__ __launch_bounds__(256) void k_jacobi(const double2 *__restrict__ g, i
       __syncthreads();
     }
   }
-  // eigenvalues descending (ties keep index order)
+  // eigenvalues descending (ties keep index order); status: any non-finite
   if (tid == 0) {
+    unsigned bad = 0u;
+    for (int i = 0; i < C; ++i)
+      if (!isfinite(A[i * C + i].x)) bad = kStatusNonFinite;
+    status[0] = bad;
     for (int i = 0; i < C; ++i) perm[i] = i;
     for (int i = 0; i < C; ++i) {
       int best = i;
@@ -234,10 +239,15 @@ __global__ void k_compress_s(const float2 *__restrict__ s, int R, int C, const d
 }
 
 // L (lower, [C][C]) with L L^H = psi; NaN when psi is not positive definite
-__global__ __launch_bounds__(256) void k_cholesky(const double2 *__restrict__ psi, int C, double2 *__restrict__ L) {
+// status[0] = kStatusNonFinite when a pivot is not positive (psi not
+// positive definite) or not finite, else 0.
+__global__ __launch_bounds__(256) void k_cholesky(const double2 *__restrict__ psi, int C, double2 *__restrict__ L,
+                                                  unsigned *status) {
   extern __shared__ double2 a[];  // [C][C]
   __shared__ double diag;
+  __shared__ int bad;
   const int tid = threadIdx.x;
+  if (tid == 0) bad = 0;
   for (int i = tid; i < C * C; i += blockDim.x) a[i] = psi[i];
   __syncthreads();
   for (int j = 0; j < C; ++j) {
@@ -245,6 +255,7 @@ __global__ __launch_bounds__(256) void k_cholesky(const double2 *__restrict__ ps
       double d = a[j * C + j].x;
       for (int k = 0; k < j; ++k) d -= a[j * C + k].x * a[j * C + k].x + a[j * C + k].y * a[j * C + k].y;
       diag = sqrt(d);  // NaN for a non-positive pivot
+      if (!(d > 0.0) || !isfinite(d)) bad = 1;
       a[j * C + j] = make_double2(diag, 0.0);
     }
     __syncthreads();
@@ -260,6 +271,7 @@ __global__ __launch_bounds__(256) void k_cholesky(const double2 *__restrict__ ps
     __syncthreads();
   }
   for (int i = tid; i < C * C; i += blockDim.x) L[i] = (i % C <= i / C) ? a[i] : make_double2(0.0, 0.0);
+  if (tid == 0) status[0] = bad ? kStatusNonFinite : 0u;
 }
 
 // v <- L^{-1} v for n coil vectors v_k[c] = x[k * vstride + c * cstride]
@@ -286,6 +298,7 @@ __global__ __launch_bounds__(256) void k_whiten(const double2 *__restrict__ Lg, 
 }
 
 struct CoilLayout {
+  unsigned *status = nullptr;  // the call's status word (start of the workspace)
   double2 *part = nullptr, *g = nullptr, *v = nullptr, *L = nullptr;
   int nblk = 0;
 };
@@ -293,6 +306,7 @@ struct CoilLayout {
 int layout_coils(int32_t C, int64_t T, Arena &a, CoilLayout *cl) {
   if (C < 1 || C > kMaxCoils) return fail(EXPENC_EINVAL, "ncoils must be in [1, %d] (got %d)", kMaxCoils, C);
   if (T < 0) return fail(EXPENC_EINVAL, "nsamples must be >= 0");
+  cl->status = take_status(a);
   cl->nblk = (int)std::max<int64_t>(1, ceil_div(T, kGramChunk));
   cl->part = a.take<double2>((size_t)cl->nblk * C * C);
   cl->g = a.take<double2>((size_t)C * C);
@@ -328,7 +342,7 @@ extern "C" int expenc_prewhiten(int32_t ncoils, const double *psi, int64_t nsamp
   hipStream_t s = (hipStream_t)stream;
   const int C = ncoils;
   const size_t lds = (size_t)C * C * sizeof(double2);
-  k_cholesky<<<1, 256, lds, s>>>(reinterpret_cast<const double2 *>(psi), C, cl.L);
+  k_cholesky<<<1, 256, lds, s>>>(reinterpret_cast<const double2 *>(psi), C, cl.L, cl.status);
   EX_LAUNCHED("cholesky");
   if (nsamples > 0) {
     k_whiten<<<(unsigned)ceil_div(nsamples, 256), 256, lds, s>>>(cl.L, C, reinterpret_cast<float2 *>(y), nsamples,
@@ -368,7 +382,7 @@ extern "C" int expenc_coil_compress(int32_t ncoils, int32_t nvirtual, int64_t ns
   if (jlds > 65536)
     EX_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k_jacobi), hipFuncAttributeMaxDynamicSharedMemorySize,
                                (int)jlds));
-  k_jacobi<<<1, 256, jlds, s>>>(cl.g, C, 40, v, eigval);
+  k_jacobi<<<1, 256, jlds, s>>>(cl.g, C, 40, v, eigval, cl.status);
   EX_LAUNCHED("jacobi");
   if (y_out) {
     k_compress_y<<<(unsigned)ceil_div(nsamples * nvirtual, 256), 256, 0, s>>>(

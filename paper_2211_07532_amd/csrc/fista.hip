@@ -85,10 +85,12 @@ __global__ __launch_bounds__(256) void k_resid_norm_part(const float2 *__restric
 // objective[b*K + k] = data[b] + lambda[b] * sum_{level, tile} l1[level][b][tile]
 // (level j wrote ceil(hx_j/16) * ceil(hy_j/8) tile sums out of nblk slots,
 // hx_j = (nxp >> j)/2, hy_j = (nyp >> j)/2)
+// With status: F(x_k) above f0[b] = F(0) = ||y_b||^2 flags divergence, a
+// non-finite F flags a non-finite iterate.
 __global__ __launch_bounds__(256) void k_objective(const double *__restrict__ data, const double *__restrict__ l1,
                                                    int levels, int B, int nblk, int nxp, int nyp,
                                                    const double *__restrict__ lam, double *__restrict__ obj, int K,
-                                                   int k) {
+                                                   int k, const double *__restrict__ f0, unsigned *status) {
   __shared__ double red[256];
   const int b = blockIdx.x;
   double s = 0.0;
@@ -103,13 +105,20 @@ __global__ __launch_bounds__(256) void k_objective(const double *__restrict__ da
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) obj[(int64_t)b * K + k] = data[b] + lam[b] * red[0];
+  if (threadIdx.x == 0) {
+    const double F = data[b] + lam[b] * red[0];
+    obj[(int64_t)b * K + k] = F;
+    if (status) {
+      if (!isfinite(F)) atomicOr(status, kStatusNonFinite);
+      else if (F > f0[b]) atomicOr(status, kStatusDiverged);
+    }
+  }
 }
 
 // CG: alpha = rs/pq; x += alpha p; r -= alpha q
 __global__ void k_cg_step(float2 *__restrict__ x, float2 *__restrict__ r, const float2 *__restrict__ p,
                           const float2 *__restrict__ q, int64_t n, const double *__restrict__ rs,
-                          const double *__restrict__ pq) {
+                          const double *__restrict__ pq, unsigned *status) {
   const int b = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -124,6 +133,7 @@ __global__ void k_cg_step(float2 *__restrict__ x, float2 *__restrict__ r, const 
   rv.y -= a * qv.y;
   x[o] = xv;
   r[o] = rv;
+  flag_nonfinite(status, xv);
 }
 
 // CG: beta = rs_new/rs; p = r + beta p   (rs updated by the caller afterwards)
@@ -160,8 +170,18 @@ __global__ void k_grad_step(float2 *__restrict__ v, const float2 *__restrict__ z
 }
 
 __global__ void k_copy_d(const double *in, double *out, int n) {
-  const int i = threadIdx.x;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = in[i];
+}
+
+__global__ void k_clear_status(unsigned *status) {
+  if (threadIdx.x == 0) status[0] = 0u;
+}
+
+int clear_status(unsigned *status, hipStream_t s) {
+  k_clear_status<<<1, 64, 0, s>>>(status);
+  EX_LAUNCHED("status clear");
+  return EXPENC_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -274,6 +294,8 @@ struct FistaLayout {
   double *sc = nullptr;      // [2P + 2PB + 3P]
   double *l1 = nullptr;      // [levels][B][l1_blocks]   (P == 1 only)
   double *data = nullptr;    // [B]
+  double *f0 = nullptr;      // [B] F(0) = ||y_b||^2   (P == 1, objective only)
+  unsigned *status = nullptr;  // the call's status word (start of the workspace)
   int l1_blocks = 0;
   double *lam_of(int) const { return sc + 2 * P; }
   double *tau() const { return sc + 2 * P + P * B; }
@@ -320,6 +342,7 @@ static int layout_fista(const expenc_op *op, int32_t nprob, int32_t batch, int32
   if (objective) {
     L->l1 = a.take<double>((size_t)levels * batch * L->l1_blocks);
     L->data = a.take<double>((size_t)batch);
+    L->f0 = a.take<double>((size_t)batch);
   }
   return a.ok() ? EXPENC_OK : EXPENC_EWORKSPACE;
 }
@@ -328,6 +351,7 @@ size_t fista_bytes(const expenc_op *op, int32_t batch, int32_t precision, int32_
   // default grids are rounded to 2^levels; 4 levels covers the usual cases
   Arena a;
   FistaLayout L;
+  take_status(a);
   const int levels = (nx_pad > 0 && ny_pad > 0) ? 1 : 4;
   if (layout_fista(op, 1, batch, precision, levels, nx_pad, ny_pad, true, a, &L) != EXPENC_OK && !L.p.R) return 0;
   return a.used + 256;
@@ -364,7 +388,7 @@ struct FistaGroup {
     EX_TRY(enc_prepare(pf, op, L.eb, s));
     if (opts->precision != EXPENC_FP32) EX_TRY(enc_prepare(p, op, L.eb, s));
     if (opts->lipschitz > 0) {
-      k_fill_d<<<1, 256, 0, s>>>(L.sc, P, opts->lipschitz);
+      k_fill_d<<<(unsigned)ceil_div(P, 256), 256, 0, s>>>(L.sc, P, opts->lipschitz);
       EX_LAUNCHED("fill");
     } else {
       EX_TRY(lipschitz_run(L.p1, op, L.eb, opts->n_power, opts->power_v0, L.pvec, L.ptmp, L.dpart, L.scratch(),
@@ -388,6 +412,11 @@ struct FistaGroup {
     }
     k_fista_scalars<<<(unsigned)ceil_div(P * B, 256), 256, 0, s>>>(L.sc, P, B);
     EX_LAUNCHED("scalars");
+    if (opts->objective) {
+      // F(0) = ||y||^2, the divergence bar of the objective trace
+      const int64_t ty = p.T * p.C;
+      EX_TRY(reduce_dot(y, y, ty, ty, B, 1.0, L.dpart, L.f0, s));
+    }
     k_zero_f2<<<(unsigned)ceil_div(img * P * B, 256), 256, 0, s>>>(L.x0, img * P * B);
     k_zero_f2<<<(unsigned)ceil_div(img * P * B, 256), 256, 0, s>>>(L.z, img * P * B);
     EX_LAUNCHED("zero");
@@ -455,7 +484,7 @@ struct FistaGroup {
       // x_k = W^H S_tau(W v), z = x_k + beta_k (x_k - x_{k-1}); v and x_k serve
       // as the transform's ping-pong buffers
       EX_TRY(dwt2_prox(f, nxp, nyp, opts->levels, P * B, L.v, L.w, xk, xprev, L.z, beta[k], L.tau(),
-                       with_obj ? L.l1 : nullptr, L.l1_blocks, cs));
+                       with_obj ? L.l1 : nullptr, L.l1_blocks, cs, L.status));
       if (with_obj) {
         EX_TRY(enc_build_z(pf, op->smaps, xk, img, nxp, L.eb, cs));
         EX_TRY(enc_forward_partials(pf, L.eb, cs));
@@ -464,7 +493,7 @@ struct FistaGroup {
         EX_LAUNCHED("residual norm");
         EX_TRY(reduce_sum_parts(L.dpart, kRedBlocks, B, 1.0, L.data, cs));
         k_objective<<<B, 256, 0, cs>>>(L.data, L.l1, opts->levels, B, L.l1_blocks, nxp, nyp, L.lam_of(0),
-                                        opts->objective, K, k);
+                                        opts->objective, K, k, L.f0, L.status);
         EX_LAUNCHED("objective");
       }
     }
@@ -493,11 +522,13 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
   if (!y || !x) return fail(EXPENC_EINVAL, "y or x is NULL");
   FistaGroup G;
   Arena a{static_cast<char *>(ws), ws_bytes, 0};
+  unsigned *status = take_status(a);
   const int st = layout_fista(op, 1, batch, opts->precision, opts->levels, opts->nx_pad, opts->ny_pad,
                               opts->objective != nullptr, a, &G.L);
   if (st == EXPENC_EWORKSPACE || !ws) {
     Arena need;
     FistaLayout tmp;
+    take_status(need);
     layout_fista(op, 1, batch, opts->precision, opts->levels, opts->nx_pad, opts->ny_pad, opts->objective != nullptr,
                  need, &tmp);
     return fail(EXPENC_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu required", ws_bytes,
@@ -509,7 +540,9 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
   G.opts = opts;
   G.y = reinterpret_cast<const float2 *>(y);
   G.refine = refine;
+  G.L.status = status;
   hipStream_t s = (hipStream_t)stream;
+  EX_TRY(clear_status(status, s));
   EX_TRY(G.prologue(s));
   uint64_t key = 1469598103934665603ull;
   key = fnv(key, op, sizeof(*op));
@@ -523,7 +556,7 @@ extern "C" int fista_solve(const expenc_op *op, int32_t batch, const float *y, f
   if (opts->n_iter > 0) EX_TRY(run_graph(key, s, [&](hipStream_t cs) { return G.body(cs); }));
   EX_TRY(G.epilogue(reinterpret_cast<float2 *>(x), s));
   if (opts->scalars) {
-    k_copy_d<<<1, 256, 0, s>>>(G.L.sc, opts->scalars, 2 + 2 * batch);
+    k_copy_d<<<(unsigned)ceil_div(2 + 2 * batch, 256), 256, 0, s>>>(G.L.sc, opts->scalars, 2 + 2 * batch);
     EX_LAUNCHED("scalars out");
   }
   return EXPENC_OK;
@@ -537,12 +570,14 @@ namespace expenc {
 struct CgLayout {
   EncPlan p;
   EncBuffers eb;
+  unsigned *status = nullptr;
   float2 *xv = nullptr, *rv = nullptr, *pv = nullptr, *qv = nullptr;
   double *dpart = nullptr, *rs = nullptr, *pq = nullptr, *rsn = nullptr;
 };
 
 static int layout_cg(const expenc_op *op, int32_t batch, int32_t precision, Arena &a, CgLayout *L) {
   EX_TRY(make_plan(op, batch, precision, &L->p));
+  L->status = take_status(a);
   carve_enc(L->p, a, &L->eb);
   const size_t n = (size_t)batch * L->p.R;
   L->xv = a.take<float2>(n);
@@ -581,6 +616,7 @@ extern "C" int cg_solve(const expenc_op *op, int32_t batch, const float *y, floa
   const int B = batch;
   const int64_t n = p.R;
   const dim3 vg((unsigned)ceil_div(n, 256), B);
+  EX_TRY(clear_status(L.status, s));
   EX_TRY(enc_prepare(p, op, L.eb, s));
   // r = A^H y ; p = r ; x = 0 ; rs = <r, r>
   EX_TRY(enc_pack_y(p, reinterpret_cast<const float2 *>(y), L.eb, s));
@@ -598,12 +634,12 @@ extern "C" int cg_solve(const expenc_op *op, int32_t batch, const float *y, floa
       EX_TRY(enc_adjoint_partials(p, L.eb, cs));
       EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.qv, n, p.nx, nullptr, nullptr, cs));
       EX_TRY(reduce_dot(L.pv, L.qv, n, n, B, 1.0, L.dpart, L.pq, cs));
-      k_cg_step<<<vg, 256, 0, cs>>>(L.xv, L.rv, L.pv, L.qv, n, L.rs, L.pq);
+      k_cg_step<<<vg, 256, 0, cs>>>(L.xv, L.rv, L.pv, L.qv, n, L.rs, L.pq, L.status);
       EX_LAUNCHED("cg step");
       EX_TRY(reduce_dot(L.rv, L.rv, n, n, B, 1.0, L.dpart, L.rsn, cs));
       k_cg_dir<<<vg, 256, 0, cs>>>(L.pv, L.rv, n, L.rs, L.rsn);
       EX_LAUNCHED("cg direction");
-      k_copy_d<<<1, 256, 0, cs>>>(L.rsn, L.rs, B);
+      k_copy_d<<<(unsigned)ceil_div(B, 256), 256, 0, cs>>>(L.rsn, L.rs, B);
       EX_LAUNCHED("cg copy");
     }
     return EXPENC_OK;
@@ -653,6 +689,7 @@ struct BatchPlan {
   std::vector<FistaGroup> groups;
   std::vector<expenc_op> packed;          // one packed operator per group
   std::vector<double *> z0s;
+  unsigned *status = nullptr;             // the call's status word (start of the workspace)
 };
 
 static int layout_batched(int32_t nprob, const expenc_op *ops, int32_t batch, const expenc_fista_opts *o, Arena &a,
@@ -662,6 +699,7 @@ static int layout_batched(int32_t nprob, const expenc_op *ops, int32_t batch, co
   if (o->objective || o->scalars) return fail(EXPENC_EUNSUPPORTED, "objective/scalars outputs are per single solve");
   if (o->nx_pad > 0 || o->ny_pad > 0)
     return fail(EXPENC_EINVAL, "batched solves pad each problem to 2^levels (nx_pad, ny_pad must be 0)");
+  bp->status = take_status(a);
   for (int i = 0; i < nprob; ++i) {
     int g = 0;
     for (; g < (int)bp->members.size(); ++g)
@@ -699,17 +737,39 @@ static int layout_batched(int32_t nprob, const expenc_op *ops, int32_t batch, co
   return a.ok() ? EXPENC_OK : EXPENC_EWORKSPACE;
 }
 
-static hipStream_t fork_stream(int device, int k) {
+// Fork/join resources of the batched capture: up to kForkStreams streams
+// (group g is captured on stream g % kForkStreams) and one event per group
+// plus the fork event, per device.  They are created before a capture
+// begins and kept until the process ends, so that no stream or event is
+// created or destroyed while a stream is being captured (an event recorded
+// into a capture stays referenced by the capture until it ends).
+constexpr int kForkStreams = 8;
+struct ForkPool {
+  std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> events;
+};
+
+static int fork_resources(int device, int ngroups, std::vector<hipStream_t> *streams,
+                          std::vector<hipEvent_t> *events) {
   static std::mutex mu;
-  static std::vector<std::vector<hipStream_t>> pool;
-  constexpr int kMax = 8;
+  static std::vector<ForkPool> pools;
   std::lock_guard<std::mutex> lk(mu);
-  if ((int)pool.size() <= device) pool.resize(device + 1);
-  auto &v = pool[device];
-  if (v.empty()) v.assign(kMax, nullptr);
-  hipStream_t &st = v[k % kMax];
-  if (!st) hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
-  return st;
+  if ((int)pools.size() <= device) pools.resize(device + 1);
+  ForkPool &fp = pools[device];
+  const int ns = std::min(ngroups, kForkStreams);
+  while ((int)fp.streams.size() < ns) {
+    hipStream_t st = nullptr;
+    EX_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    fp.streams.push_back(st);
+  }
+  while ((int)fp.events.size() < ngroups + 1) {
+    hipEvent_t e = nullptr;
+    EX_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    fp.events.push_back(e);
+  }
+  streams->assign(fp.streams.begin(), fp.streams.begin() + ns);
+  events->assign(fp.events.begin(), fp.events.begin() + ngroups + 1);
+  return EXPENC_OK;
 }
 
 }  // namespace expenc
@@ -747,6 +807,7 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
   EX_TRY(make_filter_set(opts->wavelet, &f));
   hipStream_t s = (hipStream_t)stream;
   const int NG = (int)bp.members.size();
+  EX_TRY(clear_status(bp.status, s));
   // gather the members' inputs into the packed group arrays
   for (int g = 0; g < NG; ++g) {
     const std::vector<int> &m = bp.members[g];
@@ -777,6 +838,7 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
     G.opts = opts;
     G.f = f;
     G.refine = refine;
+    G.L.status = bp.status;
     EX_TRY(G.prologue(s));
   }
   uint64_t key = 0x84222325cbf29ce4ull;
@@ -789,18 +851,20 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
   const uint64_t gen = tuning_generation();
   key = fnv(key, &gen, sizeof(gen));
   if (opts->n_iter > 0) {
-    EX_TRY(run_graph(key, s, [&](hipStream_t cs) -> int {
-      if (NG == 1) return bp.groups[0].body(cs);
+    std::vector<hipStream_t> fs;
+    std::vector<hipEvent_t> ev;
+    if (NG > 1) {
       int dev = 0;
       EX_HIP(hipGetDevice(&dev));
-      std::vector<hipEvent_t> ev(NG + 1, nullptr);
+      EX_TRY(fork_resources(dev, NG, &fs, &ev));
+    }
+    EX_TRY(run_graph(key, s, [&](hipStream_t cs) -> int {
+      if (NG == 1) return bp.groups[0].body(cs);
       int rc = EXPENC_OK;
-      for (auto &e : ev)
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = fail(EXPENC_EHIP, "event");
-      if (rc == EXPENC_OK && hipEventRecord(ev[NG], cs) != hipSuccess) rc = fail(EXPENC_EHIP, "fork record");
+      if (hipEventRecord(ev[NG], cs) != hipSuccess) return fail(EXPENC_EHIP, "fork record");
       for (int g = 0; g < NG && rc == EXPENC_OK; ++g) {
-        hipStream_t gs = fork_stream(dev, g);
-        if (!gs || hipStreamWaitEvent(gs, ev[NG], 0) != hipSuccess) {
+        hipStream_t gs = fs[g % fs.size()];
+        if (hipStreamWaitEvent(gs, ev[NG], 0) != hipSuccess) {
           rc = fail(EXPENC_EHIP, "fork");
           break;
         }
@@ -810,8 +874,6 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
         if (hipEventRecord(ev[g], gs) != hipSuccess || hipStreamWaitEvent(cs, ev[g], 0) != hipSuccess)
           rc = rc ? rc : fail(EXPENC_EHIP, "join");
       }
-      for (auto &e : ev)
-        if (e) hipEventDestroy(e);
       return rc;
     }));
   }

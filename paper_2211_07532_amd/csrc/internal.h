@@ -52,6 +52,22 @@ struct Arena {
   bool ok() const { return used <= size; }
 };
 
+// Status block at the start of every solver and coil workspace: one 32-bit
+// word of flags that kernels set (atomicOr) when they see a failure, cleared
+// at the start of each call, read back by expenc_solve_status.
+constexpr size_t kStatusBytes = 256;
+enum : unsigned {
+  kStatusNonFinite = 1u,  // an iterate (or a factor) holds NaN or Inf
+  kStatusDiverged = 2u    // the objective of eq. 1 rose above its value at x = 0
+};
+inline unsigned *take_status(Arena &a) { return a.take<unsigned>(kStatusBytes / sizeof(unsigned)); }
+// status[0] = 0 (stream-ordered; a fill kernel, so it may also be captured)
+int clear_status(unsigned *status, hipStream_t s);
+// Flags a non-finite complex value (no-op for a NULL status).
+__device__ inline void flag_nonfinite(unsigned *status, float2 v) {
+  if (status && !(isfinite(v.x) && isfinite(v.y))) atomicOr(status, kStatusNonFinite);
+}
+
 // Geometry of one encoding contraction: a GEMM-shaped sum over pixels
 // (forward) or samples (adjoint) with B*C complex columns, padded so that
 // the kernels never test bounds inside their loops.

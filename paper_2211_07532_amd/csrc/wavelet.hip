@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_idwt2_level(const float2 *__restrict__ 
                                                      const float2 *__restrict__ w, int nx, int64_t wpitch,
                                                      float2 *__restrict__ out, int ostride, int64_t opitch, int mx,
                                                      int my, FilterSet f, const float2 *__restrict__ xprev,
-                                                     float2 *__restrict__ zout, double beta) {
+                                                     float2 *__restrict__ zout, double beta, unsigned *status) {
   constexpr int NI = kInvT / 2 + TAPS / 2;
   __shared__ float2 sc[2 * NI][2 * NI];  // [low | high rows][low | high columns]
   __shared__ float2 cp[kInvT][2 * NI];   // column-pass output rows
@@ -431,6 +431,7 @@ __global__ __launch_bounds__(256) void k_idwt2_level(const float2 *__restrict__ 
     const float2 v = make_float2((float)vx, (float)vy);
     const int64_t o = b * opitch + (int64_t)m * ostride + n;
     out[o] = v;
+    flag_nonfinite(status, v);
     if (zout) {
       const float2 p = xprev[o];
       zout[o] = make_float2((float)(v.x + beta * ((double)v.x - p.x)), (float)(v.y + beta * ((double)v.y - p.y)));
@@ -535,7 +536,7 @@ int dwt2_tiles(int nx, int ny, int level) {
 // different buffers.
 int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *v, float2 *w, float2 *xk,
               const float2 *xprev, float2 *z, double beta, const double *tau, double *l1_part, int l1_stride,
-              hipStream_t s) {
+              hipStream_t s, unsigned *status) {
   if (f.taps != 2 && f.taps != kTapsMax) return fail(EXPENC_EUNSUPPORTED, "filters of %d taps", f.taps);
   if (nx % (1 << levels) || ny % (1 << levels)) return fail(EXPENC_EINVAL, "grid not a multiple of 2^levels");
   const int64_t pitch = (int64_t)nx * ny;
@@ -568,12 +569,13 @@ int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *
     dim3 grid((unsigned)ceil_div(mx, kInvT), (unsigned)ceil_div(my, kInvT), (unsigned)nimg);
     const float2 *xp = j == 0 ? xprev : nullptr;
     float2 *zo = j == 0 ? z : nullptr;
+    unsigned *st = j == 0 ? status : nullptr;
     if (f.taps == 2)
       k_idwt2_level<2><<<grid, 256, 0, s>>>(ll, lstride, pitch, w, nx, pitch, out, ostride, pitch, mx, my, f, xp, zo,
-                                            beta);
+                                            beta, st);
     else
       k_idwt2_level<8><<<grid, 256, 0, s>>>(ll, lstride, pitch, w, nx, pitch, out, ostride, pitch, mx, my, f, xp, zo,
-                                            beta);
+                                            beta, st);
     EX_LAUNCHED("idwt level");
   }
   return EXPENC_OK;

@@ -46,10 +46,10 @@ int dwt_inverse_levels(const FilterSet &f, int nx, int ny, int levels, int batch
 // x_k, both of which are overwritten (x_k with the result); x_prev and z must
 // be other buffers.  l1_part (optional) receives per-tile FP64 sums of the
 // thresholded detail moduli at [level][image][tile] (l1_stride tiles, see
-// dwt2_tiles).
+// dwt2_tiles).  status (optional): flagged if x_k holds NaN or Inf.
 int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *v, float2 *w, float2 *xk,
               const float2 *xprev, float2 *z, double beta, const double *tau, double *l1_part, int l1_stride,
-              hipStream_t s);
+              hipStream_t s, unsigned *status = nullptr);
 // Number of analysis tiles of level j (its l1 partial sums).
 int dwt2_tiles(int nx, int ny, int level);
 

@@ -38,6 +38,15 @@ def _stream(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+def _status(ws: torch.Tensor, where: str, raise_on_failure: bool) -> int:
+    """Outcome flags of the call that used ws (expenc_solve_status; waits for the
+    current stream).  Raises ExpencError on a failure if raise_on_failure."""
+    st = _b.lib().expenc_solve_status(_ptr(ws), _stream(ws.device))
+    if st in (_b.EXPENC_EINVAL, _b.EXPENC_EHIP) or (st != _b.EXPENC_OK and raise_on_failure):
+        check(st, where)
+    return st
+
+
 def _need(t: torch.Tensor, dtype, name: str, device):
     if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a torch tensor")
@@ -219,13 +228,17 @@ class FistaResult:
     lam: list
     tau: list
     objective: Optional[torch.Tensor]    # [B][n_iter] float64
+    status: Optional[int] = None         # expenc_solve_status (None when not read)
 
 
 def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4", precision="fp32",
           lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3, power_v0=None,
           n_power: int = 30, nx_pad: int = 0, ny_pad: int = 0, ista: bool = False, refine_every: int = 0,
-          trace: bool = False, sync_scalars: bool = True):
-    """FISTA on eq. 1 (see fista_solve in include/expenc.h).  Returns a FistaResult."""
+          trace: bool = False, sync_scalars: bool = True, check_status: bool = True):
+    """FISTA on eq. 1 (see fista_solve in include/expenc.h).  Returns a FistaResult.
+    With sync_scalars the call waits for the solve and reads its status word:
+    a non-finite iterate (or, with trace=True, an objective above F(0))
+    raises ExpencError when check_status, else is returned in .status."""
     single = y.dim() == 2
     yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
     _need(yb, torch.complex64, "y", op.device)
@@ -248,7 +261,8 @@ def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4"
                                ws.numel(), _stream(op.device)), "fista_solve")
     if sync_scalars:
         s = sc.cpu().tolist()
-        res = FistaResult(x[0] if single else x, s[0], s[2:2 + batch], s[2 + batch:2 + 2 * batch], obj)
+        st = _status(ws, "fista_solve", check_status)
+        res = FistaResult(x[0] if single else x, s[0], s[2:2 + batch], s[2 + batch:2 + 2 * batch], obj, st)
     else:
         res = FistaResult(x[0] if single else x, float("nan"), [], [], obj)
     return res
@@ -276,6 +290,7 @@ def prewhiten(psi: torch.Tensor, y: Optional[torch.Tensor] = None, smaps: Option
     ws = _coil_ws(C, 0, dev)
     check(_b.lib().expenc_prewhiten(C, _ptr(psi), ny, _ptr(y), npix, _ptr(smaps), _ptr(ws), ws.numel(),
                                     _stream(dev)), "expenc_prewhiten")
+    _status(ws, "expenc_prewhiten (noise covariance not positive definite)", True)
     return y, smaps
 
 
@@ -298,6 +313,7 @@ def coil_compress(y: torch.Tensor, nvirtual: int, smaps: Optional[torch.Tensor] 
     ws = _coil_ws(C, n, dev)
     check(_b.lib().expenc_coil_compress(C, nvirtual, n, _ptr(y), npix, _ptr(smaps), _ptr(yv), _ptr(sv), _ptr(v),
                                         _ptr(w), _ptr(ws), ws.numel(), _stream(dev)), "expenc_coil_compress")
+    _status(ws, "expenc_coil_compress", True)
     return yv, sv, w, v
 
 
@@ -389,6 +405,7 @@ def fista_balanced(y: torch.Tensor, op: Operator, n_iter: int, levels: int = 1, 
     check(_b.lib().fista_balanced_solve(ctypes.byref(op._c), B, _ptr(yb), _ptr(x), ctypes.byref(opts), _ptr(ws),
                                         ws.numel(), _stream(op.device)), "fista_balanced_solve")
     s = sc.cpu()
+    _status(ws, "fista_balanced_solve", True)
     return BalancedResult(x[0] if single else x, float(s[0]), float(s[1]), s[3:3 + B * nb].reshape(B, nb))
 
 
@@ -397,10 +414,13 @@ _batch_ws = {}
 
 def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: int, levels: int, wavelet="db4",
                   precision="fp32", lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3,
-                  power_v0=None, n_power: int = 30, ista: bool = False, refine_every: int = 0):
+                  power_v0=None, n_power: int = 30, ista: bool = False, refine_every: int = 0,
+                  check_status: bool = False):
     """Independent FISTA solves of problems (ys[i], ops[i]) in one call (see
     fista_solve_batched in include/expenc.h).  Every ys[i] is [T_i][C_i] (or
-    [B][T_i][C_i] with one B for all).  Returns the list of x_i."""
+    [B][T_i][C_i] with one B for all).  Returns the list of x_i.  With
+    check_status the call waits for the solves and raises ExpencError if any
+    iterate turned non-finite (otherwise it returns without waiting)."""
     if len(ys) != len(ops) or not ops:
         raise ValueError("need one y per operator")
     dev = ops[0].device
@@ -432,11 +452,14 @@ def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: i
         _batch_ws[dev] = ws
     check(_b.lib().fista_solve_batched(n, carr, batch, yp, xp, ctypes.byref(opts), _ptr(ws), ws.numel(),
                                        _stream(dev)), "fista_solve_batched")
+    if check_status:
+        _status(ws, "fista_solve_batched", True)
     return [x[0] if single else x for x in xs]
 
 
-def cg(y: torch.Tensor, op: Operator, n_iter: int, precision="fp32") -> torch.Tensor:
-    """Least squares by CG on A^H A x = A^H y from 0, n_iter iterations -> x [B][R]."""
+def cg(y: torch.Tensor, op: Operator, n_iter: int, precision="fp32", check_status: bool = False) -> torch.Tensor:
+    """Least squares by CG on A^H A x = A^H y from 0, n_iter iterations -> x [B][R].
+    With check_status the call waits and raises ExpencError on a non-finite iterate."""
     single = y.dim() == 2
     yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
     _need(yb, torch.complex64, "y", op.device)
@@ -448,4 +471,6 @@ def cg(y: torch.Tensor, op: Operator, n_iter: int, precision="fp32") -> torch.Te
     ws = op.workspace(_b.WS_CG, batch, precision)
     check(_b.lib().cg_solve(ctypes.byref(op._c), batch, _ptr(yb), _ptr(x), ctypes.byref(opts), _ptr(ws),
                             ws.numel(), _stream(op.device)), "cg_solve")
+    if check_status:
+        _status(ws, "cg_solve", True)
     return x[0] if single else x

@@ -2,7 +2,9 @@
 orthogonal (fully sampled Cartesian) encoding, the exact Lipschitz
 constant, ISTA monotone descent, the FISTA O(1/k^2) rate bound, the KKT
 conditions at a long-run optimum, CG against a dense least-squares solve,
-and the bf16/fp16 rounding emulation against torch's conversions."""
+the objective of eq. 1 against its closed-form minimum (with mutants that
+must fail), the lambda rule on a point object, and the bf16/fp16 rounding
+emulation against torch's conversions."""
 import math
 
 import numpy as np
@@ -127,12 +129,110 @@ def test_cg_matches_least_squares():
     np.testing.assert_allclose(solve.cg_ls(op2, y2, 1), op2.AH(y2) / 64, atol=1e-12)
 
 
-def test_nrmse_and_lambda_rule():
+def test_nrmse():
     a = np.array([1.0, 2.0, 2.0])
     assert solve.nrmse(a * 1.1, a) == pytest.approx(0.1)
-    op, w = _cartesian_op(n=8)
-    y = synth.random_complex((64, 4), 15)
-    assert solve.lambda_rule(op, y) == pytest.approx(1e-3 * np.max(np.abs(op.AH(y))))
+
+
+def test_lambda_rule_point_object():
+    """Unit coil, full Cartesian sampling: A^H A = N^2 I, so for a point object
+    a*delta_r the zero-filled image A^H y is N^2 a delta_r and the rule gives
+    lambda = 1e-3 * N^2 |a| (the lambda of Methods 2.1 read from W A^T y)."""
+    n = 8
+    fov = 0.2
+    coef = synth.cartesian_coef(n, fov, 3)
+    op = solve.Operator(np.ones((1, n * n), complex), coef, np.zeros(n * n), encoding.sh_basis(n, fov, 0.0, 3),
+                        None, n)
+    for r, a in ((0, 1.0), (27, 0.3 - 2.0j), (63, -5.5j)):
+        x = np.zeros(n * n, complex)
+        x[r] = a
+        assert solve.lambda_rule(op, op.A(x)) == pytest.approx(1e-3 * n * n * abs(a), rel=1e-12)
+        assert solve.lambda_rule(op, op.A(x), 0.05) == pytest.approx(0.05 * n * n * abs(a), rel=1e-12)
+
+
+def _orthogonal_problem(n=16, levels=2, seed=21):
+    """Cartesian encoding with sum_c |S_c|^2 = 1 (A^H A = N^2 I), data, lambda
+    and the closed-form minimiser of eq. 1: with u = A^H y / N^2,
+    ||A x - y||^2 = N^2 ||x - u||^2 + ||y||^2 - N^2 ||u||^2 and W orthonormal,
+    so w_hat = S_{lambda/(2 N^2)}(W u) on the detail bands, (W u) on LL."""
+    op, _ = _cartesian_op(n=n, seed=seed)
+    x = synth.phantom(synth.Workload("o", n, 0.2, 4, n * n, 1e-6, 1, 3, 0, 20, 5, "haar", levels, seed + 1))
+    y = op.A(x) + 0.02 * synth.random_complex((n * n, op.smaps.shape[0]), seed + 2)
+    lam = 0.08 * np.max(np.abs(op.AH(y)))
+    u = solve.pad(op.AH(y) / (n * n), n, n)
+    wu = wavelet.dwt2(u, levels, "haar")
+    det = wavelet.detail_mask(n, n, levels)
+    w_hat = wu.copy()
+    mag = np.abs(wu[det])
+    t = lam / (2 * n * n)
+    w_hat[det] = np.where(mag > t, wu[det] * (1 - t / np.maximum(mag, 1e-300)), 0)
+    x_hat = wavelet.idwt2(w_hat, levels, "haar")
+    # the minimum value from the decomposition above (no call of the objective)
+    f_min = (np.vdot(y, y).real - n * n * np.vdot(u, u).real + n * n * np.sum(np.abs(w_hat - wu) ** 2)
+             + lam * np.sum(np.abs(w_hat[det])))
+    return op, y, lam, levels, x_hat, f_min
+
+
+def _minimiser_holds(objective, op, y, lam, levels, x_hat, f_min):
+    """True iff the objective takes the closed-form minimum value at x_hat and
+    no pair of perturbations +-delta lowers it: 24 random image-domain
+    directions, 24 random directions on the support of W x_hat (where the l1
+    term is differentiable) and the ray through x_hat, at three scales."""
+    n = op.n
+    f_hat = objective(op, y, x_hat, lam, levels, "haar")
+    if abs(f_hat - f_min) > 1e-10 * abs(f_min):
+        return False
+    rng = np.random.default_rng(5)
+    supp = np.abs(wavelet.dwt2(x_hat, levels, "haar")) > 0
+    dirs = []
+    for k in range(24):
+        d = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        dirs.append((k, d))
+        e = (rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))) * supp
+        dirs.append((k, wavelet.idwt2(e, levels, "haar")))
+    dirs += [(k, x_hat) for k in range(3)]
+    for k, d in dirs:
+        d = d * 10.0 ** (-2 - k % 3) * np.linalg.norm(x_hat) / np.linalg.norm(d)
+        for sgn in (1.0, -1.0):
+            if objective(op, y, x_hat + sgn * d, lam, levels, "haar") < f_hat - 1e-13 * abs(f_hat):
+                return False
+    return True
+
+
+def test_objective_pins():
+    """solve.objective is eq. 1 as written: F(0) = ||y||^2, and on an
+    orthogonal encoding it takes the closed-form minimum at the closed-form
+    minimiser and rises along every tested direction.  The same check rejects
+    plausible mistakes: a 1/2 on the data term, a penalised LL band, squared
+    moduli in the l1 term."""
+    op, y, lam, levels, x_hat, f_min = _orthogonal_problem()
+    n = op.n
+    assert solve.objective(op, y, np.zeros((n, n), complex), lam, levels, "haar") == pytest.approx(
+        np.vdot(y, y).real, rel=1e-14)
+    assert _minimiser_holds(solve.objective, op, y, lam, levels, x_hat, f_min)
+
+    def half_data(op, y, xp, lam, levels, wname):
+        r = op.A(solve.crop(xp, op.n)) - y
+        w = wavelet.dwt2(xp, levels, wname)
+        det = wavelet.detail_mask(*xp.shape[-2:], levels)
+        return 0.5 * np.vdot(r, r).real + lam * np.sum(np.abs(w[det]))
+
+    def ll_penalised(op, y, xp, lam, levels, wname):
+        r = op.A(solve.crop(xp, op.n)) - y
+        return np.vdot(r, r).real + lam * np.sum(np.abs(wavelet.dwt2(xp, levels, wname)))
+
+    def squared_l1(op, y, xp, lam, levels, wname):
+        r = op.A(solve.crop(xp, op.n)) - y
+        w = wavelet.dwt2(xp, levels, wname)
+        det = wavelet.detail_mask(*xp.shape[-2:], levels)
+        return np.vdot(r, r).real + lam * np.sum(np.abs(w[det]) ** 2)
+
+    for mutant in (half_data, ll_penalised, squared_l1):
+        assert not _minimiser_holds(mutant, op, y, lam, levels, x_hat, f_min), mutant.__name__
+    # the minimiser check alone (value pin aside) also sees the first two mistakes
+    for mutant in (half_data, ll_penalised):
+        f_mut = mutant(op, y, x_hat, lam, levels, "haar")
+        assert not _minimiser_holds(mutant, op, y, lam, levels, x_hat, f_mut), mutant.__name__
 
 
 def test_momentum_coefficients():
