@@ -146,6 +146,23 @@ int expenc_adjoint(const expenc_op *op, int32_t batch, int32_t precision,
                    const float *y, float *x, void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = A_exp x as expenc_forward, with no workspace argument.  Its scratch is
+ * a static device array of the library, 128 MiB per device, held from the
+ * first call on a device until the process ends; the call itself allocates
+ * nothing.  The forward's reduction split is lowered as far as needed to fit
+ * (not below the FP32 form's chunk limit, so results may differ from
+ * expenc_forward by summation order only); an operator whose forward does not
+ * fit returns EXPENC_EWORKSPACE.  All calls on one device share the array:
+ * calls that overlap on one device (different streams, other threads) race,
+ * and must be ordered by the caller.  x: [B][R], y: [B][T][C] as in
+ * expenc_forward.
+ */
+int expenc_forward_static(const expenc_op *op, int32_t batch, int32_t precision,
+                          const float *x, float *y, void *stream);
+
+/*
  * Lipschitz constant of the gradient of ||A x - y||^2: L = 2 lambda_max(A^H A),
  * by n_iter normalised power steps v <- A^H A v / ||A^H A v|| from the
  * caller's start vector v0 [R] complex64, then the Rayleigh quotient

@@ -70,6 +70,7 @@ SIGNATURES = {
                                        _c_int, _vp, _vp]),
     "expenc_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int, _c_int, _c_int]),
     "expenc_forward": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
+    "expenc_forward_static": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _vp, _vp, _vp]),
     "expenc_adjoint": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "expenc_lipschitz": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _vp, _vp, _vp, ctypes.c_size_t,
                                         _vp]),

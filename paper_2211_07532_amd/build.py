@@ -17,7 +17,7 @@ CSRC = os.path.join(PKG, "csrc")
 OUT_DIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(OUT_DIR, "libexpenc.so")
 SOURCES = ["encode.hip", "split.hip", "split_adj.hip", "wavelet.hip", "api.hip", "fista.hip", "grad.hip", "coils.hip",
-           "balanced.hip"]
+           "balanced.hip", "noalloc.hip"]
 # Per-source code generation: the polynomial split adjoint keeps its matrix-
 # core results in the vector register file (no AGPR copies of the phase
 # tiles; 163 registers, three waves per SIMD instead of two).  The same

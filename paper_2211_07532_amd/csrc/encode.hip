@@ -675,6 +675,28 @@ size_t enc_operand_bytes(const EncPlan &p) {
   return a.used + 256;
 }
 
+int plan_forward_within(const expenc_op *op, int32_t batch, int32_t precision, size_t cap, EncPlan *p) {
+  EncPlan q;
+  EX_TRY(make_plan(op, batch, precision, &q));
+  // the forward uses no adjoint partial sums: one adjoint split keeps them small
+  q.adj_split = 1;
+  q.adj_chunk = (int32_t)q.Tp;
+  const int32_t min_split = q.prec == EXPENC_FP32 ? (int32_t)ceil_div(q.Rp, kF32ChunkMax) : 1;
+  auto set_split = [&](int32_t want) {
+    q.fwd_chunk = (int32_t)round_up(ceil_div(q.Rp, want), 16);
+    if (q.prec == EXPENC_FP32) q.fwd_chunk = std::min(q.fwd_chunk, kF32ChunkMax);
+    q.fwd_split = (int32_t)ceil_div(q.Rp, q.fwd_chunk);
+    q.nwmax = (int32_t)split_grid(q.Tp / 256 * q.fwd_split) * q.NGY * 4;
+  };
+  while (enc_operand_bytes(q) > cap && q.fwd_split > min_split)
+    set_split(std::max<int32_t>(min_split, q.fwd_split - std::max<int32_t>(1, q.fwd_split / 4)));
+  if (enc_operand_bytes(q) > cap)
+    return fail(EXPENC_EWORKSPACE, "the forward of this operator needs %zu bytes of scratch, more than the %zu "
+                "of the static scratch (use expenc_forward with a workspace)", enc_operand_bytes(q), cap);
+  *p = q;
+  return EXPENC_OK;
+}
+
 size_t enc_part_elems(const EncPlan &p) {
   const size_t pf = (size_t)p.fwd_split * p.Tp * p.NCP;
   const size_t pa = (size_t)p.adj_split * p.Rp * (p.comb ? p.NGY : p.NCP);
@@ -854,8 +876,8 @@ static void launch_adj(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
     k_adj_f32<NT, 1><<<grid, 256, 0, s>>>(b.kap, b.bet, b.yop, part, p.Rp, p.Tp, p.NCP, p.adj_chunk, p.adj_split);
 }
 
-int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  timed(0, s, [&] {
+int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s, bool timing) {
+  auto launch = [&] {
     if (p.prec != EXPENC_FP32) {
       split_forward_launch(p, b, s);
       return;
@@ -865,7 +887,9 @@ int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
       case 10: launch_fwd<10>(p, b, s); break;
       default: launch_fwd<17>(p, b, s); break;
     }
-  });
+  };
+  if (timing) timed(0, s, launch);
+  else launch();
   EX_LAUNCHED("forward contraction");
   return EXPENC_OK;
 }

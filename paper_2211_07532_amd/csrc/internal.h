@@ -271,6 +271,10 @@ struct EncBuffers {
 };
 
 size_t enc_operand_bytes(const EncPlan &p);
+// Forward-only plan whose buffers (carve_enc) fit in cap bytes: one adjoint
+// split, and the forward split lowered from make_plan's as far as needed
+// (not below the FP32 chunk cap).  EXPENC_EWORKSPACE if even that is larger.
+int plan_forward_within(const expenc_op *op, int32_t batch, int32_t precision, size_t cap, EncPlan *p);
 // Split-K partial-sum elements (float2) a plan needs.
 size_t enc_part_elems(const EncPlan &p);
 // Runs body(stream) captured into a cached HIP graph keyed by `key` (or
@@ -300,7 +304,8 @@ int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipS
 int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x_stride,
                 int32_t x_row_stride, const EncBuffers &b, hipStream_t s, const float2 *xsub = nullptr,
                 int64_t x_pstride = 0);
-int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+// (timing = false: never records the profiling events of expenc_kernel_timing)
+int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s, bool timing = true);
 // y[b][t][c] = sum_split partials (ABI layout)
 int enc_forward_reduce_out(const EncPlan &p, const EncBuffers &b, float2 *y, hipStream_t s);
 // Y operand from sign * y, y [B][T][C] (sign other than 1: FP32 plans only)
