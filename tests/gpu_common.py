@@ -59,3 +59,23 @@ class Case:
     def to_dev(self, a: np.ndarray):
         import torch
         return torch.from_numpy(np.ascontiguousarray(a).astype(np.complex64)).to(self.dev)
+
+
+def emulated_split_errors(case, x, g, ts, rs, kind):
+    """Relative errors that the round-to-nearest-even emulation of the split
+    arithmetic (oracle.splitemu: phase tile rounded to FP32, both operands
+    split hi/lo, three products) shows for the forward on sample rows ts
+    (input image x [R]) and for the adjoint on pixels rs (input data g [T][C],
+    coil combination in FP64), against exact FP64 sums."""
+    from oracle import encoding, splitemu
+    coef, time, basis, dw0, smaps = case.coef, case.time, case.basis_np, case.dw0, case.smaps
+    z = (smaps * x[None, :]).T                                    # [R][C]
+    ph = encoding.phase(coef[ts], time[ts], basis, dw0)           # [len(ts)][R]
+    e32 = np.exp(1j * ph).astype(np.complex64).astype(np.complex128)
+    fwd = rel(splitemu.split_cmatmul(e32, c64(z), kind), np.exp(1j * ph) @ z)
+    ph = encoding.phase(coef, time, basis[:, rs], None if dw0 is None else dw0[rs])  # [T][len(rs)]
+    e32 = np.exp(1j * ph).astype(np.complex64).astype(np.complex128)
+    u = splitemu.split_cmatmul(np.conj(e32).T, g, kind)           # [len(rs)][C]
+    x_emu = np.sum(np.conj(smaps[:, rs]).T * u, axis=1)
+    x_ex = np.sum(np.conj(smaps[:, rs]).T * (np.conj(np.exp(1j * ph)).T @ g), axis=1)
+    return fwd, rel(x_emu, x_ex)

@@ -1,6 +1,6 @@
 """GPU parity of the expanded encoding operators (FP32 form) against the FP64
 oracle: whole-output comparisons at small sizes that span several tiles and
-ragged tails, sampled outputs at full size, the adjoint identity, and
+ragged tails, the adjoint identity, and
 bitwise determinism.  Tolerance: relative l2 error <= 1e-5 (FP32 form)."""
 import numpy as np
 import pytest
@@ -79,35 +79,6 @@ def test_bitwise_determinism():
     a1 = ee.adjoint(g, case.op).cpu().numpy()
     a2 = ee.adjoint(g, case.op).cpu().numpy()
     assert np.array_equal(a1.view(np.uint32), a2.view(np.uint32))
-
-
-@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
-@pytest.mark.parametrize("wl", [synth.MM15, synth.MM11])
-def test_full_size_sampled_outputs(wl, sh):
-    """Full-size operators in the benchmark's launch configuration: sampled
-    samples/pixels against the oracle's one-output direct sums."""
-    ee = _ee()
-    from paper_2211_07532_amd import autotune
-    print(f"[case] full {wl.name} sh={sh}", flush=True)
-    case = Case(wl, sh=sh)
-    autotune.apply_cached(case.op, 1, "fp32")    # the shipped launch shapes (the bench's)
-    x = case.x_noisy
-    y = ee.forward(case.to_dev(x), case.op).cpu().numpy()
-    rng = np.random.default_rng(5)
-    ts = np.concatenate([[0, 1, wl.nsamples - 1], rng.integers(0, wl.nsamples, 13)])
-    got = np.stack([y[t] for t in ts])
-    ref = np.stack([encoding.forward_one(x, *case.oracle_args(), int(t)) for t in ts])
-    assert rel(got, ref) <= TOL
-    xa = ee.adjoint(case.to_dev(y), case.op).cpu().numpy()
-    rs = np.concatenate([[0, wl.npix - 1], rng.integers(0, wl.npix, 10)])
-    yy = y.astype(np.complex128)
-    got = np.array([xa[r] for r in rs])
-    ref = np.array([encoding.adjoint_one(yy, *case.oracle_args(), int(r)) for r in rs])
-    assert rel(got, ref) <= TOL
-    # adjoint identity at full size
-    lhs = np.vdot(yy, y)
-    rhs = np.vdot(xa, x)
-    assert abs(lhs - rhs) / (np.linalg.norm(y) ** 2) <= 1e-6
 
 
 def test_invalid_arguments_raise():

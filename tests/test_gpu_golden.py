@@ -93,10 +93,12 @@ def mm11():
     return w, case, y, g
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
 def test_full_size_1p1mm_fista_matches_golden(mm11, prec):
-    """The 1.1 mm configuration: FP32 against the FP16-split form with FP32
-    anchors, 100 iterations, final NRMSE against the FP64 oracle's solve."""
+    """The 1.1 mm configuration: FP32 against the split forms with FP32
+    anchors, 100 iterations, final NRMSE against the FP64 oracle's solve
+    (FP32 and fp16 within 1e-5; bf16, whose halves keep 16 bits, within the
+    split forms' 1e-4)."""
     import paper_2211_07532_amd as ee
     w, case, y, g = mm11
     v0 = case.to_dev(c64(synth.power_start(w.npix, int(g["power_seed"]))))
@@ -107,4 +109,4 @@ def test_full_size_1p1mm_fista_matches_golden(mm11, prec):
           f"lambda {res.lam[0]:.6e} (ref {float(g['lam']):.6e})", flush=True)
     assert abs(res.lipschitz - float(g["lipschitz"])) <= 1e-5 * float(g["lipschitz"])
     assert abs(res.lam[0] - float(g["lam"])) <= 1e-5 * float(g["lam"])
-    assert e <= 1e-5
+    assert e <= (1e-4 if prec == "bf16" else 1e-5)

@@ -2,15 +2,17 @@
 the anchored-refinement FISTA against the FP64 oracle.
 
 Bars: relative l2 error of A / A^H <= 1e-3 in split form (the target for the
-split operators before refinement), and no worse than 5x the error level
-the RNE split emulation predicts for the same arithmetic; image NRMSE after
-a split-form solve with FP32 anchors <= 1e-4."""
+split operators before refinement), and, in both directions, no worse than
+5x the error level the RNE split emulation predicts for the same arithmetic
+(plus 2e-6 for the FP32 phase increments); image NRMSE after a split-form
+solve with FP32 anchors <= 1e-4.  Whole-output full-size parity is in
+test_gpu_fullsize.py."""
 import numpy as np
 import pytest
 
 import synth
-from oracle import encoding, solve, splitemu
-from tests.gpu_common import Case, c64, rel
+from oracle import encoding, solve
+from tests.gpu_common import Case, c64, emulated_split_errors, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -18,16 +20,6 @@ pytestmark = pytest.mark.gpu
 def _ee():
     import paper_2211_07532_amd as ee
     return ee
-
-
-def _emulated_forward_error(case, x, kind):
-    """Relative error of the 3-product split forward predicted by RNE
-    emulation, with the phase tile rounded to FP32 first (tiny sizes)."""
-    ph = encoding.phase(case.coef, case.time, case.basis_np, case.dw0)
-    e = np.exp(1j * ph).astype(np.complex64).astype(np.complex128)
-    z = (case.smaps * x[None, :]).T.astype(np.complex64).astype(np.complex128)
-    ref = np.exp(1j * ph) @ (case.smaps * x[None, :]).T
-    return rel(splitemu.split_cmatmul(e, z, kind), ref)
 
 
 @pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
@@ -56,35 +48,15 @@ def test_split_operators(prec, name, sh):
     g = c64(synth.random_complex(y_ref.shape, 62))
     x_ref = encoding.adjoint(g, *case.oracle_args())
     e_adj = rel(ee.adjoint(case.to_dev(g), case.op, precision=prec).cpu().numpy(), x_ref)
-    emu = _emulated_forward_error(case, case.x_noisy, prec)
-    print(f"split {prec} {name} sh={sh}: forward {e_fwd:.2e} adjoint {e_adj:.2e} emulated {emu:.2e}", flush=True)
+    # the adjoint is held to the emulation of its first image alone
+    e_adj0 = rel(ee.adjoint(case.to_dev(g[:1]), case.op, precision=prec).cpu().numpy()[0], x_ref[0])
+    emu_f, emu_a = emulated_split_errors(case, case.x_noisy, g[0], np.arange(w.nsamples), np.arange(w.npix), prec)
+    e_fwd0 = rel(y[0], y_ref[0])
+    print(f"split {prec} {name} sh={sh}: forward {e_fwd:.2e} ({e_fwd0:.2e} image 0, emulated {emu_f:.2e}), "
+          f"adjoint {e_adj:.2e} ({e_adj0:.2e} image 0, emulated {emu_a:.2e})", flush=True)
     assert e_fwd <= 1e-3 and e_adj <= 1e-3
-    assert e_fwd <= 5 * emu + 2e-6
-
-
-@pytest.mark.parametrize("wl", [synth.MM15, synth.MM11], ids=["1.5mm", "1.1mm"])
-@pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
-@pytest.mark.parametrize("prec", ["bf16", "fp16"])
-def test_split_full_size_sampled(prec, sh, wl):
-    ee = _ee()
-    from paper_2211_07532_amd import autotune
-    print(f"[case] split full {wl.name} {prec} sh={sh}", flush=True)
-    case = Case(wl, sh=sh)
-    autotune.apply_cached(case.op, 1, prec)      # the shipped launch shapes (the bench's)
-    x = case.x_noisy
-    y = ee.forward(case.to_dev(x), case.op, precision=prec).cpu().numpy()
-    rng = np.random.default_rng(6)
-    ts = np.concatenate([[0, wl.nsamples - 1], rng.integers(0, wl.nsamples, 10)])
-    got = np.stack([y[t] for t in ts])
-    ref = np.stack([encoding.forward_one(x, *case.oracle_args(), int(t)) for t in ts])
-    e = rel(got, ref)
-    xa = ee.adjoint(case.to_dev(y), case.op, precision=prec).cpu().numpy()
-    rs = np.concatenate([[0, wl.npix - 1], rng.integers(0, wl.npix, 8)])
-    got = np.array([xa[r] for r in rs])
-    ref = np.array([encoding.adjoint_one(y.astype(np.complex128), *case.oracle_args(), int(r)) for r in rs])
-    e2 = rel(got, ref)
-    print(f"split {prec} full {wl.name} sh={sh}: forward {e:.2e} adjoint {e2:.2e}", flush=True)
-    assert e <= 1e-3 and e2 <= 1e-3
+    assert e_fwd0 <= 5 * emu_f + 2e-6
+    assert e_adj0 <= 5 * emu_a + 2e-6
 
 
 @pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
