@@ -238,6 +238,16 @@ int soft_threshold_vjp(int32_t nx, int32_t ny, int32_t levels, int32_t batch, co
 int expenc_field_grad(const expenc_op *op, int32_t precision, const float *w, const float *kk,
                       double *grad_coef, double *grad_dw0, void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * out = a x + b y over n complex64 values, a and b real (FP32 arithmetic).
+ * The linear steps of a FISTA iteration on eq. 1 (Methods 2.1) as a
+ * separate call, for differentiating through unrolled iterations: the
+ * residual A z - y (a = 1, b = -1), the gradient step z - (2/L) grad
+ * (b = -2/L) and the momentum (1 + beta) x_k - beta x_{k-1}.  out may equal
+ * x or y.
+ */
+int expenc_axpby(int64_t n, double a, const float *x, double b, const float *y, float *out, void *stream);
+
 /* Options of fista_solve / cg_solve. */
 typedef struct expenc_fista_opts {
   int32_t n_iter;          /* iterations K (Methods 2.1 uses 100)                    */

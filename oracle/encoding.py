@@ -195,3 +195,75 @@ def vjp_adjoint(y, gx, smaps, coef, time, basis, dw0):
     eh_ty = e.conj().T @ (time[:, None] * y)             # [R][C]
     gd = np.imag(gx.conj() * np.sum(smaps.conj().T * eh_ty, axis=1))
     return grad_y, gc, gd
+
+
+
+# The same field-parameter VJPs without forming E whole (for sizes such as
+# 128 x 128 pixels x 12000 samples): grad_coef is computed in blocks of its
+# sample index t, grad_dw0 in blocks of its pixel index r, each block by the
+# formulas above restricted to its own outputs (no sum is split).
+
+def _basis_products(e_blk, basis, z):
+    """(E_blk (b_l * z))[t, l, c] for every basis term l: one matmul with the
+    L*C columns b_l(r) z[r, c]."""
+    r_n, c_n = z.shape
+    l_n = basis.shape[0]
+    bz = (basis[:, :, None] * z[None, :, :]).transpose(1, 0, 2).reshape(r_n, l_n * c_n)
+    return (e_blk @ bz).reshape(e_blk.shape[0], l_n, c_n)
+
+
+def field_vjp_forward(x, g, smaps, coef, time, basis, dw0, block: int = 256):
+    """(grad_coef [T][L], grad_dw0 [R] or None) of vjp_forward, blocked:
+      grad_coef[t, l] = -Im sum_c conj(g[t,c]) (E (b_l * Z))[t, c]   (blocks of t)
+      grad_dw0[r]     = -Im sum_c Z[r,c] conj((E^H (t * g))[r, c])   (blocks of r)"""
+    g = np.asarray(g, dtype=np.complex128)
+    z = (smaps * np.asarray(x, dtype=np.complex128)[None, :]).T      # [R][C]
+    t_n, r_n = coef.shape[0], smaps.shape[1]
+    gc = np.empty(coef.shape)
+    gd = None if dw0 is None else np.empty(r_n)
+
+    def run_t(se):
+        s, e = se
+        e_blk = np.exp(1j * phase(coef[s:e], time[s:e], basis, dw0))            # [Tblk][R]
+        gc[s:e] = -np.imag(np.sum(g[s:e, None, :].conj() * _basis_products(e_blk, basis, z), axis=2))
+
+    def run_r(se):
+        s, e = se
+        e_blk = np.exp(1j * phase(coef, time, basis[:, s:e], dw0[s:e]))          # [T][Rblk]
+        eh_tg = e_blk.conj().T @ (time[:, None] * g)                             # [Rblk][C]
+        gd[s:e] = -np.imag(np.sum(z[s:e] * eh_tg.conj(), axis=1))
+
+    with _pool() as p:
+        list(p.map(run_t, _blocks(t_n, block)))
+        if dw0 is not None:
+            list(p.map(run_r, _blocks(r_n, block)))
+    return gc, gd
+
+
+def field_vjp_adjoint(y, gx, smaps, coef, time, basis, dw0, block: int = 256):
+    """(grad_coef [T][L], grad_dw0 [R] or None) of vjp_adjoint, blocked:
+      grad_coef[t, l] = Im sum_c y[t,c] conj((E (b_l * S * gx))[t, c])             (blocks of t)
+      grad_dw0[r]     = Im( conj(gx[r]) sum_c conj(S_c(r)) (E^H (t * y))[r, c] )   (blocks of r)"""
+    y = np.asarray(y, dtype=np.complex128)
+    gx = np.asarray(gx, dtype=np.complex128)
+    sg = (smaps * gx[None, :]).T                                              # [R][C]
+    t_n, r_n = coef.shape[0], smaps.shape[1]
+    gc = np.empty(coef.shape)
+    gd = None if dw0 is None else np.empty(r_n)
+
+    def run_t(se):
+        s, e = se
+        e_blk = np.exp(1j * phase(coef[s:e], time[s:e], basis, dw0))
+        gc[s:e] = np.imag(np.sum(y[s:e, None, :] * _basis_products(e_blk, basis, sg).conj(), axis=2))
+
+    def run_r(se):
+        s, e = se
+        e_blk = np.exp(1j * phase(coef, time, basis[:, s:e], dw0[s:e]))
+        eh_ty = e_blk.conj().T @ (time[:, None] * y)
+        gd[s:e] = np.imag(gx[s:e].conj() * np.sum(smaps[:, s:e].conj().T * eh_ty, axis=1))
+
+    with _pool() as p:
+        list(p.map(run_t, _blocks(t_n, block)))
+        if dw0 is not None:
+            list(p.map(run_r, _blocks(r_n, block)))
+    return gc, gd

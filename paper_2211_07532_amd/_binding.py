@@ -110,6 +110,7 @@ SIGNATURES = {
                                         ctypes.POINTER(ctypes.c_int64)]),
     "expenc_kernel_timing": (ctypes.c_int, [_c_int, ctypes.POINTER(ctypes.c_double)]),
     "expenc_solve_status": (ctypes.c_int, [_vp, _vp]),
+    "expenc_axpby": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, _vp, ctypes.c_double, _vp, _vp, _vp]),
     "expenc_last_error": (ctypes.c_char_p, []),
 }
 

@@ -7,13 +7,16 @@
 * ``WaveletFwd`` / ``WaveletInv`` : W and W^H (orthonormal, so each is the
   other's backward);
 * ``SoftThreshold`` : the prox of the l1 term, backward = ``soft_threshold_vjp``;
+* ``Axpby`` : a x + b y (real a, b) in the library (``expenc_axpby``), for
+  the linear steps of an iteration: the residual, the gradient step and the
+  momentum; its backward is the same call with the scalars;
 * ``unrolled_fista`` : K iterations of FISTA on eq. 1 with fixed L and lambda,
   optionally with per-iteration checkpointing (each iteration is recomputed
   in the backward pass from its inputs instead of storing its intermediates).
 
 Complex gradients follow torch's convention grad = dL/dRe + i dL/dIm.
-The elementwise glue between the operators (cropping, the gradient step and
-the momentum combination) is plain tensor arithmetic.
+Between the library calls only layout moves remain in torch (the crop of
+the encoded block, its zero padding to the wavelet grid, reshapes).
 """
 from __future__ import annotations
 
@@ -170,6 +173,22 @@ class SoftThreshold(torch.autograd.Function):
         return out.reshape(w.shape), None, None
 
 
+class Axpby(torch.autograd.Function):
+    """out = a x + b y for complex64 x, y of one shape and real a, b."""
+
+    @staticmethod
+    def forward(ctx, a: float, x, b: float, y):
+        ctx.a, ctx.b = float(a), float(b)
+        return _e.axpby(ctx.a, x.contiguous(), ctx.b, y.contiguous())
+
+    @staticmethod
+    def backward(ctx, g):
+        g = g.contiguous()
+        gx = _e.axpby(ctx.a, g, 0.0, g) if ctx.needs_input_grad[1] else None
+        gy = _e.axpby(ctx.b, g, 0.0, g) if ctx.needs_input_grad[3] else None
+        return None, gx, None, gy
+
+
 def momentum(n_iter: int):
     """beta_k = (t_k - 1)/t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2."""
     out, t = [], 1.0
@@ -183,13 +202,13 @@ def momentum(n_iter: int):
 def _iteration(z, x_prev, y, coef, dw0, spec, L, lam, beta, levels, wavelet, nxp, nyp):
     nx, ny = spec.nx, spec.ny
     zc = z[..., :ny, :nx].reshape(z.shape[0], nx * ny).contiguous()
-    r = ExpEncForward.apply(zc, coef, dw0, spec) - y
-    g = ExpEncAdjoint.apply(r.contiguous(), coef, dw0, spec).reshape(z.shape[0], ny, nx)
+    r = Axpby.apply(1.0, ExpEncForward.apply(zc, coef, dw0, spec), -1.0, y)
+    g = ExpEncAdjoint.apply(r, coef, dw0, spec).reshape(z.shape[0], ny, nx)
     g = torch.nn.functional.pad(torch.view_as_real(g), (0, 0, 0, nxp - nx, 0, nyp - ny))
-    v = z - (2.0 / L) * torch.view_as_complex(g.contiguous())
+    v = Axpby.apply(1.0, z, -2.0 / L, torch.view_as_complex(g.contiguous()))
     w = SoftThreshold.apply(WaveletFwd.apply(v, levels, wavelet), lam / L, levels)
     x = WaveletInv.apply(w, levels, wavelet)
-    return x, x + beta * (x - x_prev)
+    return x, Axpby.apply(1.0 + beta, x, -beta, x_prev)
 
 
 def unrolled_fista(y, coef, dw0, spec: OperatorSpec, L: float, lam: float, n_iter: int, levels: int,

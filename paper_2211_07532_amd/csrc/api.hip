@@ -173,6 +173,15 @@ __global__ void k_copy_f2(const float2 *__restrict__ in, float2 *__restrict__ ou
   if (i < n) out[i] = in[i];
 }
 
+// out = a x + b y over n complex values (real a, b)
+__global__ void k_axpby(int64_t n, float a, const float2 *__restrict__ x, float b, const float2 *__restrict__ y,
+                        float2 *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float2 u = x[i], v = y[i];
+  out[i] = make_float2(fmaf(a, u.x, b * v.x), fmaf(a, u.y, b * v.y));
+}
+
 // L[p] = 2 * num[p]/den[p] for each problem
 __global__ void k_lipschitz_final(const double *__restrict__ num, const double *__restrict__ den, double *out, int P) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -339,6 +348,18 @@ extern "C" int expenc_lipschitz(const expenc_op *op, int32_t precision, int32_t 
   hipStream_t s = (hipStream_t)stream;
   EX_TRY(enc_prepare(p1, op, eb, s));
   return lipschitz_run(p1, op, eb, n_iter, v0, vec, tmp, dpart, dpart + kRedBlocks, lipschitz_out, s);
+}
+
+extern "C" int expenc_axpby(int64_t n, double a, const float *x, double b, const float *y, float *out,
+                            void *stream) {
+  if (n < 0) return fail(EXPENC_EINVAL, "n must be >= 0");
+  if (n == 0) return EXPENC_OK;
+  if (!x || !y || !out) return fail(EXPENC_EINVAL, "NULL array");
+  k_axpby<<<(unsigned)ceil_div(n, 256), 256, 0, (hipStream_t)stream>>>(
+      n, (float)a, reinterpret_cast<const float2 *>(x), (float)b, reinterpret_cast<const float2 *>(y),
+      reinterpret_cast<float2 *>(out));
+  EX_LAUNCHED("axpby");
+  return EXPENC_OK;
 }
 
 extern "C" int expenc_kernel_timing(int32_t mode, double *out) { return kernel_timing(mode, out); }

@@ -27,6 +27,7 @@
 #include <cmath>
 #include <cstdio>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -36,28 +37,6 @@ namespace expenc {
 
 
 static constexpr double kInv2Pi = 0.15915494309189533576888376337251436;
-
-// Real solid harmonics up to 3rd order at (x, y, z), in the basis order of
-// expenc_sh_basis.
-__device__ inline void sh_eval(double x, double y, double z, double (&v)[16]) {
-  const double x2 = x * x, y2 = y * y, z2 = z * z;
-  v[0] = 1.0;
-  v[1] = x;
-  v[2] = y;
-  v[3] = z;
-  v[4] = x * y;
-  v[5] = y * z;
-  v[6] = 2.0 * z2 - x2 - y2;
-  v[7] = x * z;
-  v[8] = x2 - y2;
-  v[9] = y * (3.0 * x2 - y2);
-  v[10] = x * y * z;
-  v[11] = y * (4.0 * z2 - x2 - y2);
-  v[12] = z * (2.0 * z2 - 3.0 * x2 - 3.0 * y2);
-  v[13] = x * (4.0 * z2 - x2 - y2);
-  v[14] = z * (x2 - y2);
-  v[15] = x * (x2 - 3.0 * y2);
-}
 
 // ---------------------------------------------------------------------------
 // Setup kernels
@@ -81,30 +60,6 @@ __global__ void k_prep_kap(const double *__restrict__ coef, const double *__rest
   kap[i] = v;
 }
 
-// bet for EXPENC_BASIS_SH: the solid harmonics evaluated at the pixel centres.
-__global__ void k_prep_bet_sh(const double *__restrict__ dw0, double *__restrict__ bet, int nx, int ny, int Rp, int L,
-                              int NT, double dx, double dy, double z, const double *__restrict__ z0s) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)Rp * NT) return;
-  const int pz = blockIdx.y;
-  if (dw0) dw0 += (int64_t)pz * nx * ny;
-  bet += (int64_t)pz * Rp * NT;
-  if (z0s) z = z0s[pz];
-  const int r = (int)(i / NT);
-  const int j = (int)(i % NT);
-  double v = 0.0;
-  if (r < nx * ny) {
-    if (j < L) {
-      double b[16];
-      sh_eval((r % nx - 0.5 * nx) * dx, (r / nx - 0.5 * ny) * dy, z, b);
-      v = b[j];
-    } else if (j == L && dw0) {
-      v = dw0[r] * kInv2Pi;
-    }
-  }
-  bet[i] = v;
-}
-
 __global__ void k_prep_bet(const double *__restrict__ basis, const double *__restrict__ dw0,
                            double *__restrict__ bet, int R, int Rp, int L, int NT) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -123,22 +78,25 @@ __global__ void k_prep_bet(const double *__restrict__ basis, const double *__res
   bet[i] = v;
 }
 
-// Z[r][col] = S_c(r) * x_b(r), col = b*C + c; zero for padded pixels/columns.
+// Z[r'][col] = S_c(r) * x_b(r), col = b*C + c, row r' = y*nxq + x of pixel
+// r = y*nx + x (nxq = nx, or nx rounded up to 16 for the solid-harmonic
+// kind's row-padded layout); zero for padded pixels/columns.
 __global__ void k_build_z_f32(const float2 *__restrict__ smaps, const float2 *__restrict__ x,
                               int64_t x_stride, int x_row_stride, int nx, int R, int Rp, int C,
-                              int NC, int NCP, float2 *__restrict__ z, int64_t x_pstride) {
+                              int NC, int NCP, float2 *__restrict__ z, int64_t x_pstride, int nxq) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)Rp * NCP) return;
   const int pz = blockIdx.y;
   smaps += (int64_t)pz * C * R;
   x += pz * x_pstride;
   z += (int64_t)pz * Rp * NCP;
-  int r = (int)(i / NCP);
+  const int rq = (int)(i / NCP);
+  const int yy = rq / nxq, xx = rq % nxq;
+  const int r = yy * nx + xx;
   int col = (int)(i % NCP);
   float2 v = make_float2(0.f, 0.f);
-  if (r < R && col < NC) {
+  if (xx < nx && r < R && col < NC) {
     int b = col / C, c = col % C;
-    int yy = r / nx, xx = r % nx;
     float2 s = smaps[(int64_t)c * R + r];
     float2 u = x[b * x_stride + (int64_t)yy * x_row_stride + xx];
     v = make_float2(s.x * u.x - s.y * u.y, s.x * u.y + s.y * u.x);
@@ -312,6 +270,172 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
   }
 
   adj_epilogue<GW>(part, nullptr, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
+}
+
+// ---------------------------------------------------------------------------
+// FP32 contractions with the solid-harmonic basis in polynomial form.  With
+// z fixed, phi(t, r)/2pi = sum_m P_m(t) mono_m(x, y) + t dw0(r)/2pi, where
+// mono runs over 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3 and P_m(t) =
+// pmono[t][m] (split.hip builds the table): ten FP64 terms per entry
+// instead of the 17 of the general basis, still in FP64 throughout, so the
+// phase keeps the general kernels' accuracy for any field strength.  Pixels
+// are laid out row-padded (r' = y nxq + x, nxq = nx rounded up to 16, as in
+// the split forms).  The contraction is that of k_fwd_f32 / k_adj_f32.
+// ---------------------------------------------------------------------------
+
+// Forward: rows = samples.  Along a 16-pixel tile of one image row the
+// lane's phase is a cubic in the offset k = j - 8 from the tile centre
+// (coefficients from the FP64 row polynomial at the centre), evaluated in
+// FP64, plus t dw0(r)/2pi.
+template <int GW>
+__global__ __launch_bounds__(256) void k_fwd_f32_sh(const double *__restrict__ pmono, const double *__restrict__ dwq,
+                                                    const float2 *__restrict__ zop, float *__restrict__ part,
+                                                    int64_t Tp, int Rp, int NCP, int chunk, int nsplit, int nxq,
+                                                    int nx, int ny, double dx, double dy) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int split, rb;
+  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+  const int pz = blockIdx.z;  // problem
+  pmono += pz * Tp * 12;
+  dwq += (int64_t)pz * Rp;
+  zop += (int64_t)pz * Rp * NCP;
+  part += pz * nsplit * Tp * NCP * 2;
+  double P[10];
+#pragma unroll
+  for (int m = 0; m < 10; ++m) P[m] = pmono[(row0 + lane) * 12 + m];
+  const double tt = pmono[(row0 + lane) * 12 + 10];
+  const double dx2 = dx * dx, dx3 = dx2 * dx;
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+  const int r0 = split * chunk;
+  const int r1 = min(Rp, r0 + chunk);
+  const float2 *zl = zop + (int64_t)half * NCP + g0 * 16 + c16;
+  for (int r = r0; r < r1; r += 16) {
+    const int yi = r / nxq, xi = r % nxq + 8;
+    const double ym = (yi - 0.5 * ny) * dy, xc = (xi - 0.5 * nx) * dx;
+    const double a0 = P[0] + ym * (P[2] + ym * (P[5] + ym * P[9]));
+    const double a1 = P[1] + ym * (P[4] + ym * P[8]);
+    const double a2 = P[3] + ym * P[7];
+    const double a3 = P[6];
+    const double c0 = a0 + xc * (a1 + xc * (a2 + xc * a3));
+    const double d1 = (a1 + xc * (2.0 * a2 + 3.0 * a3 * xc)) * dx;
+    const double d2 = (a2 + 3.0 * a3 * xc) * dx2;
+    const double d3 = a3 * dx3;
+#pragma unroll
+    for (int j = 0; j < 16; j += 2) {
+      const double ka = j - 8, kb = j - 7;
+      const double pa = fma(tt, dwq[r + j], fma(fma(fma(d3, ka, d2), ka, d1), ka, c0));
+      const double pb = fma(tt, dwq[r + j + 1], fma(fma(fma(d3, kb, d2), kb, d1), kb, c0));
+      // centred reduction to [-1/2, 1/2] turns before rounding to FP32
+      const float fa = (float)(pa - __builtin_rint(pa));
+      const float fb = (float)(pb - __builtin_rint(pb));
+      const float ca = __builtin_amdgcn_cosf(fa), sa = __builtin_amdgcn_sinf(fa);
+      const float cb = __builtin_amdgcn_cosf(fb), sb = __builtin_amdgcn_sinf(fb);
+      const auto cc = __builtin_amdgcn_permlane32_swap(__float_as_uint(ca), __float_as_uint(cb), false, false);
+      const auto ss = __builtin_amdgcn_permlane32_swap(__float_as_uint(sa), __float_as_uint(sb), false, false);
+      const float c_lo = __uint_as_float(cc[0]), c_hi = __uint_as_float(cc[1]);
+      const float s_lo = __uint_as_float(ss[0]), s_hi = __uint_as_float(ss[1]);
+#pragma unroll
+      for (int g = 0; g < GW; ++g) {
+        const float2 z = zl[(int64_t)(r + j) * NCP + g * 16];
+        const float b1 = im ? z.y : z.x;
+        const float b2 = im ? z.x : -z.y;
+        acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_lo, b1, acc[0][g], 0, 0, 0);
+        acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_hi, b1, acc[1][g], 0, 0, 0);
+        acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_lo, b2, acc[0][g], 0, 0, 0);
+        acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_hi, b2, acc[1][g], 0, 0, 0);
+      }
+    }
+  }
+  float *dst = part + (int64_t)split * Tp * NCP * 2;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) {
+        const int64_t row = row0 + a * 32 + 8 * (v >> 2) + 4 * half + (v & 3);
+        const int col = (g0 + g) * 16 + c16;
+        dst[(row * NCP + col) * 2 + im] = acc[a][g][v];
+      }
+}
+
+// Adjoint: rows = pixels.  The lane's pixel holds its monomials (FP64); per
+// sample the ten coefficients P_m(t) and t arrive as wave-uniform scalar
+// loads, and the phase is their FP64 dot product.  COMB: coils combined in
+// the epilogue (sq), else per-coil partial sums (its register use, not the
+// loop's, would set the occupancy of the other variant).
+template <int GW, bool COMB>
+__global__ __launch_bounds__(256) void k_adj_f32_sh(const double *__restrict__ pmono, const double *__restrict__ dwq,
+                                                    const float2 *__restrict__ yop, float *__restrict__ part, int Rp,
+                                                    int64_t Tp, int NCP, int chunk, int nsplit, int nxq, int nx,
+                                                    int ny, double dx, double dy, const float2 *__restrict__ sq) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int split, rb;
+  if (!(COMB ? split_tile_rows(Rp / 256, nsplit, &split, &rb) : split_tile(Rp / 256, nsplit, &split, &rb))) return;
+  const int64_t row0 = (int64_t)rb * 256 + wave * 64;
+  const int g0 = blockIdx.y * GW;
+  const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
+  const int pz = blockIdx.z;  // problem
+  pmono += pz * Tp * 12;
+  dwq += (int64_t)pz * Rp;
+  yop += pz * Tp * NCP;
+  const int rq = (int)(row0 + lane);
+  const double x = (rq % nxq - 0.5 * nx) * dx, y = (rq / nxq - 0.5 * ny) * dy;
+  const double x2 = x * x, y2 = y * y;
+  // monomials 1..9 in the order of pmono (x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3), then dw0/2pi
+  const double mo[10] = {x, y, x2, x * y, y2, x2 * x, x2 * y, x * y2, y2 * y, dwq[rq]};
+  f32x16 acc[2][GW];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int g = 0; g < GW; ++g)
+#pragma unroll
+      for (int v = 0; v < 16; ++v) acc[a][g][v] = 0.f;
+  const int64_t t0 = (int64_t)split * chunk;
+  const int64_t t1 = min(Tp, t0 + chunk);
+  const float2 *yl = yop + (int64_t)half * NCP + g0 * 16 + c16;
+#pragma unroll 2
+  for (int64_t t = t0; t < t1; t += 2) {
+    const double *ka = pmono + t * 12;
+    double pa = ka[0], pb = ka[12];
+#pragma unroll
+    for (int m = 0; m < 10; ++m) {
+      pa = fma(ka[1 + m], mo[m], pa);
+      pb = fma(ka[13 + m], mo[m], pb);
+    }
+    // centred reduction to [-1/2, 1/2] turns before rounding to FP32
+    const float fa = (float)(pa - __builtin_rint(pa));
+    const float fb = (float)(pb - __builtin_rint(pb));
+    const float ca = __builtin_amdgcn_cosf(fa), sa = __builtin_amdgcn_sinf(fa);
+    const float cb = __builtin_amdgcn_cosf(fb), sb = __builtin_amdgcn_sinf(fb);
+    const auto cc = __builtin_amdgcn_permlane32_swap(__float_as_uint(ca), __float_as_uint(cb), false, false);
+    const auto ss = __builtin_amdgcn_permlane32_swap(__float_as_uint(sa), __float_as_uint(sb), false, false);
+    const float c_lo = __uint_as_float(cc[0]), c_hi = __uint_as_float(cc[1]);
+    const float s_lo = __uint_as_float(ss[0]), s_hi = __uint_as_float(ss[1]);
+#pragma unroll
+    for (int g = 0; g < GW; ++g) {
+      const float2 yv = yl[t * NCP + g * 16];
+      // conj(E) * Y = Er*[Yr|Yi] + Ei*[Yi|-Yr]
+      const float b1 = im ? yv.y : yv.x;
+      const float b2 = im ? -yv.x : yv.y;
+      acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_lo, b1, acc[0][g], 0, 0, 0);
+      acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(c_hi, b1, acc[1][g], 0, 0, 0);
+      acc[0][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_lo, b2, acc[0][g], 0, 0, 0);
+      acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_hi, b2, acc[1][g], 0, 0, 0);
+    }
+  }
+  adj_epilogue<GW>(part, COMB ? sq : nullptr, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -613,7 +737,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.ny = op->ny;
   q.R = op->nx * op->ny;
   q.sh = op->basis_kind == EXPENC_BASIS_SH;
-  q.nxq = (q.sh && precision != EXPENC_FP32) ? (int32_t)round_up(op->nx, 16) : op->nx;
+  q.nxq = q.sh ? (int32_t)round_up(op->nx, 16) : op->nx;
   q.dx = q.sh ? op->fov_x / op->nx : 0.0;
   q.dy = q.sh ? op->fov_y / op->ny : 0.0;
   q.z0 = q.sh ? op->z0 : 0.0;
@@ -710,6 +834,14 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
   b->zop = a.take<float2>(P * p.Rp * p.NCP);
   b->yop = a.take<float2>(P * p.Tp * p.NCP);
   b->part = a.take<float2>(std::max(enc_part_elems(p), min_part));
+  if (p.sh) {
+    // polynomial phase tables (every precision; dpa: the split adjoint's
+    // increment operand)
+    b->pmono = a.take<double>(P * p.Tp * 12);
+    b->dpa = a.take<float>(P * p.Tp * 16);
+    b->dwq = a.take<double>(P * p.Rp);
+    b->ddw = a.take<float>(P * p.Rp);
+  }
   if (p.prec != EXPENC_FP32) {
     b->zs = a.take<char>(P * p.Rp * (p.NCP / 16) * 256);
     b->ys = a.take<char>(P * p.Tp * (p.NCP / 16) * 256);
@@ -719,12 +851,7 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
       b->amax = a.take<float>(P * 3 * kAmaxBlocks);
       b->wmax = a.take<float>(P * p.nwmax);
     }
-    if (p.sh) {
-      b->pmono = a.take<double>(P * p.Tp * 12);
-      b->dpa = a.take<float>(P * p.Tp * 16);
-      b->dwq = a.take<double>(P * p.Rp);
-      b->ddw = a.take<float>(P * p.Rp);
-    } else {
+    if (!p.sh) {
       b->dbet = a.take<float>(P * p.Rp * p.NT);
       b->dkap = a.take<float>(P * p.Tp * p.NT);
     }
@@ -739,16 +866,13 @@ int enc_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipS
   k_prep_kap<<<grid_p(p.Tp * p.NT, 256, p.P), 256, 0, s>>>(op->coef, op->time, b.kap, p.T, p.Tp, p.L, p.NT);
   EX_LAUNCHED("prep_kap");
   const bool split = p.prec != EXPENC_FP32;
-  if (!(split && p.sh)) {  // the polynomial split kernels do not read bet
-    if (p.sh)
-      k_prep_bet_sh<<<grid_p((int64_t)p.Rp * p.NT, 256, p.P), 256, 0, s>>>(op->dw0, b.bet, p.nx, p.ny, p.Rp, p.L,
-                                                                            p.NT, p.dx, p.dy, p.z0, p.z0s);
-    else
-      k_prep_bet<<<grid_p((int64_t)p.Rp * p.NT, 256, p.P), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L,
-                                                                         p.NT);
+  if (!p.sh) {  // the polynomial (solid-harmonic) kernels do not read bet
+    k_prep_bet<<<grid_p((int64_t)p.Rp * p.NT, 256, p.P), 256, 0, s>>>(op->basis, op->dw0, b.bet, p.R, p.Rp, p.L,
+                                                                       p.NT);
     EX_LAUNCHED("prep_bet");
   }
   if (split) return split_prepare(p, op, b, s);
+  if (p.sh) return sh_prepare(p, op, b, s);
   return EXPENC_OK;
 }
 
@@ -758,7 +882,7 @@ int enc_build_z(const EncPlan &p, const float *smaps, const float2 *x, int64_t x
   if (xsub) return fail(EXPENC_EUNSUPPORTED, "operand difference is only built for split forms");
   k_build_z_f32<<<grid_p((int64_t)p.Rp * p.NCP, 256, p.P), 256, 0, s>>>(
       reinterpret_cast<const float2 *>(smaps), x, x_stride, x_row_stride, p.nx, p.R, p.Rp, p.C, p.NC,
-      p.NCP, b.zop, x_pstride);
+      p.NCP, b.zop, x_pstride, p.nxq);
   EX_LAUNCHED("build_z");
   return EXPENC_OK;
 }
@@ -876,10 +1000,46 @@ static void launch_adj(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
     k_adj_f32<NT, 1><<<grid, 256, 0, s>>>(b.kap, b.bet, b.yop, part, p.Rp, p.Tp, p.NCP, p.adj_chunk, p.adj_split);
 }
 
+static void launch_fwd_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid(split_grid(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
+  float *part = reinterpret_cast<float *>(b.part);
+  if (p.GW == 2)
+    k_fwd_f32_sh<2><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.zop, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk, p.fwd_split,
+                                         p.nxq, p.nx, p.ny, p.dx, p.dy);
+  else
+    k_fwd_f32_sh<1><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.zop, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk, p.fwd_split,
+                                         p.nxq, p.nx, p.ny, p.dx, p.dy);
+}
+
+static void launch_adj_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
+  dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
+  float *part = reinterpret_cast<float *>(b.part);
+  auto go = [&](auto gw, auto comb) {
+    k_adj_f32_sh<decltype(gw)::value, decltype(comb)::value><<<grid, 256, 0, s>>>(
+        b.pmono, b.dwq, b.yop, part, p.Rp, p.Tp, p.NCP, p.adj_chunk, p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy,
+        b.sq);
+  };
+  using T1 = std::integral_constant<int, 1>;
+  using T2 = std::integral_constant<int, 2>;
+  using On = std::true_type;
+  using Off = std::false_type;
+  if (p.GW == 2) {
+    if (p.comb) go(T2{}, On{});
+    else go(T2{}, Off{});
+  } else {
+    if (p.comb) go(T1{}, On{});
+    else go(T1{}, Off{});
+  }
+}
+
 int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s, bool timing) {
   auto launch = [&] {
     if (p.prec != EXPENC_FP32) {
       split_forward_launch(p, b, s);
+      return;
+    }
+    if (p.sh) {
+      launch_fwd_sh(p, b, s);
       return;
     }
     switch (p.NT) {
@@ -899,6 +1059,10 @@ int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   timed(1, s, [&] {
     if (p.prec != EXPENC_FP32) {
       split_adjoint_launch(p, b, s);
+      return;
+    }
+    if (p.sh) {
+      launch_adj_sh(p, b, s);
       return;
     }
     switch (p.NT) {

@@ -17,13 +17,22 @@
 
 namespace expenc {
 
-// xb[l][r] = b_l(r) * w(r)  (b_l from the FP64 phase table bet[r][l])
+// xb[l][r] = b_l(r) * w(r): b_l from the FP64 phase table bet[r][l] (basis
+// given as maps), or, with bet NULL, the solid harmonics at the pixel centre
+// ((x - nx/2) dx, (y - ny/2) dy, z0)
 __global__ void k_basis_weight(const double *__restrict__ bet, int NT, int L, const float2 *__restrict__ w, int R,
-                               float2 *__restrict__ xb) {
+                               float2 *__restrict__ xb, int nx, int ny, double dx, double dy, double z0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)L * R) return;
   const int l = (int)(i / R), r = (int)(i % R);
-  const float b = (float)bet[(int64_t)r * NT + l];
+  float b;
+  if (bet) {
+    b = (float)bet[(int64_t)r * NT + l];
+  } else {
+    double v[16];
+    sh_eval((r % nx - 0.5 * nx) * dx, (r / nx - 0.5 * ny) * dy, z0, v);
+    b = (float)v[l];
+  }
   const float2 v = w[r];
   xb[i] = make_float2(b * v.x, b * v.y);
 }
@@ -115,7 +124,8 @@ extern "C" int expenc_field_grad(const expenc_op *op, int32_t precision, const f
   const int C = p1.C;
   EX_TRY(enc_prepare(pL, op, G.eb, s));
   if (grad_coef && L > 0) {
-    k_basis_weight<<<(unsigned)ceil_div((int64_t)L * R, 256), 256, 0, s>>>(G.eb.bet, pL.NT, L, w2, R, G.xb);
+    k_basis_weight<<<(unsigned)ceil_div((int64_t)L * R, 256), 256, 0, s>>>(pL.sh ? nullptr : G.eb.bet, pL.NT, L, w2,
+                                                                          R, G.xb, p1.nx, p1.ny, pL.dx, pL.dy, pL.z0);
     EX_LAUNCHED("basis weighting");
     EX_TRY(enc_build_z(pL, op->smaps, G.xb, R, p1.nx, G.eb, s));
     EX_TRY(enc_forward_partials(pL, G.eb, s));

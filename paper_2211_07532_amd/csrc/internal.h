@@ -203,6 +203,28 @@ __device__ inline void adj_epilogue(float *part, const float2 *sq, int Rp, int N
       }
 }
 
+// Real solid harmonics up to 3rd order at (x, y, z), in the basis order of
+// expenc_sh_basis.
+__device__ inline void sh_eval(double x, double y, double z, double (&v)[16]) {
+  const double x2 = x * x, y2 = y * y, z2 = z * z;
+  v[0] = 1.0;
+  v[1] = x;
+  v[2] = y;
+  v[3] = z;
+  v[4] = x * y;
+  v[5] = y * z;
+  v[6] = 2.0 * z2 - x2 - y2;
+  v[7] = x * z;
+  v[8] = x2 - y2;
+  v[9] = y * (3.0 * x2 - y2);
+  v[10] = x * y * z;
+  v[11] = y * (4.0 * z2 - x2 - y2);
+  v[12] = z * (2.0 * z2 - 3.0 * x2 - 3.0 * y2);
+  v[13] = x * (4.0 * z2 - x2 - y2);
+  v[14] = z * (x2 - y2);
+  v[15] = x * (x2 - 3.0 * y2);
+}
+
 struct EncPlan {
   int32_t nx = 0, ny = 0, R = 0, Rp = 0;  // pixels, padded to a multiple of 256
   int64_t T = 0, Tp = 0;                  // samples, padded to a multiple of 256
@@ -329,6 +351,9 @@ int enc_forward_residual(const EncPlan &p, const EncBuffers &b, const float2 *y_
 
 // Split-precision kernels (split.hip).
 int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s);
+// Polynomial phase tables of the solid-harmonic kind (pmono, dwq, ddw; dpa
+// for the split forms) from kap (split.hip).
+int sh_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s);
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // the polynomial (solid-harmonic) split adjoint, built in split_adj.hip

@@ -308,13 +308,22 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__
     const float d1 = (float)((a1 + xc * (2.0 * a2 + 3.0 * a3 * xc)) * dx);
     const float d2 = (float)((a2 + 3.0 * a3 * xc) * dx2);
     const float d3 = (float)(a3 * dx3);
+    // p(k) = an + d1 k + d2 k^2 + d3 k^3 at k = j - 8: the even part
+    // an + d2 k^2 and the odd factor d1 + d3 k^2 are shared by k and -k
+    float ph[16];
+    ph[8] = an;
+#pragma unroll
+    for (int m = 1; m < 8; ++m) {
+      const float k = (float)m, k2 = (float)(m * m);
+      const float ev = fmaf(d2, k2, an), od = fmaf(d3, k2, d1);
+      ph[8 + m] = fmaf(od, k, ev);
+      ph[8 - m] = fmaf(od, -k, ev);
+    }
+    ph[0] = fmaf(fmaf(fmaf(d3, -8.f, d2), -8.f, d1), -8.f, an);
     float c[16], sn[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-      const float k = (float)(j - 8);
-      float ph = fmaf(fmaf(fmaf(d3, k, d2), k, d1), k, an);
-      ph = fmaf(tf, ddw[r + j], ph);
-      const float f = __builtin_amdgcn_fractf(ph);
+      const float f = __builtin_amdgcn_fractf(fmaf(tf, ddw[r + j], ph[j]));
       c[j] = __builtin_amdgcn_cosf(f);
       sn[j] = __builtin_amdgcn_sinf(f);
     }
@@ -729,6 +738,21 @@ __global__ void k_prep_sq(const float2 *__restrict__ smaps, int nx, int ny, int 
   sq[(int64_t)pz * Rp * NCP + i] = v;
 }
 
+int sh_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
+  auto gp = [&](int64_t n) { return dim3((unsigned)ceil_div(n, 256), (unsigned)p.P); };
+  k_prep_pmono<<<gp(p.Tp), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), p.z0s, b.pmono);
+  EX_LAUNCHED("monomial coefficients");
+  if (p.prec != EXPENC_FP32) {
+    k_prep_dpa<<<gp(p.Tp / 32 * 64), 256, 0, s>>>(b.pmono, p.Tp, b.dpa);
+    EX_LAUNCHED("increment table (samples)");
+  }
+  k_prep_dwq<<<gp(p.Rp), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);
+  EX_LAUNCHED("off-resonance layout");
+  k_tile_diff<<<gp(p.Rp), 256, 0, s>>>(b.dwq, b.ddw, p.Rp, 1);
+  EX_LAUNCHED("tile differences (pixels)");
+  return EXPENC_OK;
+}
+
 int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipStream_t s) {
   auto gp = [&](int64_t n) { return dim3((unsigned)ceil_div(n, 256), (unsigned)p.P); };
   if (p.scaled) {
@@ -744,17 +768,7 @@ int split_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hi
                                                           p.nxq, p.Rp, p.C, p.NCP, b.sq);
     EX_LAUNCHED("coil table");
   }
-  if (p.sh) {
-    k_prep_pmono<<<gp(p.Tp), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), p.z0s, b.pmono);
-    EX_LAUNCHED("monomial coefficients");
-    k_prep_dpa<<<gp(p.Tp / 32 * 64), 256, 0, s>>>(b.pmono, p.Tp, b.dpa);
-    EX_LAUNCHED("increment table (samples)");
-    k_prep_dwq<<<gp(p.Rp), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);
-    EX_LAUNCHED("off-resonance layout");
-    k_tile_diff<<<gp(p.Rp), 256, 0, s>>>(b.dwq, b.ddw, p.Rp, 1);
-    EX_LAUNCHED("tile differences (pixels)");
-    return EXPENC_OK;
-  }
+  if (p.sh) return sh_prepare(p, op, b, s);
   k_tile_diff<<<gp((int64_t)p.Rp * p.NT), 256, 0, s>>>(b.bet, b.dbet, p.Rp, p.NT);
   EX_LAUNCHED("tile differences (pixels)");
   k_tile_diff<<<gp(p.Tp * p.NT), 256, 0, s>>>(b.kap, b.dkap, p.Tp, p.NT);

@@ -221,6 +221,19 @@ def wavelet_prox(v: torch.Tensor, levels: int, tau: torch.Tensor, x_prev: torch.
     return x.reshape(v.shape), z.reshape(v.shape), w.reshape(v.shape)
 
 
+def axpby(a: float, x: torch.Tensor, b: float, y: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """a x + b y for complex64 tensors of one shape (a, b real), in the library."""
+    _need(x, torch.complex64, "x", None)
+    _need(y, torch.complex64, "y", x.device)
+    if x.shape != y.shape:
+        raise ValueError("x and y must have one shape")
+    o = out if out is not None else torch.empty_like(x)
+    _need(o, torch.complex64, "out", x.device)
+    check(_b.lib().expenc_axpby(x.numel(), float(a), _ptr(x), float(b), _ptr(y), _ptr(o), _stream(x.device)),
+          "expenc_axpby")
+    return o
+
+
 @dataclasses.dataclass
 class FistaResult:
     x: torch.Tensor                      # [B][ny][nx]

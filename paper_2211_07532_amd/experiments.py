@@ -56,9 +56,10 @@ class Setting:
     snr: float
 
 
-def workload(accel: float, snr: float, seed: int = 11):
+def workload(accel: float, snr: float, seed: int = 11, n: int = 148):
+    """The simulation's workload: n x n (148 by default; smaller grids keep the
+    FOV, so the pixels grow), T = 3 n^2 / R samples at 1 us."""
     synth = _synth()
-    n = 148
     t = int(round(3 * n * n / accel))
     return synth.Workload(f"sim-R{accel:g}-snr{snr:g}", n, 0.222, 32, t, 1e-6, accel, N_2ND, 150.0, snr, 100,
                           "db4", 3, seed)
@@ -85,10 +86,10 @@ def _t(a, dtype=None):
     return torch.from_numpy(a).cuda()
 
 
-def simulate(accel: float, snr: float, ho_frac: float, seed: int = 11):
+def simulate(accel: float, snr: float, ho_frac: float, seed: int = 11, n: int = 148):
     """(x_true [R], y [T][32], pieces) with y = A_exp x_noisy on the GPU."""
     synth = _synth()
-    w = workload(accel, snr, seed)
+    w = workload(accel, snr, seed, n)
     x_true = synth.phantom(w)
     x_noisy = x_true + synth.image_noise(w, x_true)
     smaps = synth.coil_maps(w)

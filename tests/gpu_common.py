@@ -61,21 +61,36 @@ class Case:
         return torch.from_numpy(np.ascontiguousarray(a).astype(np.complex64)).to(self.dev)
 
 
-def emulated_split_errors(case, x, g, ts, rs, kind):
+def emulated_split_errors(case, x, g, ts, rs, kind, y_norm=None, x_norm=None):
     """Relative errors that the round-to-nearest-even emulation of the split
     arithmetic (oracle.splitemu: phase tile rounded to FP32, both operands
-    split hi/lo, three products) shows for the forward on sample rows ts
-    (input image x [R]) and for the adjoint on pixels rs (input data g [T][C],
-    coil combination in FP64), against exact FP64 sums."""
+    split hi/lo, three products) shows for the forward (input image x [R])
+    and the adjoint (input data g [T][C], coil combination in FP64), against
+    exact FP64 sums, evaluated on the sample rows ts and pixels rs.  With all
+    rows / pixels these are the whole outputs' errors.  With a uniform random
+    subset, pass the exact norms of the whole outputs (y_norm, x_norm): the
+    error energy of the subset, scaled by T/len(ts) (R/len(rs)), then
+    estimates the whole output's (the error is spread evenly over the
+    outputs while their energy is not)."""
     from oracle import encoding, splitemu
     coef, time, basis, dw0, smaps = case.coef, case.time, case.basis_np, case.dw0, case.smaps
     z = (smaps * x[None, :]).T                                    # [R][C]
     ph = encoding.phase(coef[ts], time[ts], basis, dw0)           # [len(ts)][R]
     e32 = np.exp(1j * ph).astype(np.complex64).astype(np.complex128)
-    fwd = rel(splitemu.split_cmatmul(e32, c64(z), kind), np.exp(1j * ph) @ z)
+    y_ex = np.exp(1j * ph) @ z
+    d_y = np.linalg.norm(splitemu.split_cmatmul(e32, c64(z), kind) - y_ex)
     ph = encoding.phase(coef, time, basis[:, rs], None if dw0 is None else dw0[rs])  # [T][len(rs)]
     e32 = np.exp(1j * ph).astype(np.complex64).astype(np.complex128)
     u = splitemu.split_cmatmul(np.conj(e32).T, g, kind)           # [len(rs)][C]
     x_emu = np.sum(np.conj(smaps[:, rs]).T * u, axis=1)
     x_ex = np.sum(np.conj(smaps[:, rs]).T * (np.conj(np.exp(1j * ph)).T @ g), axis=1)
-    return fwd, rel(x_emu, x_ex)
+    d_x = np.linalg.norm(x_emu - x_ex)
+    if y_norm is None:
+        fwd = d_y / np.linalg.norm(y_ex)
+    else:
+        fwd = d_y * np.sqrt(len(time) / len(ts)) / y_norm
+    if x_norm is None:
+        adj = d_x / np.linalg.norm(x_ex)
+    else:
+        adj = d_x * np.sqrt(smaps.shape[1] / len(rs)) / x_norm
+    return float(fwd), float(adj)

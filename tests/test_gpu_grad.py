@@ -177,3 +177,31 @@ def test_unrolled_fista_gradients_and_checkpointing():
     assert l0 == l1
     assert np.array_equal(gx0.view(np.uint32), gx1.view(np.uint32))
     assert np.array_equal(gc0, gc1) and np.array_equal(gd0, gd1)
+
+
+GOLDEN_DIFF = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "diff_unrolled.npz")
+
+
+def test_unrolled_gradients_match_fp64_oracle_at_diff_config():
+    """The differentiation workload at full size (128 x 128, 16 coils,
+    T = 12000, 16 field terms + dB0, 10 unrolled FISTA iterations, db4 J = 3):
+    the loss and the checkpointed gradients with respect to x_in, k_l(t) and
+    dB0 against the FP64 oracle's reverse pass (tests/golden/diff_unrolled.npz,
+    written by tests/golden/make_golden.py diff with the same L and lambda):
+    loss within 1e-4, each gradient within 1e-3 (relative l2)."""
+    import os
+    if not os.path.exists(GOLDEN_DIFF):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py diff")
+    ee, ag = _ee()
+    g = np.load(GOLDEN_DIFF)
+    w = synth.DIFF
+    case = Case(w)
+    L, lam = float(g["lipschitz"]), float(g["lam"])
+    print(f"[case] unrolled gradients vs oracle, {w.name}: L {L:.4e} lambda {lam:.4e}", flush=True)
+    loss, gx, gc, gd = _gpu_unrolled(ag, w, case, L, lam, ckpt=True)
+    errs = {"x": rel(gx, g["grad_x"]), "coef": rel(gc, g["grad_coef"]), "dw0": rel(gd, g["grad_dw0"])}
+    e_loss = abs(loss - float(g["loss"])) / float(g["loss"])
+    print(f"  loss {loss:.6e} vs {float(g['loss']):.6e} ({e_loss:.2e}); gradient errors "
+          + " ".join(f"{k} {v:.2e}" for k, v in errs.items()), flush=True)
+    assert e_loss <= 1e-4
+    assert max(errs.values()) <= 1e-3
