@@ -54,6 +54,16 @@ TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "fp16": ["split_adj.hip", "split_dev.h", "internal.h", "../build.py"]}
 
 
+def applications(prec, n_iter, n_power=N_POWER):
+    """Operator applications of one solve as fista_solve issues them: n_power
+    power steps (A and A^H each), the Rayleigh quotient (FP32: one A, whose
+    residual operand gives ||A v||^2; split forms: A and A^H once more), one
+    A^H for the lambda rule (whose result is also the first iteration's
+    gradient at z_0 = 0) and A and A^H in each of the other n_iter - 1
+    iterations."""
+    return 2 * n_power + (1 if prec == "fp32" else 2) + 1 + 2 * (n_iter - 1)
+
+
 def source_sha(form):
     import hashlib
     h = hashlib.sha256()
@@ -63,11 +73,16 @@ def source_sha(form):
     return h.hexdigest()
 
 
-def traffic_for(form, adj_split):
+def traffic_for(form, adj_split, key="bytes"):
     e = TRAFFIC.get(form)
     if not e or e["sha"] != source_sha(form) or e["adj_split"] != adj_split:
         return None
-    return e["bytes"]
+    return e.get(key)
+
+
+# VALU issue time of a launch: each wave64 vector instruction occupies its
+# SIMD for 4 cycles (16 lanes per cycle); 1024 SIMDs at 2.4 GHz
+VALU_ISSUE_PER_S = 1024 * 2.4e9 / 4
 
 
 def parse():
@@ -320,7 +335,7 @@ def run_batch(args, prec, ee, torch):
     tb, xb = timed(batched)
     tl, xl = timed(looped)
     diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xb, xl))
-    apps = 2 * K + (2 * N_POWER + 1) + 1
+    apps = applications(prec, K)
     cmac = sum(w.nsamples * w.npix * w.ncoils for w in ws) * apps
     sizes = {}
     for w in ws:
@@ -362,7 +377,6 @@ def main():
     v0 = torch.from_numpy(synth.power_start(w.npix, 7).astype(np.complex64)).to(dev)
     golden = np.load(GOLDEN)["x_hat"] if os.path.exists(GOLDEN) else None
     cmac = w.nsamples * w.npix * w.ncoils
-    apps = 2 * w.n_iter + (2 * N_POWER + 1) + 1
     lib = B.lib()
     forms = [args.precision] if args.precision != "all" else list(FORMS)
     out = {}
@@ -424,8 +438,10 @@ def main():
         t_mfma = FORM_FLOP_PER_CMAC[prec] * cmac / (PEAK_TFLOPS[prec] * 1e12) * 1e3
         t_sincos = 2.0 * w.nsamples * w.npix / SINCOS_PEAK * 1e3
         adj_split = tuning["adj_split"] if tuning else None
+        apps = applications(prec, w.n_iter)
         out[prec] = {
             "gcmac_per_s": round(apps * cmac / dt / 1e9, 2), "ms_per_step": round(dt * 1e3, 3),
+            "operator_applications_per_step": apps,
             "fista_iter_per_s": round(it_s, 2), "nrmse_vs_fp64": None if nrmse is None else float(f"{nrmse:.3e}"),
             "kernel_ms": {"forward_contraction": round(fwd_ms, 4), "adjoint_contraction": round(adj_ms, 4)},
             "launch_shape": tuning,
@@ -437,6 +453,24 @@ def main():
                               "kernel_ms": round(dom_ms, 4), "frac": round(max(t_mfma, t_sincos) / dom_ms, 4),
                               "frac_forward": round(max(t_mfma, t_sincos) / fwd_ms, 4)},
         }
+        # the bound with the vector unit included: VALU issue time from the
+        # rocprofv3 SQ_INSTS_VALU count of the same kernel source and shape
+        # (null when the source has changed since), and the sum of matrix and
+        # vector time that these kernels measure close to (no co-issue)
+        vi_adj, vi_fwd = traffic_for(prec, adj_split, "valu_instr"), traffic_for(prec, adj_split, "fwd_valu_instr")
+        if vi_adj and vi_fwd:
+            tv_a, tv_f = vi_adj / VALU_ISSUE_PER_S * 1e3, vi_fwd / VALU_ISSUE_PER_S * 1e3
+            # the split adjoint also forms its phase on the matrix cores: a
+            # rank-12 FP32 product per entry
+            t_phase = 0.0 if prec == "fp32" else 12 * w.nsamples * w.npix / (PEAK_TFLOPS["fp32"] / 2 * 1e12) * 1e3
+            out[prec]["roofline_valu"] = {
+                "valu_instr_per_entry_adjoint": round(vi_adj * 64 / (w.nsamples * w.npix), 2),
+                "valu_instr_per_entry_forward": round(vi_fwd * 64 / (w.nsamples * w.npix), 2),
+                "t_valu_ms_adjoint": round(tv_a, 4), "t_valu_ms_forward": round(tv_f, 4),
+                "frac": round(max(t_mfma + t_phase, t_sincos, tv_a) / adj_ms, 4),
+                "frac_forward": round(max(t_mfma, t_sincos, tv_f) / fwd_ms, 4),
+                "frac_serial": round((t_mfma + t_phase + tv_a) / adj_ms, 4),
+                "frac_serial_forward": round((t_mfma + tv_f) / fwd_ms, 4)}
 
     # headline: the fastest form whose solve meets NRMSE <= 1e-4 against the FP64 oracle
     ok = [p for p in forms if out[p]["nrmse_vs_fp64"] is None or out[p]["nrmse_vs_fp64"] <= 1e-4]
@@ -457,11 +491,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "image": f"{w.n}x{w.n}", "coils": w.ncoils, "samples": w.nsamples,
                    "field_terms": w.nbasis, "fista_iters": w.n_iter, "wavelet": f"{w.wavelet} J={w.levels}",
-                   "power_iters": N_POWER, "operator_applications_per_step": apps},
+                   "power_iters": N_POWER, "operator_applications_per_step": h["operator_applications_per_step"]},
         "fista_iter_per_s": h["fista_iter_per_s"],
         "nrmse_vs_fp64": h["nrmse_vs_fp64"],
         "roofline": h["roofline"],
         "roofline_form": h["roofline_form"],
+        "roofline_valu": h.get("roofline_valu"),
         "forms": out,
     }
     if "fp32" in out and head != "fp32":
