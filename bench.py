@@ -316,6 +316,9 @@ def run_batch(args, prec, ee, torch):
     def batched():
         return ee.fista_batched(ys, ops, K, J, wav, **kw)
 
+    def grouped():
+        return ee.fista_batched(ys, ops, K, J, wav, launch="grouped", **kw)
+
     def looped():
         out = []
         for y, op in zip(ys, ops):
@@ -333,7 +336,16 @@ def run_batch(args, prec, ee, torch):
         return (time.perf_counter() - t0) / args.batch_steps, r
 
     tb, xb = timed(batched)
+    grp = {}
+    if prec != "fp32":
+        print("[bench] batch, grouped persistent contractions", file=sys.stderr, flush=True)
+        tg, xg = timed(grouped)
+        grp = {"recon_per_s_grouped": round(len(ws) / tg, 3), "s_per_batch_grouped": round(tg, 3),
+               "grouped_equals_forked": all(bool(torch.equal(a, b)) for a, b in zip(xg, xb))}
+    print("[bench] batch, looped single solves", file=sys.stderr, flush=True)
     tl, xl = timed(looped)
+    if grp:
+        grp["speedup_grouped_vs_looped"] = round(tl / grp["s_per_batch_grouped"], 3)
     diff = max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b)) for a, b in zip(xb, xl))
     apps = applications(prec, K)
     cmac = sum(w.nsamples * w.npix * w.ncoils for w in ws) * apps
@@ -345,7 +357,7 @@ def run_batch(args, prec, ee, torch):
             "recon_per_s_batched": round(len(ws) / tb, 3), "recon_per_s_looped": round(len(ws) / tl, 3),
             "speedup_vs_looped": round(tl / tb, 3), "gcmac_per_s_batched": round(cmac / tb / 1e9, 2),
             "s_per_batch": round(tb, 3), "s_per_loop": round(tl, 3),
-            "batched_vs_looped_max_rel_diff": float(f"{diff:.3e}"), "tuning": tuning}
+            "batched_vs_looped_max_rel_diff": float(f"{diff:.3e}"), **grp, "tuning": tuning}
 
 
 FORMS = {"fp32": "f32", "bf16": "bf16-split", "fp16": "f16-split"}

@@ -259,7 +259,8 @@ typedef struct expenc_fista_opts {
   int32_t refine_every;    /* split forms: exact FP32 gradient every m iterations (0 = 25 fp16, 17 bf16) */
   int32_t n_power;         /* power steps when lipschitz <= 0 (in the solve's
                               precision when batch == 1, else FP32)                  */
-  int32_t reserved;
+  int32_t batch_launch;    /* fista_solve_batched: EXPENC_BATCH_FORKED or
+                              EXPENC_BATCH_GROUPED (ignored by fista_solve)         */
   double lipschitz;        /* > 0: L to use; <= 0: estimate from power_v0            */
   double lambda;           /* >= 0: lambda to use; < 0: lambda_factor * max|A^H y|
                               (A^H y in FP32; it also gives the first iteration's
@@ -304,6 +305,15 @@ int fista_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
  * at least max_i R_i complex values and problem i starts from its first
  * R_i.  The inputs are copied into the workspace at the start of the call.
  */
+/* Launch pattern of a batched solve (expenc_fista_opts.batch_launch).
+ * FORKED: every group runs its own iteration loop (one launch per pass for
+ * the group's problems) on a stream forked inside the captured graph.
+ * GROUPED: the groups advance in lock step and each split-difference
+ * iteration's forward and adjoint contractions run as one persistent launch
+ * whose workgroups walk the (problem, row block, split) tiles of every group
+ * (split precisions with EXPENC_BASIS_SH and one column width for every
+ * group, else EXPENC_EUNSUPPORTED).  Both give bit-identical results. */
+enum { EXPENC_BATCH_FORKED = 0, EXPENC_BATCH_GROUPED = 1 };
 size_t fista_batched_workspace_size(int32_t nprob, const expenc_op *ops, int32_t batch,
                                     const expenc_fista_opts *opts);
 int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t batch, const float *const *y,

@@ -18,6 +18,8 @@ EXPENC_EHIP = -3
 EXPENC_EUNSUPPORTED = -4
 EXPENC_ENONFINITE = -5
 EXPENC_EDIVERGED = -6
+EXPENC_BATCH_FORKED = 0
+EXPENC_BATCH_GROUPED = 1
 
 FP32, BF16_SPLIT, FP16_SPLIT = 0, 1, 2
 HAAR, DB4 = 0, 1
@@ -46,7 +48,7 @@ class FistaOpts(ctypes.Structure):
         ("wavelet", ctypes.c_int32), ("levels", ctypes.c_int32),
         ("nx_pad", ctypes.c_int32), ("ny_pad", ctypes.c_int32),
         ("ista", ctypes.c_int32), ("refine_every", ctypes.c_int32),
-        ("n_power", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("n_power", ctypes.c_int32), ("batch_launch", ctypes.c_int32),
         ("lipschitz", ctypes.c_double), ("lambda_", ctypes.c_double),
         ("lambda_factor", ctypes.c_double),
         ("power_v0", _vp), ("objective", _vp), ("scalars", _vp),

@@ -136,7 +136,7 @@ __global__ __launch_bounds__(256) void k_fwd_f32(const double *__restrict__ kap,
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  if (!split_tile(blockIdx.x, (int)(Tp / 256), nsplit, &split, &rb)) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!split_tile(Rp / 256, nsplit, &split, &rb)) return;
+  if (!split_tile(blockIdx.x, Rp / 256, nsplit, &split, &rb)) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(256) void k_adj_f32(const double *__restrict__ kap,
     }
   }
 
-  adj_epilogue<GW>(part, nullptr, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
+  adj_epilogue<GW>(part, nullptr, Rp, NCP, nsplit, split, pz, blockIdx.y, gridDim.y, row0, g0, lane, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -295,7 +295,7 @@ __global__ __launch_bounds__(256) void k_fwd_f32_sh(const double *__restrict__ p
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  if (!split_tile(blockIdx.x, (int)(Tp / 256), nsplit, &split, &rb)) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(256) void k_adj_f32_sh(const double *__restrict__ p
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!(COMB ? split_tile_rows(Rp / 256, nsplit, &split, &rb) : split_tile(Rp / 256, nsplit, &split, &rb))) return;
+  if (!(COMB ? split_tile_rows(blockIdx.x, Rp / 256, nsplit, &split, &rb) : split_tile(blockIdx.x, Rp / 256, nsplit, &split, &rb))) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
@@ -435,7 +435,7 @@ __global__ __launch_bounds__(256) void k_adj_f32_sh(const double *__restrict__ p
       acc[1][g] = __builtin_amdgcn_mfma_f32_32x32x2f32(s_hi, b2, acc[1][g], 0, 0, 0);
     }
   }
-  adj_epilogue<GW>(part, COMB ? sq : nullptr, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
+  adj_epilogue<GW>(part, COMB ? sq : nullptr, Rp, NCP, nsplit, split, pz, blockIdx.y, gridDim.y, row0, g0, lane, acc);
 }
 
 // ---------------------------------------------------------------------------

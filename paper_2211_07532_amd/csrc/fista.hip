@@ -360,6 +360,8 @@ size_t fista_bytes(const expenc_op *op, int32_t batch, int32_t precision, int32_
 static int check_fista_opts(const expenc_fista_opts *o, int *eff_refine) {
   if (!o) return fail(EXPENC_EINVAL, "options are NULL");
   if (o->n_iter < 0) return fail(EXPENC_EINVAL, "n_iter must be >= 0");
+  if (o->batch_launch != EXPENC_BATCH_FORKED && o->batch_launch != EXPENC_BATCH_GROUPED)
+    return fail(EXPENC_EINVAL, "unknown batch_launch %d", o->batch_launch);
   if (o->wavelet != EXPENC_HAAR && o->wavelet != EXPENC_DB4) return fail(EXPENC_EINVAL, "unknown wavelet %d", o->wavelet);
   if (o->lipschitz <= 0 && (!o->power_v0 || o->n_power < 1))
     return fail(EXPENC_EINVAL, "lipschitz <= 0 requires power_v0 and n_power >= 1");
@@ -432,6 +434,25 @@ struct FistaGroup {
   }
 
   int body(hipStream_t cs) {
+    for (int k = 0; k < opts->n_iter; ++k) EX_TRY(iteration(cs, k, kStageAll));
+    return EXPENC_OK;
+  }
+
+  // Whether iteration k applies the split operators to z - z_ref (the
+  // iterations whose contractions a grouped batched launch takes over).
+  bool split_difference(int k) const {
+    const int K = opts->n_iter;
+    return opts->precision != EXPENC_FP32 && !(k == 0 && gref_at_zero) && !(k % refine == 0 || k == K - 1);
+  }
+
+  // Stages of one iteration: kStagePre ends before the forward contraction,
+  // kStageMid lies between the two contractions, kStagePost follows the
+  // adjoint.  The contractions themselves run only with kStageAll; a caller
+  // that runs the stages one at a time issues them in between (only for the
+  // iterations of split_difference; the others run with kStageAll).
+  static constexpr int kStagePre = 1, kStageMid = 2, kStagePost = 4, kStageAll = 7;
+
+  int iteration(hipStream_t cs, int k, int stage) {
     const EncPlan &p = L.p, &pf = L.pf;
     const int P = L.P, B = L.B;
     const int nxp = L.nxp, nyp = L.nyp;
@@ -443,7 +464,8 @@ struct FistaGroup {
     const bool with_obj = opts->objective != nullptr;
     const double *alpha = L.sc + P;
     const int K = opts->n_iter;
-    for (int k = 0; k < K; ++k) {
+    const bool whole = stage == kStageAll;
+    {
       float2 *xk = (k % 2 == 0) ? L.x1 : L.x0;
       float2 *xprev = (k % 2 == 0) ? L.x0 : L.x1;
       // z_0 = 0, so the first residual A z - y is -y without a forward product
@@ -454,6 +476,7 @@ struct FistaGroup {
         return enc_forward_residual(q, L.eb, y, cs);
       };
       const int pnx = padded ? nxp : 0, pny = padded ? nyp : 0;
+      if (!split_difference(k) && !whole) return fail(EXPENC_EINVAL, "iteration %d runs whole", k);
       if (k == 0 && gref_at_zero) {
         // v = z_0 - (2/L) A^H y from the prologue's FP32 -A^H y (also the
         // split forms' first anchor: z_ref = z_0)
@@ -475,12 +498,14 @@ struct FistaGroup {
         EX_TRY(copy_f2(L.z, L.zref, all, cs));
       } else {
         // split operators on the difference: g = g_ref + A~^H A~ (z - z_ref)
-        EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs, L.zref, pimg));
-        EX_TRY(enc_forward_partials(p, L.eb, cs));
-        EX_TRY(enc_forward_residual(p, L.eb, nullptr, cs));
-        EX_TRY(enc_adjoint_partials(p, L.eb, cs));
-        EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, L.gref, pimg, pnx, pny));
+        if (stage & kStagePre) EX_TRY(enc_build_z(p, op->smaps, L.z, img, nxp, L.eb, cs, L.zref, pimg));
+        if (whole) EX_TRY(enc_forward_partials(p, L.eb, cs));
+        if (stage & kStageMid) EX_TRY(enc_forward_residual(p, L.eb, nullptr, cs));
+        if (whole) EX_TRY(enc_adjoint_partials(p, L.eb, cs));
+        if (stage & kStagePost)
+          EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, L.gref, pimg, pnx, pny));
       }
+      if (!(stage & kStagePost)) return EXPENC_OK;
       // x_k = W^H S_tau(W v), z = x_k + beta_k (x_k - x_{k-1}); v and x_k serve
       // as the transform's ping-pong buffers
       EX_TRY(dwt2_prox(f, nxp, nyp, opts->levels, P * B, L.v, L.w, xk, xprev, L.z, beta[k], L.tau(),
@@ -858,8 +883,9 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
       EX_HIP(hipGetDevice(&dev));
       EX_TRY(fork_resources(dev, NG, &fs, &ev));
     }
-    EX_TRY(run_graph(key, s, [&](hipStream_t cs) -> int {
-      if (NG == 1) return bp.groups[0].body(cs);
+    // Group g's work fn(g, stream) on a stream forked from cs, joined back.
+    auto forked = [&](hipStream_t cs, auto &&fn) -> int {
+      if (NG == 1) return fn(0, cs);
       int rc = EXPENC_OK;
       if (hipEventRecord(ev[NG], cs) != hipSuccess) return fail(EXPENC_EHIP, "fork record");
       for (int g = 0; g < NG && rc == EXPENC_OK; ++g) {
@@ -868,13 +894,48 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
           rc = fail(EXPENC_EHIP, "fork");
           break;
         }
-        rc = bp.groups[g].body(gs);
+        rc = fn(g, gs);
         // always join a forked stream back, also after an error, so that a
         // capture can end cleanly
         if (hipEventRecord(ev[g], gs) != hipSuccess || hipStreamWaitEvent(cs, ev[g], 0) != hipSuccess)
           rc = rc ? rc : fail(EXPENC_EHIP, "join");
       }
       return rc;
+    };
+    bool grouped = opts->batch_launch == EXPENC_BATCH_GROUPED && opts->precision != EXPENC_FP32;
+    for (int g = 0; g < NG && grouped; ++g) grouped = split_groupable(bp.groups[0].L.p, bp.groups[g].L.p);
+    if (opts->batch_launch == EXPENC_BATCH_GROUPED && !grouped)
+      return fail(EXPENC_EUNSUPPORTED, "grouped batch launches need split precision and the solid-harmonic kind "
+                                       "with one column width for every group");
+    std::vector<const EncPlan *> plans(NG);
+    std::vector<const EncBuffers *> bufs(NG);
+    for (int g = 0; g < NG; ++g) {
+      plans[g] = &bp.groups[g].L.p;
+      bufs[g] = &bp.groups[g].L.eb;
+    }
+    EX_TRY(run_graph(key, s, [&](hipStream_t cs) -> int {
+      if (!grouped) return forked(cs, [&](int g, hipStream_t gs) { return bp.groups[g].body(gs); });
+      // lock-step groups: each iteration's two split contractions run as one
+      // persistent launch over every group's tiles
+      constexpr int kAll = FistaGroup::kStageAll;
+      for (int k = 0; k < opts->n_iter; ++k) {
+        if (!bp.groups[0].split_difference(k)) {
+          EX_TRY(forked(cs, [&](int g, hipStream_t gs) { return bp.groups[g].iteration(gs, k, kAll); }));
+          continue;
+        }
+        EX_TRY(forked(cs, [&](int g, hipStream_t gs) {
+          return bp.groups[g].iteration(gs, k, FistaGroup::kStagePre);
+        }));
+        EX_TRY(split_forward_grouped(plans.data(), bufs.data(), NG, cs));
+        EX_TRY(forked(cs, [&](int g, hipStream_t gs) {
+          return bp.groups[g].iteration(gs, k, FistaGroup::kStageMid);
+        }));
+        EX_TRY(split_adjoint_grouped(plans.data(), bufs.data(), NG, cs));
+        EX_TRY(forked(cs, [&](int g, hipStream_t gs) {
+          return bp.groups[g].iteration(gs, k, FistaGroup::kStagePost);
+        }));
+      }
+      return EXPENC_OK;
     }));
   }
   for (int g = 0; g < NG; ++g) {

@@ -78,10 +78,11 @@ __device__ inline void flag_nonfinite(unsigned *status, float2 v) {
 // contiguous range of reduction chunks and the slice of the streamed operand
 // it needs stays in its L2.  The grid has 8Q >= N workgroups; the at most 7
 // surplus ones return at once.
-__device__ inline bool split_tile(int nrb, int nsplit, int *split, int *rb) {
+// (b: the workgroup's index in the launch's x dimension; a persistent
+// launch passes the index of the tile it is working on.)
+__device__ inline bool split_tile(int b, int nrb, int nsplit, int *split, int *rb) {
   const int n = nrb * nsplit;
   const int q = (n + 7) >> 3;
-  const int b = blockIdx.x;
   const int bp = (b & 7) * q + (b >> 3);
   if (bp >= n) return false;
   *split = bp / nrb;
@@ -95,11 +96,11 @@ __device__ inline bool split_tile(int nrb, int nsplit, int *split, int *rb) {
 // split-major.  Its slice of the row table then stays in its L2 across the
 // splits, and the workgroups in flight on an XCD still share the chunks of a
 // few splits of the streamed operand.  Same grid as split_tile.
-__device__ inline bool split_tile_rows(int nrb, int nsplit, int *split, int *rb) {
+__device__ inline bool split_tile_rows(int b, int nrb, int nsplit, int *split, int *rb) {
   const int n = nrb * nsplit;
   const int q = (n + 7) >> 3;
-  const int j = blockIdx.x >> 3;
-  const int lo = (blockIdx.x & 7) * q, hi = min(n, lo + q);
+  const int j = b >> 3;
+  const int lo = (b & 7) * q, hi = min(n, lo + q);
   if (lo + j >= hi) return false;
   // the range holds row block r of split s iff lo <= r * nsplit + s < hi
   int cum = 0;
@@ -179,13 +180,13 @@ __device__ inline void store_combined(float *__restrict__ dst, const float2 *__r
 
 // End of an adjoint contraction workgroup: with sq (single image, split
 // forms) the coil-combined partial image of (problem pz, split, column block
-// y) goes to part as float2 [P][nsplit][NGY][Rp]; without, the per-coil
-// accumulators go to [P][nsplit][Rp][NCP] complex.
+// gy of ngy) goes to part as float2 [P][nsplit][NGY][Rp]; without, the
+// per-coil accumulators go to [P][nsplit][Rp][NCP] complex.
 template <int GW>
 __device__ inline void adj_epilogue(float *part, const float2 *sq, int Rp, int NCP, int nsplit, int split, int pz,
-                                    int64_t row0, int g0, int lane, f32x16 (&acc)[2][GW]) {
+                                    int gy, int ngy, int64_t row0, int g0, int lane, f32x16 (&acc)[2][GW]) {
   if (sq) {
-    const int64_t slice = ((int64_t)pz * nsplit + split) * gridDim.y + blockIdx.y;
+    const int64_t slice = ((int64_t)pz * nsplit + split) * ngy + gy;
     store_combined<GW>(part + slice * Rp * 2, sq + (int64_t)pz * Rp * NCP, NCP, row0, g0, lane, acc);
     return;
   }
@@ -358,6 +359,29 @@ void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // the polynomial (solid-harmonic) split adjoint, built in split_adj.hip
 void split_adjoint_sh_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
+
+// Persistent launch of one split contraction over several problem groups
+// (plans of one shape class: solid-harmonic kind, same number format and
+// column width GW).  Virtual workgroup t runs workgroup (x, y, z) of group
+// g's own grid, where off[g] <= t < off[g+1] and t - off[g] numbers that grid
+// x fastest; resident workgroups walk t with the launch's stride.
+constexpr int kMaxGrouped = 8;
+template <class Args>
+struct GroupedLaunch {
+  Args a[kMaxGrouped];
+  int64_t off[kMaxGrouped + 1];
+  int gx[kMaxGrouped], gy[kMaxGrouped];
+  int ng;
+};
+// Whether two plans can share a grouped launch.
+bool split_groupable(const EncPlan &a, const EncPlan &b);
+// The forward (adjoint) contractions of n plans, in launches of at most
+// kMaxGrouped groups each.
+int split_forward_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s);
+int split_adjoint_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s);
+// Grid of a persistent launch: the workgroups resident at once (occupancy x
+// compute units), at most the virtual ones, a multiple of 8.
+int persistent_grid(const void *kernel, int64_t nvirtual, unsigned *grid);
 int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
                   int32_t x_row_stride, const EncBuffers &b, hipStream_t s, int64_t x_pstride);
 int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, const float2 *y_meas,

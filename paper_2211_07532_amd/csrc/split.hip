@@ -105,15 +105,17 @@ __device__ inline void phase_tile16(const double (&pv)[NT], const float (&pf)[NT
   pack_tile16<BF>(c, sn, A);
 }
 
-// Slot of this wave in the per-problem maxima array of a forward launch.
-__device__ inline int wave_slot() { return (int)((blockIdx.y * gridDim.x + blockIdx.x) * 4 + (threadIdx.x >> 6)); }
+// Slot of this wave in the per-problem maxima array of a forward launch
+// (workgroup bx, by of a grid gx wide).
+__device__ inline int wave_slot(int bx, int by, int gx) { return (by * gx + bx) * 4 + (threadIdx.x >> 6); }
+__device__ inline int wave_slot() { return wave_slot(blockIdx.x, blockIdx.y, gridDim.x); }
 
 // Writes a wave's forward partial sums; with wmax (scaled form) also the
 // wave's max |value| into its slot (a bound for the residual operand), per
 // wave and without a workgroup barrier.
 template <int GW>
 __device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0, int lane, f32x16 (&acc)[2][GW],
-                                      float *wmax) {
+                                      float *wmax, int slot) {
   const int half = lane >> 5, c16 = lane & 15, im = (lane >> 4) & 1;
   float m = 0.f;
 #pragma unroll
@@ -130,7 +132,7 @@ __device__ inline void store_partials(float *dst, int64_t row0, int NCP, int g0,
   if (wmax) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if (lane == 0) wmax[wave_slot()] = m;
+    if (lane == 0) wmax[slot] = m;
   }
 }
 
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(256) void k_fwd_split(const double *__restrict__ ka
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) return;
+  if (!split_tile(blockIdx.x, (int)(Tp / 256), nsplit, &split, &rb)) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
@@ -180,7 +182,7 @@ __global__ __launch_bounds__(256) void k_fwd_split(const double *__restrict__ ka
       acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
     }
   }
-  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc, nullptr);
+  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc, nullptr, 0);
 }
 
 // Adjoint, split form: rows = pixels, reduction over samples (16 per step).
@@ -193,7 +195,7 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (!(sq ? split_tile_rows(Rp / 256, nsplit, &split, &rb) : split_tile(Rp / 256, nsplit, &split, &rb))) return;
+  if (!(sq ? split_tile_rows(blockIdx.x, Rp / 256, nsplit, &split, &rb) : split_tile(blockIdx.x, Rp / 256, nsplit, &split, &rb))) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
   const int g0 = blockIdx.y * GW;
   const int NGP = NCP / 16;
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
       acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
     }
   }
-  adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
+  adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, blockIdx.y, gridDim.y, row0, g0, lane, acc);
 }
 
 
@@ -258,24 +260,42 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
 // are packed in that order, so no exchange between lanes is needed.
 // ---------------------------------------------------------------------------
 
+// Arguments of one problem group's forward launch.
+struct FwdShArgs {
+  const double *pmono, *dwq;
+  const float *ddw;
+  const u32x4 *zs;
+  float *part, *wmax;
+  int64_t Tp;
+  int Rp, NCP, chunk, nsplit, nxq, nx, ny;
+  double dx, dy;
+};
+
+// One workgroup of the forward (workgroup bx, by, bz of a gx x gy x P grid).
 template <int GW, bool BF>
-__global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__ pmono, const double *__restrict__ dwq,
-                                                      const float *__restrict__ ddw, const u32x4 *__restrict__ zs,
-                                                      float *__restrict__ part, int64_t Tp, int Rp, int NCP, int chunk,
-                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy,
-                                                      float *__restrict__ wmax) {
+__device__ inline void fwd_split_sh_body(const FwdShArgs &a, int bx, int by, int bz, int gx, int gy) {
+  const double *__restrict__ pmono = a.pmono;
+  const double *__restrict__ dwq = a.dwq;
+  const float *__restrict__ ddw = a.ddw;
+  const u32x4 *__restrict__ zs = a.zs;
+  float *__restrict__ part = a.part;
+  float *__restrict__ wmax = a.wmax;
+  const int64_t Tp = a.Tp;
+  const int Rp = a.Rp, NCP = a.NCP, chunk = a.chunk, nsplit = a.nsplit, nxq = a.nxq, nx = a.nx, ny = a.ny;
+  const double dx = a.dx, dy = a.dy;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int split, rb;
-  if (wmax) wmax += (int64_t)blockIdx.z * gridDim.y * gridDim.x * 4;
-  if (!split_tile((int)(Tp / 256), nsplit, &split, &rb)) {
-    if (wmax && lane == 0) wmax[wave_slot()] = 0.f;
+  if (wmax) wmax += (int64_t)bz * gy * gx * 4;
+  const int slot = wave_slot(bx, by, gx);
+  if (!split_tile(bx, (int)(Tp / 256), nsplit, &split, &rb)) {
+    if (wmax && lane == 0) wmax[slot] = 0.f;
     return;
   }
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
-  const int g0 = blockIdx.y * GW;
+  const int g0 = by * GW;
   const int NGP = NCP / 16;
-  const int pz = blockIdx.z;  // problem
+  const int pz = bz;  // problem
   pmono += pz * Tp * 12;
   dwq += (int64_t)pz * Rp;
   ddw += (int64_t)pz * Rp;
@@ -337,7 +357,30 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(const double *__restrict__
       acc[1][g] = step6<BF>(A[1], b, acc[1][g]);
     }
   }
-  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc, wmax);
+  store_partials<GW>(part + (int64_t)split * Tp * NCP * 2, row0, NCP, g0, lane, acc, wmax, slot);
+}
+
+template <int GW, bool BF>
+__global__ __launch_bounds__(256) void k_fwd_split_sh(FwdShArgs a) {
+  fwd_split_sh_body<GW, BF>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
+}
+
+// Persistent form for several problem groups of one shape class (same GW
+// and number format): the virtual workgroups of every group's grid are
+// numbered group by group (x fastest), and each resident workgroup walks
+// them with the launch's stride.  Every group's x extent is a multiple of
+// eight, as is the stride, so a virtual workgroup runs on the XCD its index
+// assigns it and split_tile's L2 locality holds.
+template <int GW, bool BF>
+__global__ __launch_bounds__(256) void k_fwd_split_sh_grouped(GroupedLaunch<FwdShArgs> G) {
+  for (int64_t t = blockIdx.x; t < G.off[G.ng]; t += gridDim.x) {
+    int g = 0;
+    while (g + 1 < G.ng && t >= G.off[g + 1]) ++g;
+    const int64_t l = t - G.off[g];
+    const int gx = G.gx[g], gy = G.gy[g];
+    const int64_t q = l / gx;
+    fwd_split_sh_body<GW, BF>(G.a[g], (int)(l - q * gx), (int)(q % gy), (int)(q / gy), gx, gy);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -825,18 +868,68 @@ static void adj_split_nt(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   }
 }
 
+static FwdShArgs fwd_sh_args(const EncPlan &p, const EncBuffers &b) {
+  return FwdShArgs{b.pmono, b.dwq, b.ddw, reinterpret_cast<const u32x4 *>(b.zs), reinterpret_cast<float *>(b.part),
+                   p.scaled ? b.wmax : nullptr, p.Tp, p.Rp, p.NCP, p.fwd_chunk, p.fwd_split, p.nxq, p.nx, p.ny,
+                   p.dx, p.dy};
+}
+
 template <bool BF>
 static void fwd_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   dim3 grid(split_grid(p.Tp / 256 * p.fwd_split), (unsigned)p.NGY, (unsigned)p.P);
-  float *part = reinterpret_cast<float *>(b.part);
-  const u32x4 *zs = reinterpret_cast<const u32x4 *>(b.zs);
-  float *wmax = p.scaled ? b.wmax : nullptr;
+  const FwdShArgs a = fwd_sh_args(p, b);
   if (p.GW == 2)
-    k_fwd_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.ddw, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
-                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy, wmax);
+    k_fwd_split_sh<2, BF><<<grid, 256, 0, s>>>(a);
   else
-    k_fwd_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dwq, b.ddw, zs, part, p.Tp, p.Rp, p.NCP, p.fwd_chunk,
-                                               p.fwd_split, p.nxq, p.nx, p.ny, p.dx, p.dy, wmax);
+    k_fwd_split_sh<1, BF><<<grid, 256, 0, s>>>(a);
+}
+
+bool split_groupable(const EncPlan &a, const EncPlan &b) {
+  return a.sh && b.sh && a.prec == b.prec && a.prec != EXPENC_FP32 && a.GW == b.GW && a.comb == b.comb &&
+         a.scaled == b.scaled;
+}
+
+int persistent_grid(const void *kernel, int64_t nvirtual, unsigned *grid) {
+  int dev = 0, ncu = 0, per_cu = 0;
+  EX_HIP(hipGetDevice(&dev));
+  EX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  EX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
+  const int64_t resident = (int64_t)std::max(per_cu, 1) * ncu;
+  *grid = (unsigned)((std::min(resident, nvirtual) + 7) / 8 * 8);
+  return EXPENC_OK;
+}
+
+template <int GW, bool BF>
+static int fwd_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
+  const void *kern = reinterpret_cast<const void *>(&k_fwd_split_sh_grouped<GW, BF>);
+  GroupedLaunch<FwdShArgs> G{};
+  G.ng = n;
+  G.off[0] = 0;
+  for (int g = 0; g < n; ++g) {
+    G.a[g] = fwd_sh_args(*p[g], *b[g]);
+    G.gx[g] = (int)split_grid(p[g]->Tp / 256 * p[g]->fwd_split);
+    G.gy[g] = p[g]->NGY;
+    G.off[g + 1] = G.off[g] + (int64_t)G.gx[g] * G.gy[g] * p[g]->P;
+  }
+  unsigned grid = 0;
+  EX_TRY(persistent_grid(kern, G.off[n], &grid));
+  k_fwd_split_sh_grouped<GW, BF><<<grid, 256, 0, s>>>(G);
+  EX_LAUNCHED("grouped forward contraction");
+  return EXPENC_OK;
+}
+
+int split_forward_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
+  for (int i = 0; i < n; i += kMaxGrouped) {
+    const int m = std::min(kMaxGrouped, n - i);
+    for (int g = i; g < i + m; ++g)
+      if (!split_groupable(*p[i], *p[g])) return fail(EXPENC_EINVAL, "plans of a grouped launch differ in shape");
+    const bool bf = p[i]->prec == EXPENC_BF16_SPLIT;
+    int rc;
+    if (p[i]->GW == 2) rc = bf ? fwd_grouped<2, true>(p + i, b + i, m, s) : fwd_grouped<2, false>(p + i, b + i, m, s);
+    else rc = bf ? fwd_grouped<1, true>(p + i, b + i, m, s) : fwd_grouped<1, false>(p + i, b + i, m, s);
+    EX_TRY(rc);
+  }
+  return EXPENC_OK;
 }
 
 void split_forward_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {

@@ -7,21 +7,41 @@
 
 namespace expenc {
 
+// Arguments of one problem group's adjoint launch.
+struct AdjShArgs {
+  const double *pmono;
+  const float *dpa;
+  const double *dwq;
+  const u32x4 *ys;
+  float *part;
+  const float2 *sq;
+  int64_t Tp;
+  int Rp, NCP, chunk, nsplit, nxq, nx, ny;
+  double dx, dy;
+};
+
+// One workgroup of the adjoint (workgroup bx, by, bz of a grid with gy
+// column groups).
 template <int GW, bool BF>
-__global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__ pmono, const float *__restrict__ dpa,
-                                                      const double *__restrict__ dwq, const u32x4 *__restrict__ ys,
-                                                      float *__restrict__ part, int Rp, int64_t Tp, int NCP, int chunk,
-                                                      int nsplit, int nxq, int nx, int ny, double dx, double dy,
-                                                      const float2 *__restrict__ sq) {
+__device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int bz, int gy) {
+  const double *__restrict__ pmono = a.pmono;
+  const float *__restrict__ dpa = a.dpa;
+  const double *__restrict__ dwq = a.dwq;
+  const u32x4 *__restrict__ ys = a.ys;
+  float *__restrict__ part = a.part;
+  const float2 *__restrict__ sq = a.sq;
+  const int64_t Tp = a.Tp;
+  const int Rp = a.Rp, NCP = a.NCP, chunk = a.chunk, nsplit = a.nsplit, nxq = a.nxq, nx = a.nx, ny = a.ny;
+  const double dx = a.dx, dy = a.dy;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int hl = lane >> 5, jl = lane & 31;
   int split, rb;
-  if (!(sq ? split_tile_rows(Rp / 256, nsplit, &split, &rb) : split_tile(Rp / 256, nsplit, &split, &rb))) return;
+  if (!(sq ? split_tile_rows(bx, Rp / 256, nsplit, &split, &rb) : split_tile(bx, Rp / 256, nsplit, &split, &rb))) return;
   const int64_t row0 = (int64_t)rb * 256 + wave * 64;
-  const int g0 = blockIdx.y * GW;
+  const int g0 = by * GW;
   const int NGP = NCP / 16;
-  const int pz = blockIdx.z;  // problem
+  const int pz = bz;  // problem
   pmono += pz * Tp * 12;
   dpa += pz * Tp * 16;
   dwq += (int64_t)pz * Rp;
@@ -114,21 +134,75 @@ __global__ __launch_bounds__(256) void k_adj_split_sh(const double *__restrict__
       }
     }
   }
-  adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, row0, g0, lane, acc);
+  adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, by, gy, row0, g0, lane, acc);
+}
+
+template <int GW, bool BF>
+__global__ __launch_bounds__(256) void k_adj_split_sh(AdjShArgs a) {
+  adj_split_sh_body<GW, BF>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
+}
+
+// Persistent form over several problem groups (the forward's grouped kernel
+// in split.hip describes the numbering and why the XCD mapping holds).
+template <int GW, bool BF>
+__global__ __launch_bounds__(256) void k_adj_split_sh_grouped(GroupedLaunch<AdjShArgs> G) {
+  for (int64_t t = blockIdx.x; t < G.off[G.ng]; t += gridDim.x) {
+    int g = 0;
+    while (g + 1 < G.ng && t >= G.off[g + 1]) ++g;
+    const int64_t l = t - G.off[g];
+    const int gx = G.gx[g], gy = G.gy[g];
+    const int64_t q = l / gx;
+    adj_split_sh_body<GW, BF>(G.a[g], (int)(l - q * gx), (int)(q % gy), (int)(q / gy), gy);
+  }
+}
+
+static AdjShArgs adj_sh_args(const EncPlan &p, const EncBuffers &b) {
+  return AdjShArgs{b.pmono, b.dpa, b.dwq, reinterpret_cast<const u32x4 *>(b.ys), reinterpret_cast<float *>(b.part),
+                   p.comb ? b.sq : nullptr, p.Tp, p.Rp, p.NCP, p.adj_chunk, p.adj_split, p.nxq, p.nx, p.ny, p.dx,
+                   p.dy};
 }
 
 template <bool BF>
 static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
-  float *part = reinterpret_cast<float *>(b.part);
-  const u32x4 *ys = reinterpret_cast<const u32x4 *>(b.ys);
-  const float2 *sm = p.comb ? b.sq : nullptr;
+  const AdjShArgs a = adj_sh_args(p, b);
   if (p.GW == 2)
-    k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy, sm);
+    k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(a);
   else
-    k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(b.pmono, b.dpa, b.dwq, ys, part, p.Rp, p.Tp, p.NCP, p.adj_chunk,
-                                               p.adj_split, p.nxq, p.nx, p.ny, p.dx, p.dy, sm);
+    k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(a);
+}
+
+template <int GW, bool BF>
+static int adj_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
+  const void *kern = reinterpret_cast<const void *>(&k_adj_split_sh_grouped<GW, BF>);
+  GroupedLaunch<AdjShArgs> G{};
+  G.ng = n;
+  G.off[0] = 0;
+  for (int g = 0; g < n; ++g) {
+    G.a[g] = adj_sh_args(*p[g], *b[g]);
+    G.gx[g] = (int)split_grid((int64_t)p[g]->Rp / 256 * p[g]->adj_split);
+    G.gy[g] = p[g]->NGY;
+    G.off[g + 1] = G.off[g] + (int64_t)G.gx[g] * G.gy[g] * p[g]->P;
+  }
+  unsigned grid = 0;
+  EX_TRY(persistent_grid(kern, G.off[n], &grid));
+  k_adj_split_sh_grouped<GW, BF><<<grid, 256, 0, s>>>(G);
+  EX_LAUNCHED("grouped adjoint contraction");
+  return EXPENC_OK;
+}
+
+int split_adjoint_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
+  for (int i = 0; i < n; i += kMaxGrouped) {
+    const int m = std::min(kMaxGrouped, n - i);
+    for (int g = i; g < i + m; ++g)
+      if (!split_groupable(*p[i], *p[g])) return fail(EXPENC_EINVAL, "plans of a grouped launch differ in shape");
+    const bool bf = p[i]->prec == EXPENC_BF16_SPLIT;
+    int rc;
+    if (p[i]->GW == 2) rc = bf ? adj_grouped<2, true>(p + i, b + i, m, s) : adj_grouped<2, false>(p + i, b + i, m, s);
+    else rc = bf ? adj_grouped<1, true>(p + i, b + i, m, s) : adj_grouped<1, false>(p + i, b + i, m, s);
+    EX_TRY(rc);
+  }
+  return EXPENC_OK;
 }
 
 void split_adjoint_sh_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {

@@ -428,12 +428,18 @@ _batch_ws = {}
 def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: int, levels: int, wavelet="db4",
                   precision="fp32", lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3,
                   power_v0=None, n_power: int = 30, ista: bool = False, refine_every: int = 0,
-                  check_status: bool = False):
+                  check_status: bool = False, launch: str = "forked"):
     """Independent FISTA solves of problems (ys[i], ops[i]) in one call (see
     fista_solve_batched in include/expenc.h).  Every ys[i] is [T_i][C_i] (or
     [B][T_i][C_i] with one B for all).  Returns the list of x_i.  With
     check_status the call waits for the solves and raises ExpencError if any
-    iterate turned non-finite (otherwise it returns without waiting)."""
+    iterate turned non-finite (otherwise it returns without waiting).
+    launch: "forked" (each group's own launches on forked streams) or
+    "grouped" (lock-step groups sharing one persistent launch per split
+    contraction; split precisions, solid-harmonic operators)."""
+    launches = {"forked": _b.EXPENC_BATCH_FORKED, "grouped": _b.EXPENC_BATCH_GROUPED}
+    if launch not in launches:
+        raise ValueError(f"launch must be one of {sorted(launches)}")
     if len(ys) != len(ops) or not ops:
         raise ValueError("need one y per operator")
     dev = ops[0].device
@@ -448,7 +454,7 @@ def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: i
     if lipschitz <= 0 and power_v0 is None:
         raise ValueError("lipschitz <= 0 needs power_v0 (the seeded start vector)")
     opts = _b.FistaOpts(n_iter, _prec(precision), _wav(wavelet), levels, 0, 0, int(ista), refine_every,
-                        n_power, 0, float(lipschitz), float(lam), float(lambda_factor),
+                        n_power, launches[launch], float(lipschitz), float(lam), float(lambda_factor),
                         None if power_v0 is None else _need(power_v0, torch.complex64, "power_v0", dev).data_ptr(),
                         None, None)
     n = len(ops)

@@ -197,3 +197,58 @@ def test_full_size_twelve_per_launch_keeps_single_accuracy():
     e = max(solve.nrmse(x.cpu().numpy().reshape(-1), g["x_hat"]) for x in xs)
     print(f"  12 per launch: worst NRMSE {e:.2e} (single {e_single:.2e})", flush=True)
     assert e <= max(2.0 * e_single, 2e-5)
+
+
+def _many_groups(n_groups, n_iter, levels=2):
+    # one problem per size class, so every problem is a group of its own
+    out = []
+    for k in range(n_groups):
+        n = 16 + 4 * k
+        t = int(round(3 * n * n / 4.0))
+        out.append(synth.Workload(f"grp-{k}", n, 0.222, 6, t, 2e-6, 4.0, 16, 100.0, 15.0, n_iter, "db4",
+                                  levels, 700 + k, z0=0.002 * (k % 3 - 1)))
+    return out
+
+
+@pytest.mark.parametrize("prec,n_groups", [("fp16", 3), ("bf16", 3), ("fp16", 10)])
+def test_grouped_launch_is_bitwise_equal_to_forked(prec, n_groups):
+    """The persistent grouped contractions (every group's tiles in one launch
+    per pass, groups in lock step) against each group's own launches on
+    forked streams: the same tiles with the same arithmetic, so the results
+    are bit-identical.  30 iterations cover the first gradient from the
+    lambda rule, split-difference iterations and FP32 anchors; 10 groups take
+    two grouped launches per pass (at most 8 groups each)."""
+    ee = _ee()
+    ws = _many_groups(n_groups, 30) if n_groups > 3 else _mixed_workloads(n_per=2, n_iter=30)
+    cases = [Case(w, sh=True) for w in ws]
+    ys = [c.to_dev(c64(_oracle_op(c).A(c.x_noisy))) for c in cases]
+    v0 = cases[0].to_dev(c64(synth.power_start(max(w.npix for w in ws), 17)))
+    kw = dict(precision=prec, lipschitz=0.0, power_v0=v0, n_power=20, lam=-1.0, lambda_factor=1e-3,
+              check_status=True)
+    print(f"[case] grouped vs forked {prec}: {len(ws)} problems, sizes {sorted({w.n for w in ws})}", flush=True)
+    xf = ee.fista_batched(ys, [c.op for c in cases], 30, 2, "db4", launch="forked", **kw)
+    xg = ee.fista_batched(ys, [c.op for c in cases], 30, 2, "db4", launch="grouped", **kw)
+    for k, (a, b) in enumerate(zip(xf, xg)):
+        same = np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+        if not same:
+            print(f"  problem {k}: grouped vs forked {rel(b.cpu().numpy(), a.cpu().numpy()):.2e}", flush=True)
+        assert same
+    # the replayed graph of the grouped form gives the same result again
+    xg2 = ee.fista_batched(ys, [c.op for c in cases], 30, 2, "db4", launch="grouped", **kw)
+    for a, b in zip(xg, xg2):
+        assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
+
+
+def test_grouped_launch_rejects_unsupported_forms():
+    from paper_2211_07532_amd import _binding as b
+    ee = _ee()
+    ws = _mixed_workloads(n_per=1, n_iter=4)
+    for prec, sh in (("fp32", True), ("fp16", False)):
+        cases = [Case(w, sh=sh) for w in ws]
+        ys = [c.to_dev(c64(_oracle_op(c).A(c.x_noisy))) for c in cases]
+        with pytest.raises(b.ExpencError) as ei:
+            ee.fista_batched(ys, [c.op for c in cases], 4, 2, "db4", precision=prec, lipschitz=1e4, lam=1e-3,
+                             launch="grouped")
+        assert ei.value.status == b.EXPENC_EUNSUPPORTED
+    with pytest.raises(ValueError):
+        ee.fista_batched(ys, [c.op for c in cases], 4, 2, "db4", lipschitz=1e4, lam=1e-3, launch="queued")
