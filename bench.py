@@ -42,16 +42,19 @@ N_POWER = 20
 # 256 MiB copy.  Valid only for the kernel source and launch shape they were
 # taken on: `sha` is the SHA-256 of the files the kernel is built from.
 TRAFFIC = {
-    "fp32": {"kernel": "k_adj_f32<17, 2>", "adj_split": 47, "bytes": 406555149,
-             "sha": "fe71e959be039acb51007d73d4435f9a4807ac211b33e3545f44f9cd54bc3760"},
-    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89591036,
-             "sha": "8cde22e9aa231bc5ad02759c51c0115c93d4a9b09f1c4490342b1bb2497c6283"},
-    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89583460,
-             "sha": "8cde22e9aa231bc5ad02759c51c0115c93d4a9b09f1c4490342b1bb2497c6283"},
+    "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290755072,
+             "valu_instr": 158732000, "fwd_valu_instr": 121229000,
+             "sha": "da62a89def6365626997cafbcdf8b0ae8fd2dd7e4f8d764017959163f9ac33f6"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89606349,
+             "valu_instr": 93196400, "fwd_valu_instr": 106418000,
+             "sha": "591c5e1804153d61bf75bad7854f80b9a35a09f1090319df0c2fda1c3cc5bb63"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89587302,
+             "valu_instr": 74911900, "fwd_valu_instr": 87461900,
+             "sha": "591c5e1804153d61bf75bad7854f80b9a35a09f1090319df0c2fda1c3cc5bb63"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
-                   "bf16": ["split_adj.hip", "split_dev.h", "internal.h", "../build.py"],
-                   "fp16": ["split_adj.hip", "split_dev.h", "internal.h", "../build.py"]}
+                   "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],
+                   "fp16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"]}
 
 
 def applications(prec, n_iter, n_power=N_POWER):
