@@ -132,10 +132,10 @@ __global__ __launch_bounds__(256) void k_dwt_rows(const float2 *src, float2 *dst
       if (j >= mx) j -= mx;
       if (j >= mx) j %= mx;
       const float2 v = line[j];
-      ax += f.h[k] * v.x;
-      ay += f.h[k] * v.y;
-      dx += f.g[k] * v.x;
-      dy += f.g[k] * v.y;
+      ax = fma(f.h[k], (double)v.x, ax);
+      ay = fma(f.h[k], (double)v.y, ay);
+      dx = fma(f.g[k], (double)v.x, dx);
+      dy = fma(f.g[k], (double)v.y, dy);
     }
     d[m] = make_float2((float)ax, (float)ay);
     d[half + m] = make_float2((float)dx, (float)dy);
@@ -162,8 +162,8 @@ __global__ __launch_bounds__(256) void k_idwt_rows(const float2 *src, float2 *ds
       if (q < 0) q += mx;
       const int i = q >> 1;
       const float2 a = line[i], d = line[half + i];
-      vx += f.h[k] * a.x + f.g[k] * d.x;
-      vy += f.h[k] * a.y + f.g[k] * d.y;
+      vx = fma(f.g[k], (double)d.x, fma(f.h[k], (double)a.x, vx));
+      vy = fma(f.g[k], (double)d.y, fma(f.h[k], (double)a.y, vy));
     }
     const float2 v = make_float2((float)vx, (float)vy);
     dst[base + m] = v;
@@ -202,10 +202,10 @@ __global__ __launch_bounds__(256) void k_dwt_cols(float2 *__restrict__ w, int nx
         int j = 2 * m + k;
         if (j >= my) j %= my;
         const float2 v = strip[j * 16 + cx];
-        ax += f.h[k] * v.x;
-        ay += f.h[k] * v.y;
-        dx += f.g[k] * v.x;
-        dy += f.g[k] * v.y;
+        ax = fma(f.h[k], (double)v.x, ax);
+        ay = fma(f.h[k], (double)v.y, ay);
+        dx = fma(f.g[k], (double)v.x, dx);
+        dy = fma(f.g[k], (double)v.y, dy);
       }
       float2 a = make_float2((float)ax, (float)ay), dd = make_float2((float)dx, (float)dy);
       if (tau) {
@@ -254,8 +254,8 @@ __global__ __launch_bounds__(256) void k_idwt_cols(float2 *__restrict__ w, int n
         if (q < 0) q += my;
         const int i = q >> 1;
         const float2 a = strip[i * 16 + cx], d = strip[(half + i) * 16 + cx];
-        vx += f.h[k] * a.x + f.g[k] * d.x;
-        vy += f.h[k] * a.y + f.g[k] * d.y;
+        vx = fma(f.g[k], (double)d.x, fma(f.h[k], (double)a.x, vx));
+        vy = fma(f.g[k], (double)d.y, fma(f.h[k], (double)a.y, vy));
       }
       img[(int64_t)m * nx + x0 + cx] = make_float2((float)vx, (float)vy);
     }
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(256) void k_idwt_cols(float2 *__restrict__ w, int n
 
 constexpr int kTapsMax = 8;
 constexpr int kFwdTX = 16, kFwdTY = 8;  // analysis tile: coefficient positions per band
-constexpr int kInvT = 16;               // synthesis tile: output pixels per side
+constexpr int kInvTX = 32, kInvTY = 16;  // synthesis tile: output pixels (x, y)
 
 // i mod n for i in [-n, 2n) with two compares; other i (a level narrower
 // than a tile's footprint) take the general remainder.
@@ -287,6 +287,10 @@ __device__ inline int wrap(int i, int n) {
   }
   return i;
 }
+
+__device__ inline double2 widen(float2 v) { return make_double2(v.x, v.y); }
+// FP32 rounding of an intermediate pass result, kept in FP64 form
+__device__ inline double2 round32(double x, double y) { return make_double2((float)x, (float)y); }
 
 // Analysis of one level: in (mx x my, row stride istride, image pitch
 // ipitch) -> LL to ll (hx x hy, row stride lstride, pitch lpitch) and the
@@ -321,10 +325,10 @@ __global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ i
 #pragma unroll
     for (int k = 0; k < TAPS; ++k) {
       const float2 v = sin_[r][2 * x + k];
-      ax += f.h[k] * v.x;
-      ay += f.h[k] * v.y;
-      dx += f.g[k] * v.x;
-      dy += f.g[k] * v.y;
+      ax = fma(f.h[k], (double)v.x, ax);
+      ay = fma(f.h[k], (double)v.y, ay);
+      dx = fma(f.g[k], (double)v.x, dx);
+      dy = fma(f.g[k], (double)v.y, dy);
     }
     slo[r][x] = make_float2((float)ax, (float)ay);
     shi[r][x] = make_float2((float)dx, (float)dy);
@@ -339,10 +343,10 @@ __global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ i
 #pragma unroll
     for (int k = 0; k < TAPS; ++k) {
       const float2 v = part ? shi[2 * y + k][x] : slo[2 * y + k][x];
-      ax += f.h[k] * v.x;
-      ay += f.h[k] * v.y;
-      dx += f.g[k] * v.x;
-      dy += f.g[k] * v.y;
+      ax = fma(f.h[k], (double)v.x, ax);
+      ay = fma(f.h[k], (double)v.y, ay);
+      dx = fma(f.g[k], (double)v.x, dx);
+      dy = fma(f.g[k], (double)v.y, dy);
     }
     float2 a = make_float2((float)ax, (float)ay), dd = make_float2((float)dx, (float)dy);
     if (tau) {
@@ -376,65 +380,77 @@ __global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ i
 // stride lstride, pitch lpitch) and the detail bands from w's level block
 // (row stride nx, pitch wpitch) -> out (mx x my, row stride ostride, pitch
 // opitch); with zout, also zout = out + beta (out - xprev) (out's layout).
-// A 16 x 16 output tile needs 8 + TAPS/2 coefficient rows and columns of
-// each half, from i0 = m0/2 - TAPS/2 + 1 (periodic).
-// Block: 256 threads; grid (ceil(mx/16), ceil(my/16), images).
+// Output pixels 2i and 2i + 1 (along either axis) are sums over the same
+// TAPS/2 coefficients i - TAPS/2 + 1 .. i of each half, with the even and
+// the odd taps respectively, so one thread forms both members of such a
+// pair: a 32 x 16 output tile needs 16 + TAPS/2 - 1 coefficient columns
+// and 8 + TAPS/2 - 1 coefficient rows of each half, staged in FP64.
+// Block: 256 threads (16 rows x 16 pairs in the row pass); grid
+// (ceil(mx/32), ceil(my/16), images).
 template <int TAPS>
 __global__ __launch_bounds__(256) void k_idwt2_level(const float2 *__restrict__ ll, int lstride, int64_t lpitch,
                                                      const float2 *__restrict__ w, int nx, int64_t wpitch,
                                                      float2 *__restrict__ out, int ostride, int64_t opitch, int mx,
                                                      int my, FilterSet f, const float2 *__restrict__ xprev,
                                                      float2 *__restrict__ zout, double beta, unsigned *status) {
-  constexpr int NI = kInvT / 2 + TAPS / 2;
-  __shared__ float2 sc[2 * NI][2 * NI];  // [low | high rows][low | high columns]
-  __shared__ float2 cp[kInvT][2 * NI];   // column-pass output rows
+  constexpr int H = TAPS / 2;
+  constexpr int NY = kInvTY / 2 + H - 1, NX = kInvTX / 2 + H - 1;
+  __shared__ double2 sc[2 * NY][2 * NX];  // [low | high rows][low | high columns]
+  __shared__ double2 cp[kInvTY][2 * NX];  // column-pass output rows (FP32 values)
   const int b = blockIdx.z;
   const int hx = mx >> 1, hy = my >> 1;
-  const int m0 = blockIdx.y * kInvT, n0 = blockIdx.x * kInvT;
-  const int i0 = m0 / 2 - TAPS / 2 + 1, j0 = n0 / 2 - TAPS / 2 + 1;
+  const int m0 = blockIdx.y * kInvTY, n0 = blockIdx.x * kInvTX;
+  const int i0 = m0 / 2 - H + 1, j0 = n0 / 2 - H + 1;
   const float2 *wb = w + b * wpitch;
-  for (int i = threadIdx.x; i < 4 * NI * NI; i += blockDim.x) {
-    const int r = i / (2 * NI), c = i % (2 * NI);
-    const bool rh = r >= NI, ch = c >= NI;
-    const int gy = wrap(i0 + (rh ? r - NI : r), hy), gx = wrap(j0 + (ch ? c - NI : c), hx);
-    sc[r][c] = (!rh && !ch) ? ll[b * lpitch + (int64_t)gy * lstride + gx]
-                            : wb[(int64_t)(rh ? hy + gy : gy) * nx + (ch ? hx + gx : gx)];
+  for (int i = threadIdx.x; i < 4 * NY * NX; i += blockDim.x) {
+    const int r = i / (2 * NX), c = i - r * (2 * NX);
+    const bool rh = r >= NY, ch = c >= NX;
+    const int gy = wrap(i0 + (rh ? r - NY : r), hy), gx = wrap(j0 + (ch ? c - NX : c), hx);
+    sc[r][c] = widen((!rh && !ch) ? ll[b * lpitch + (int64_t)gy * lstride + gx]
+                                  : wb[(int64_t)(rh ? hy + gy : gy) * nx + (ch ? hx + gx : gx)]);
   }
   __syncthreads();
-  // columns: output row ml of every staged column
-  for (int i = threadIdx.x; i < kInvT * 2 * NI; i += blockDim.x) {
-    const int ml = i / (2 * NI), c = i % (2 * NI);
-    double vx = 0.0, vy = 0.0;
+  // columns: output rows 2p, 2p + 1 at every staged column
+  for (int i = threadIdx.x; i < (kInvTY / 2) * 2 * NX; i += blockDim.x) {
+    const int p = i / (2 * NX), c = i - p * (2 * NX);
+    double ex = 0.0, ey = 0.0, ox = 0.0, oy = 0.0;
 #pragma unroll
-    for (int kk = 0; kk < TAPS / 2; ++kk) {
-      const int k = 2 * kk + (ml & 1);
-      const int il = (ml - k) / 2 + TAPS / 2 - 1;
-      const float2 a = sc[il][c], d = sc[NI + il][c];
-      vx += f.h[k] * a.x + f.g[k] * d.x;
-      vy += f.h[k] * a.y + f.g[k] * d.y;
+    for (int kk = 0; kk < H; ++kk) {
+      const double2 a = sc[p + H - 1 - kk][c], d = sc[NY + p + H - 1 - kk][c];
+      ex = fma(f.g[2 * kk], d.x, fma(f.h[2 * kk], a.x, ex));
+      ey = fma(f.g[2 * kk], d.y, fma(f.h[2 * kk], a.y, ey));
+      ox = fma(f.g[2 * kk + 1], d.x, fma(f.h[2 * kk + 1], a.x, ox));
+      oy = fma(f.g[2 * kk + 1], d.y, fma(f.h[2 * kk + 1], a.y, oy));
     }
-    cp[ml][c] = make_float2((float)vx, (float)vy);
+    cp[2 * p][c] = round32(ex, ey);
+    cp[2 * p + 1][c] = round32(ox, oy);
   }
   __syncthreads();
-  const int ml = threadIdx.x >> 4, nl = threadIdx.x & 15;
-  const int m = m0 + ml, n = n0 + nl;
+  // rows: output pixels 2q, 2q + 1 of row ml (one pair per thread)
+  const int ml = threadIdx.x >> 4, q = threadIdx.x & 15;
+  const int m = m0 + ml, n = n0 + 2 * q;
   if (m < my && n < mx) {
-    double vx = 0.0, vy = 0.0;
+    double ex = 0.0, ey = 0.0, ox = 0.0, oy = 0.0;
 #pragma unroll
-    for (int kk = 0; kk < TAPS / 2; ++kk) {
-      const int k = 2 * kk + (nl & 1);
-      const int jl = (nl - k) / 2 + TAPS / 2 - 1;
-      const float2 a = cp[ml][jl], d = cp[ml][NI + jl];
-      vx += f.h[k] * a.x + f.g[k] * d.x;
-      vy += f.h[k] * a.y + f.g[k] * d.y;
+    for (int kk = 0; kk < H; ++kk) {
+      const double2 a = cp[ml][q + H - 1 - kk], d = cp[ml][NX + q + H - 1 - kk];
+      ex = fma(f.g[2 * kk], d.x, fma(f.h[2 * kk], a.x, ex));
+      ey = fma(f.g[2 * kk], d.y, fma(f.h[2 * kk], a.y, ey));
+      ox = fma(f.g[2 * kk + 1], d.x, fma(f.h[2 * kk + 1], a.x, ox));
+      oy = fma(f.g[2 * kk + 1], d.y, fma(f.h[2 * kk + 1], a.y, oy));
     }
-    const float2 v = make_float2((float)vx, (float)vy);
+    const float2 v0 = make_float2((float)ex, (float)ey), v1 = make_float2((float)ox, (float)oy);
     const int64_t o = b * opitch + (int64_t)m * ostride + n;
-    out[o] = v;
-    flag_nonfinite(status, v);
+    out[o] = v0;
+    out[o + 1] = v1;
+    flag_nonfinite(status, v0);
+    flag_nonfinite(status, v1);
     if (zout) {
-      const float2 p = xprev[o];
-      zout[o] = make_float2((float)(v.x + beta * ((double)v.x - p.x)), (float)(v.y + beta * ((double)v.y - p.y)));
+      const float2 p0 = xprev[o], p1 = xprev[o + 1];
+      zout[o] = make_float2((float)(v0.x + beta * ((double)v0.x - p0.x)),
+                            (float)(v0.y + beta * ((double)v0.y - p0.y)));
+      zout[o + 1] = make_float2((float)(v1.x + beta * ((double)v1.x - p1.x)),
+                                (float)(v1.y + beta * ((double)v1.y - p1.y)));
     }
   }
 }
@@ -566,7 +582,7 @@ int dwt2_prox(const FilterSet &f, int nx, int ny, int levels, int nimg, float2 *
     const int lstride = top ? nx : mx >> 1;
     float2 *out = j == 0 ? xk : inv_buf(j);
     const int ostride = j == 0 ? nx : mx;
-    dim3 grid((unsigned)ceil_div(mx, kInvT), (unsigned)ceil_div(my, kInvT), (unsigned)nimg);
+    dim3 grid((unsigned)ceil_div(mx, kInvTX), (unsigned)ceil_div(my, kInvTY), (unsigned)nimg);
     const float2 *xp = j == 0 ? xprev : nullptr;
     float2 *zo = j == 0 ? z : nullptr;
     unsigned *st = j == 0 ? status : nullptr;

@@ -19,9 +19,17 @@ struct FilterSet {
 
 // Soft-threshold of one complex coefficient: w * max(0, 1 - tau/|w|)
 // (evaluated in FP64 so that the threshold carries no FP32 rounding bias).
+// 1/|w| is the hardware reciprocal square root of |w|^2 refined by one
+// Newton step, y (1 + (1 - |w|^2 y^2) / 2), which is accurate to a few FP64
+// ulps, far below the FP32 rounding of the result; |w| > tau is tested as
+// |w|^2 > tau^2.  NaN input stays NaN (0 * NaN).  |w|^2 of FP32 components
+// is zero or above 1e-90, so the reciprocal square root never sees an FP64
+// subnormal.
 __device__ inline float2 soft(float2 v, double t) {
-  const double m = sqrt((double)v.x * v.x + (double)v.y * v.y);
-  const double sc = m > t ? 1.0 - t / m : 0.0;
+  const double m2 = (double)v.x * v.x + (double)v.y * v.y;
+  const double y0 = __builtin_amdgcn_rsq(m2);
+  const double y = fma(0.5 * y0, fma(-m2 * y0, y0, 1.0), y0);
+  const double sc = m2 > t * t ? 1.0 - t * y : 0.0;
   return make_float2((float)(v.x * sc), (float)(v.y * sc));
 }
 
