@@ -457,6 +457,26 @@ int expenc_set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int
 int expenc_plan_info(const expenc_op *op, int32_t batch, int32_t precision, int32_t nprob, int64_t *out);
 
 /*
+ * expenc_set_tuning with the contractions' column width as well:
+ * col_groups = 16-column groups of the B*C coil columns that one wave
+ * carries (1 or 2; 0 = the default, 2 when there are at least two groups).
+ * Two share every phase tile between 32 columns; one halves the
+ * accumulator registers and puts the groups in separate workgroups.  The
+ * operand layouts follow the width, so later plans (and workspace sizes)
+ * change with it.  Other properties as for expenc_set_tuning; all three
+ * values 0 remove the entry.
+ */
+int expenc_set_launch_shape(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target,
+                            int32_t adj_target, int32_t col_groups);
+
+/*
+ * expenc_plan_info writing min(n_out, 7) values: out[0..5] as there and
+ * out[6] = the column width in 16-column groups per wave.
+ */
+int expenc_plan_info_ex(const expenc_op *op, int32_t batch, int32_t precision, int32_t nprob, int64_t *out,
+                        int32_t n_out);
+
+/*
  * Profiling aid (not part of the method): per-kernel timing of the two
  * contraction kernels with HIP events recorded on their launch stream around
  * every eager launch (launches captured into a graph are not timed).

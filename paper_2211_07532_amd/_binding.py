@@ -110,6 +110,9 @@ SIGNATURES = {
     "expenc_set_tuning": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int, _c_int]),
     "expenc_plan_info": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int,
                                         ctypes.POINTER(ctypes.c_int64)]),
+    "expenc_plan_info_ex": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int,
+                                           ctypes.POINTER(ctypes.c_int64), _c_int]),
+    "expenc_set_launch_shape": (ctypes.c_int, [ctypes.POINTER(ExpencOp), _c_int, _c_int, _c_int, _c_int, _c_int]),
     "expenc_kernel_timing": (ctypes.c_int, [_c_int, ctypes.POINTER(ctypes.c_double)]),
     "expenc_solve_status": (ctypes.c_int, [_vp, _vp]),
     "expenc_axpby": (ctypes.c_int, [ctypes.c_int64, ctypes.c_double, _vp, ctypes.c_double, _vp, _vp, _vp]),

@@ -3,11 +3,16 @@
 Both contractions split their reduction (over pixels for A, over samples for
 A^H) into chunks so that one launch has about `target` workgroups; more
 chunks fill the 256 compute units better but cost partial-sum traffic and a
-longer reduction.  For one operator geometry (grid, coils, samples, basis
-terms and kind), batch and precision, ``tune`` times whole forward and
-adjoint applications (torch events on the launch stream) over a ladder of
-targets, keeps the fastest per direction, registers it with the library
-(``expenc_set_tuning``) and stores it in a JSON cache keyed by the GPU
+longer reduction.  The column width is the other tunable: a wave carries one
+or two 16-column groups of the coil columns (two share each phase tile;
+one needs half the accumulators and spreads the groups over workgroups).
+For one operator geometry (grid, coils, samples, basis terms and kind),
+batch and precision, ``tune`` times whole forward and adjoint applications
+(torch events on the launch stream) over a ladder of targets for each width,
+keeps the fastest target per direction within each width and the width with
+the smallest forward + adjoint time (the width is shared by both directions:
+the operand layouts follow it), registers the result with the library
+(``expenc_set_launch_shape``) and stores it in a JSON cache keyed by the GPU
 architecture and compute-unit count and the geometry, so later processes
 apply it without timing again (``apply_cached``).  ``tuning_defaults.json``
 beside this module ships the shapes measured for the benchmark geometries on
@@ -71,17 +76,20 @@ def _store(path: str, key: str, entry: dict) -> None:
     os.replace(tmp, path)
 
 
-def set_targets(op: _e.Operator, batch: int, precision, fwd_target: int, adj_target: int) -> None:
-    _b.check(_b.lib().expenc_set_tuning(ctypes.byref(op._c), batch, _e._prec(precision), int(fwd_target),
-                                        int(adj_target)), "expenc_set_tuning")
+def set_targets(op: _e.Operator, batch: int, precision, fwd_target: int, adj_target: int,
+                col_groups: int = 0) -> None:
+    """Registers the workgroup targets (0: default) and the column width
+    (16-column groups per wave, 1 or 2; 0: default) for op's geometry."""
+    _b.check(_b.lib().expenc_set_launch_shape(ctypes.byref(op._c), batch, _e._prec(precision), int(fwd_target),
+                                              int(adj_target), int(col_groups)), "expenc_set_launch_shape")
 
 
 def plan_info(op: _e.Operator, batch: int = 1, precision="fp32", nprob: int = 1) -> dict:
-    out = (ctypes.c_int64 * 6)()
-    _b.check(_b.lib().expenc_plan_info(ctypes.byref(op._c), batch, _e._prec(precision), nprob, out),
-             "expenc_plan_info")
+    out = (ctypes.c_int64 * 7)()
+    _b.check(_b.lib().expenc_plan_info_ex(ctypes.byref(op._c), batch, _e._prec(precision), nprob, out, 7),
+             "expenc_plan_info_ex")
     return {"fwd_split": out[0], "adj_split": out[1], "fwd_workgroups": out[2], "adj_workgroups": out[3],
-            "fwd_split_max": out[4], "adj_split_max": out[5]}
+            "fwd_split_max": out[4], "adj_split_max": out[5], "col_groups": out[6]}
 
 
 @dataclasses.dataclass
@@ -90,8 +98,10 @@ class TuneResult:
     adj_target: int
     fwd_ms: float
     adj_ms: float
-    timings: Dict[int, tuple]      # target -> (forward ms, adjoint ms)
+    timings: Dict[tuple, tuple]    # (column groups, target) -> (forward ms, adjoint ms)
     cached: bool = False
+    col_groups: int = 0            # 0: the library's default width
+    width_ms: Dict[int, float] = dataclasses.field(default_factory=dict)  # width -> best forward + adjoint ms
 
 
 def apply_cached(op: _e.Operator, batch: int = 1, precision="fp32", path: Optional[str] = None,
@@ -105,8 +115,9 @@ def apply_cached(op: _e.Operator, batch: int = 1, precision="fp32", path: Option
         e = _load(DEFAULTS).get(key)
     if not e:
         return None
-    set_targets(op, batch, precision, e["fwd_target"], e["adj_target"])
-    return TuneResult(e["fwd_target"], e["adj_target"], e["fwd_ms"], e["adj_ms"], {}, cached=True)
+    gw = int(e.get("col_groups", 0))
+    set_targets(op, batch, precision, e["fwd_target"], e["adj_target"], gw)
+    return TuneResult(e["fwd_target"], e["adj_target"], e["fwd_ms"], e["adj_ms"], {}, cached=True, col_groups=gw)
 
 
 def _time_calls(fn, reps: int) -> float:
@@ -122,10 +133,14 @@ def _time_calls(fn, reps: int) -> float:
 
 
 def tune(op: _e.Operator, batch: int = 1, precision="fp32", candidates: Sequence[int] = CANDIDATES,
-         reps: int = 5, path: Optional[str] = None, use_cache: bool = True, seed: int = 0) -> TuneResult:
-    """Times forward and adjoint applications for each workgroup target and
-    registers the fastest per direction.  Candidates that yield the same
-    split as an earlier one are skipped."""
+         reps: int = 5, path: Optional[str] = None, use_cache: bool = True, seed: int = 0,
+         widths: Optional[Sequence[int]] = None) -> TuneResult:
+    """Times forward and adjoint applications for each column width and
+    workgroup target; registers the fastest target per direction of the
+    width with the smallest forward + adjoint time.  Candidates that yield
+    the same split as an earlier one of the same width are skipped.  widths
+    defaults to (2, 1) when the coil columns span at least two 16-column
+    groups, else the single width 1."""
     path = path or cache_path()
     if use_cache:
         r = apply_cached(op, batch, precision, path)
@@ -134,25 +149,37 @@ def tune(op: _e.Operator, batch: int = 1, precision="fp32", candidates: Sequence
     g = torch.Generator(device="cpu").manual_seed(seed)
     x = torch.randn((batch, op.npix, 2), generator=g).to(op.device)
     x = torch.view_as_complex(x.contiguous())
-    y = _e.forward(x, op, precision)
-    timings: Dict[int, tuple] = {}
-    seen_f, seen_a = set(), set()
-    for t in candidates:
-        set_targets(op, batch, precision, t, t)
-        info = plan_info(op, batch, precision)
-        tf = ta = float("inf")
-        if info["fwd_split"] not in seen_f:
-            seen_f.add(info["fwd_split"])
-            tf = _time_calls(lambda: _e.forward(x, op, precision, out=y), reps)
-        if info["adj_split"] not in seen_a:
-            seen_a.add(info["adj_split"])
-            ta = _time_calls(lambda: _e.adjoint(y, op, precision), reps)
-        timings[t] = (tf, ta)
-    best_f = min(timings, key=lambda t: timings[t][0])
-    best_a = min(timings, key=lambda t: timings[t][1])
-    set_targets(op, batch, precision, best_f, best_a)
-    res = TuneResult(best_f, best_a, timings[best_f][0], timings[best_a][1], timings)
-    _store(path, _key(op, batch, precision), {"fwd_target": best_f, "adj_target": best_a,
+    if widths is None:
+        widths = (2, 1) if batch * op.ncoils > 16 else (1,)
+    timings: Dict[tuple, tuple] = {}
+    width_ms: Dict[int, float] = {}
+    best = None
+    for gw in widths:
+        set_targets(op, batch, precision, 0, 0, gw)
+        y = _e.forward(x, op, precision)
+        seen_f, seen_a = set(), set()
+        for t in candidates:
+            set_targets(op, batch, precision, t, t, gw)
+            info = plan_info(op, batch, precision)
+            tf = ta = float("inf")
+            if info["fwd_split"] not in seen_f:
+                seen_f.add(info["fwd_split"])
+                tf = _time_calls(lambda: _e.forward(x, op, precision, out=y), reps)
+            if info["adj_split"] not in seen_a:
+                seen_a.add(info["adj_split"])
+                ta = _time_calls(lambda: _e.adjoint(y, op, precision), reps)
+            timings[(gw, t)] = (tf, ta)
+        mine = [k for k in timings if k[0] == gw]
+        bf = min(mine, key=lambda k: timings[k][0])
+        ba = min(mine, key=lambda k: timings[k][1])
+        total = timings[bf][0] + timings[ba][1]
+        width_ms[gw] = total
+        if best is None or total < best[0]:
+            best = (total, gw, bf[1], ba[1], timings[bf][0], timings[ba][1])
+    _, gw, best_f, best_a, fms, ams = best
+    set_targets(op, batch, precision, best_f, best_a, gw)
+    res = TuneResult(best_f, best_a, fms, ams, timings, col_groups=gw, width_ms=width_ms)
+    _store(path, _key(op, batch, precision), {"fwd_target": best_f, "adj_target": best_a, "col_groups": gw,
                                               "fwd_ms": res.fwd_ms, "adj_ms": res.adj_ms})
     return res
 
@@ -189,8 +216,10 @@ def main(argv=None):
                          sh_grid=(w.fov, w.fov, w.z0))
         for f in a.forms.split(","):
             r = tune(op, 1, f, reps=10, path=a.out, use_cache=False)
-            print(f"{w.name} {f}: forward target {r.fwd_target} ({r.fwd_ms:.4f} ms), "
-                  f"adjoint target {r.adj_target} ({r.adj_ms:.4f} ms)", flush=True)
+            widths = ", ".join(f"{g}: {t:.4f}" for g, t in sorted(r.width_ms.items()))
+            print(f"{w.name} {f}: column groups {r.col_groups}, forward target {r.fwd_target} "
+                  f"({r.fwd_ms:.4f} ms), adjoint target {r.adj_target} ({r.adj_ms:.4f} ms); "
+                  f"best A + A^H ms per width {{{widths}}}", flush=True)
             set_targets(op, 1, f, 0, 0)
 
 

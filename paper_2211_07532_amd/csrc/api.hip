@@ -380,19 +380,32 @@ extern "C" int expenc_set_tuning(const expenc_op *op, int32_t batch, int32_t pre
                                  int32_t adj_target) {
   EncPlan chk;
   EX_TRY(make_plan(op, batch, precision, &chk));
-  return set_tuning(op, batch, precision, fwd_target, adj_target);
+  return set_tuning(op, batch, precision, fwd_target, adj_target, 0);
+}
+
+extern "C" int expenc_set_launch_shape(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target,
+                                       int32_t adj_target, int32_t col_groups) {
+  return set_tuning(op, batch, precision, fwd_target, adj_target, col_groups);
+}
+
+extern "C" int expenc_plan_info_ex(const expenc_op *op, int32_t batch, int32_t precision, int32_t nprob,
+                                   int64_t *out, int32_t n_out) {
+  if (!out) return fail(EXPENC_EINVAL, "out is NULL");
+  if (n_out < 0) return fail(EXPENC_EINVAL, "n_out must be >= 0");
+  EncPlan p;
+  EX_TRY(make_plan(op, batch, precision, &p, nprob));
+  const int64_t v[7] = {p.fwd_split,
+                        p.adj_split,
+                        (int64_t)p.Tp / 256 * p.fwd_split * p.NGY * p.P,  // forward workgroups per launch
+                        (int64_t)p.Rp / 256 * p.adj_split * p.NGY * p.P,  // adjoint workgroups per launch
+                        p.Rp / 16,                                        // largest forward split
+                        p.Tp / 16,                                        // largest adjoint split
+                        p.GW};                                            // 16-column groups per wave
+  for (int i = 0; i < n_out && i < 7; ++i) out[i] = v[i];
+  return EXPENC_OK;
 }
 
 extern "C" int expenc_plan_info(const expenc_op *op, int32_t batch, int32_t precision, int32_t nprob,
                                 int64_t *out) {
-  if (!out) return fail(EXPENC_EINVAL, "out is NULL");
-  EncPlan p;
-  EX_TRY(make_plan(op, batch, precision, &p, nprob));
-  out[0] = p.fwd_split;
-  out[1] = p.adj_split;
-  out[2] = (int64_t)p.Tp / 256 * p.fwd_split * p.NGY * p.P;  // forward workgroups per launch
-  out[3] = (int64_t)p.Rp / 256 * p.adj_split * p.NGY * p.P;  // adjoint workgroups per launch
-  out[4] = p.Rp / 16;                                         // largest forward split
-  out[5] = p.Tp / 16;                                         // largest adjoint split
-  return EXPENC_OK;
+  return expenc_plan_info_ex(op, batch, precision, nprob, out, 6);
 }

@@ -669,7 +669,7 @@ static int target_workgroups() {
 struct TuneEntry {
   int32_t nx, ny, ncoils, nbasis, basis_kind, batch, precision;
   int64_t nsamples;
-  int32_t fwd_target, adj_target;
+  int32_t fwd_target, adj_target, col_groups;
 };
 static std::mutex g_tune_mu;
 static std::vector<TuneEntry> g_tune;
@@ -683,29 +683,32 @@ static bool tune_match(const TuneEntry &e, const expenc_op *op, int32_t batch, i
          e.nsamples == op->nsamples;
 }
 
-static void tuned_targets(const expenc_op *op, int32_t batch, int32_t precision, int *fwd, int *adj) {
+static void tuned_targets(const expenc_op *op, int32_t batch, int32_t precision, int *fwd, int *adj, int *gw) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (const TuneEntry &e : g_tune)
     if (tune_match(e, op, batch, precision)) {
       if (e.fwd_target > 0) *fwd = e.fwd_target;
       if (e.adj_target > 0) *adj = e.adj_target;
+      if (e.col_groups > 0) *gw = e.col_groups;
       return;
     }
 }
 
-int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target) {
+int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target,
+               int32_t col_groups) {
   if (!op) return fail(EXPENC_EINVAL, "operator descriptor is NULL");
   if (fwd_target < 0 || adj_target < 0 || fwd_target > (1 << 20) || adj_target > (1 << 20))
     return fail(EXPENC_EINVAL, "workgroup targets must be in [0, 2^20]");
+  if (col_groups < 0 || col_groups > 2) return fail(EXPENC_EINVAL, "col_groups must be 0, 1 or 2");
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (size_t i = 0; i < g_tune.size(); ++i)
     if (tune_match(g_tune[i], op, batch, precision)) {
       g_tune.erase(g_tune.begin() + i);
       break;
     }
-  if (fwd_target > 0 || adj_target > 0)
+  if (fwd_target > 0 || adj_target > 0 || col_groups > 0)
     g_tune.push_back(TuneEntry{op->nx, op->ny, op->ncoils, op->nbasis, op->basis_kind, batch, precision,
-                               op->nsamples, fwd_target, adj_target});
+                               op->nsamples, fwd_target, adj_target, col_groups});
   g_tune_gen.fetch_add(1);
   return EXPENC_OK;
 }
@@ -748,7 +751,11 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.B = batch;
   q.NC = q.C * q.B;
   q.G = (int32_t)ceil_div(q.NC, 16);
-  q.GW = q.G >= 2 ? 2 : 1;
+  int tgt_fwd = target_workgroups(), tgt_adj = tgt_fwd, tuned_gw = 0;
+  tuned_targets(op, batch, precision, &tgt_fwd, &tgt_adj, &tuned_gw);
+  // 16-column groups per wave: two (one phase tile feeds both) unless tuned
+  // to one or there is only one
+  q.GW = (q.G >= 2 && tuned_gw != 1) ? 2 : 1;
   q.NGY = (int32_t)ceil_div(q.G, q.GW);
   q.comb = (batch == 1 && precision != EXPENC_FP32);
   q.NCP = q.NGY * q.GW * 16;  // every wave's column groups exist (zero-filled past NC)
@@ -758,8 +765,6 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.has_dw0 = op->dw0 != nullptr;
   q.P = nprob;
   q.scaled = precision == EXPENC_FP16_SPLIT;
-  int tgt_fwd = target_workgroups(), tgt_adj = tgt_fwd;
-  tuned_targets(op, batch, precision, &tgt_fwd, &tgt_adj);
   // forward: 256 sample rows per workgroup, split over pixels
   {
     int64_t nrb = q.Tp / 256 * q.P;

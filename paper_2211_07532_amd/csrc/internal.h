@@ -313,7 +313,8 @@ uint64_t hash_bytes(uint64_t h, const void *p, size_t n);
 // within 1e-5 of the FP64 solve on the 1.5 mm reconstruction (50 iterations:
 // 4.9e-6 fp16, 6.9e-6 bf16).
 inline int default_refine(int32_t precision) { return precision == EXPENC_FP16_SPLIT ? 25 : 17; }
-int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target);
+int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target,
+               int32_t col_groups);
 uint64_t tuning_generation();
 // Carves the buffers of plan p; the partial-sum buffer gets at least
 // min_part float2 elements (so a second plan can share it).

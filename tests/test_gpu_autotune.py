@@ -74,3 +74,45 @@ def test_batched_solve_with_tuned_totals_matches_oracle():
             assert solve.nrmse(xs[k].cpu().numpy().reshape(-1), ref) <= 1e-5
     finally:
         autotune.set_targets(cases[0].op, 1, "fp32", 0, 0)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_column_width_one_keeps_parity(prec):
+    """The tuner's other dimension: with 32 coils (two 16-column groups) a
+    wave may carry one group instead of two (the groups then go to separate
+    workgroups).  Under width 1 the plan reports it, A and A^H stay within
+    the form's bar against the FP64 oracle, and an 8-iteration FISTA solve
+    (operand builds, residual packing and the coil-combining reduction over
+    two column groups) matches the oracle's."""
+    import paper_2211_07532_amd as ee
+    from paper_2211_07532_amd import autotune
+    w = synth.Workload("gw1", 32, 0.222, 32, 2000, 2e-6, 2.0, 16, 80.0, 20.0, 8, "db4", 2, 93, z0=0.001)
+    case = Case(w, sh=True)
+    try:
+        assert autotune.plan_info(case.op, 1, prec)["col_groups"] == 2
+        autotune.set_targets(case.op, 1, prec, 0, 0, 1)
+        if prec != "fp32":
+            autotune.set_targets(case.op, 1, "fp32", 0, 0, 1)
+        info = autotune.plan_info(case.op, 1, prec)
+        print(f"[case] width 1, {prec}: {info}", flush=True)
+        assert info["col_groups"] == 1
+        x = case.x_noisy
+        y_ref = encoding.forward(x, *case.oracle_args())
+        x_ref = encoding.adjoint(y_ref, *case.oracle_args())
+        bar = 1e-5 if prec == "fp32" else 1e-3
+        y = ee.forward(case.to_dev(x), case.op, prec).cpu().numpy()
+        xa = ee.adjoint(case.to_dev(c64(y_ref)), case.op, prec).cpu().numpy()
+        e_f, e_a = rel(y.reshape(y_ref.shape), y_ref), rel(xa.reshape(x_ref.shape), x_ref)
+        print(f"  A {e_f:.2e}  A^H {e_a:.2e}", flush=True)
+        assert e_f <= bar and e_a <= bar
+        op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
+        yd = c64(op.A(x))
+        L = 1.05 * solve.power_lipschitz(op, c64(synth.power_start(w.npix, 4)), 30)
+        r = ee.fista(case.to_dev(yd), case.op, 8, 2, "db4", precision=prec, lipschitz=L, lam=1e-3)
+        ref = solve.fista(op, yd, L, 1e-3, 8, 2, "db4", w.n_pad)
+        e = solve.nrmse(r.x.cpu().numpy().reshape(-1), ref)
+        print(f"  FISTA 8 iterations: NRMSE vs oracle {e:.2e}", flush=True)
+        assert e <= (1e-5 if prec == "fp32" else 1e-4)
+    finally:
+        autotune.set_targets(case.op, 1, prec, 0, 0, 0)
+        autotune.set_targets(case.op, 1, "fp32", 0, 0, 0)
