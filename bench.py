@@ -44,13 +44,13 @@ N_POWER = 20
 TRAFFIC = {
     "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290755072,
              "valu_instr": 158732000, "fwd_valu_instr": 121229000,
-             "sha": "da62a89def6365626997cafbcdf8b0ae8fd2dd7e4f8d764017959163f9ac33f6"},
+             "sha": "6acaf85201e55d0555733c9f1b6641a0cc073090c5dfa7d82e3cc044a29720d1"},
     "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89606349,
              "valu_instr": 93196400, "fwd_valu_instr": 106418000,
-             "sha": "591c5e1804153d61bf75bad7854f80b9a35a09f1090319df0c2fda1c3cc5bb63"},
+             "sha": "6088a9a3bd153b5ed0730aa5e3c3d4db94509c0f7f0cc8bc3247bb0a4e42e12a"},
     "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89587302,
              "valu_instr": 74911900, "fwd_valu_instr": 87461900,
-             "sha": "591c5e1804153d61bf75bad7854f80b9a35a09f1090319df0c2fda1c3cc5bb63"},
+             "sha": "6088a9a3bd153b5ed0730aa5e3c3d4db94509c0f7f0cc8bc3247bb0a4e42e12a"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],
