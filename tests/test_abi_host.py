@@ -135,3 +135,38 @@ def test_wavelet_prox_arguments_rejected():
     assert lib.wavelet_prox(32, 32, 2, 1, 1, v, w, x, xp, xp, 0.5, tau, None) == b.EXPENC_EINVAL
     assert lib.wavelet_prox(32, 32, 2, 7, 1, v, w, x, xp, z, 0.5, tau, None) == b.EXPENC_EINVAL
     assert lib.wavelet_prox(32, 32, 2, 1, 0, v, w, x, xp, z, 0.5, tau, None) == b.EXPENC_EINVAL
+
+
+def test_launch_shape_width_and_batch_launch_validation():
+    """The column width of the launch shape (16-column groups per wave) and
+    the batched solve's launch pattern are validated and planned on the host."""
+    b, lib = _lib()
+    fp16 = b.FP16_SPLIT
+    op = _op(b)                     # 32 coils: two 16-column groups
+    out = (ctypes.c_int64 * 7)()
+    assert lib.expenc_plan_info_ex(ctypes.byref(op), 1, fp16, 1, out, 7) == b.EXPENC_OK
+    assert out[6] == 2              # default width: both groups in one wave
+    assert list(out)[:6] == _info(b, lib, op, prec=fp16)
+    try:
+        assert lib.expenc_set_launch_shape(ctypes.byref(op), 1, fp16, 0, 0, 3) == b.EXPENC_EINVAL
+        assert lib.expenc_set_launch_shape(ctypes.byref(op), 1, fp16, 0, 0, 1) == b.EXPENC_OK
+        assert lib.expenc_plan_info_ex(ctypes.byref(op), 1, fp16, 1, out, 7) == b.EXPENC_OK
+        assert out[6] == 1
+        # an entry is per precision: FP32 keeps the default width
+        assert lib.expenc_plan_info_ex(ctypes.byref(op), 1, 0, 1, out, 7) == b.EXPENC_OK and out[6] == 2
+        # n_out bounds the writes
+        short = (ctypes.c_int64 * 7)(*([-9] * 7))
+        assert lib.expenc_plan_info_ex(ctypes.byref(op), 1, fp16, 1, short, 2) == b.EXPENC_OK
+        assert list(short)[2:] == [-9] * 5
+        # one 16-column group is always width 1
+        op16 = _op(b, c=16)
+        assert lib.expenc_plan_info_ex(ctypes.byref(op16), 1, fp16, 1, out, 7) == b.EXPENC_OK and out[6] == 1
+    finally:
+        lib.expenc_set_launch_shape(ctypes.byref(op), 1, fp16, 0, 0, 0)
+    assert lib.expenc_plan_info_ex(ctypes.byref(op), 1, fp16, 1, out, 7) == b.EXPENC_OK and out[6] == 2
+    # the batched solve's launch pattern is FORKED or GROUPED
+    opts = b.FistaOpts(2, fp16, 1, 2, 0, 0, 0, 0, 0, 7, 1.0, 1.0, 0.0, None, None, None)
+    arr = (b.ExpencOp * 1)(op)
+    assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) == 0
+    opts.batch_launch = b.EXPENC_BATCH_GROUPED
+    assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) > 0
