@@ -516,6 +516,15 @@ def main():
     }
     if "fp32" in out and head != "fp32":
         line["split_vs_fp32_fista_iter_ratio"] = round(h["fista_iter_per_s"] / out["fp32"]["fista_iter_per_s"], 3)
+    # which form the headline is, and the metric's named bf16 split beside it
+    line["headline_form"] = {"form": head, "dtype": FORMS[head],
+                             "rule": "fastest form whose solve meets NRMSE <= 1e-4 against the FP64 oracle"}
+    if "bf16" in out and "fp32" in out:
+        line["bf16_split"] = {"gcmac_per_s": out["bf16"]["gcmac_per_s"],
+                              "fista_iter_per_s": out["bf16"]["fista_iter_per_s"],
+                              "nrmse_vs_fp64": out["bf16"]["nrmse_vs_fp64"],
+                              "vs_fp32_fista_iter_ratio": round(out["bf16"]["fista_iter_per_s"] /
+                                                                out["fp32"]["fista_iter_per_s"], 3)}
     print("[bench] balanced FISTA with the undecimated wavelet", file=sys.stderr, flush=True)
     line["balanced_fista"] = run_balanced(sorted({"fp32", head}), ee, torch, w, op, y, v0)
     print("[bench] least squares (CG) against CS", file=sys.stderr, flush=True)
