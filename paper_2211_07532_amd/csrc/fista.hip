@@ -832,6 +832,12 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
   EX_TRY(make_filter_set(opts->wavelet, &f));
   hipStream_t s = (hipStream_t)stream;
   const int NG = (int)bp.members.size();
+  // the grouped launch pattern needs one shape class for every group
+  bool grouped = opts->batch_launch == EXPENC_BATCH_GROUPED && opts->precision != EXPENC_FP32;
+  for (int g = 0; g < NG && grouped; ++g) grouped = split_groupable(bp.groups[0].L.p, bp.groups[g].L.p);
+  if (opts->batch_launch == EXPENC_BATCH_GROUPED && !grouped)
+    return fail(EXPENC_EUNSUPPORTED, "grouped batch launches need split precision and the solid-harmonic kind "
+                                     "with one column width for every group");
   EX_TRY(clear_status(bp.status, s));
   // gather the members' inputs into the packed group arrays
   for (int g = 0; g < NG; ++g) {
@@ -902,11 +908,6 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
       }
       return rc;
     };
-    bool grouped = opts->batch_launch == EXPENC_BATCH_GROUPED && opts->precision != EXPENC_FP32;
-    for (int g = 0; g < NG && grouped; ++g) grouped = split_groupable(bp.groups[0].L.p, bp.groups[g].L.p);
-    if (opts->batch_launch == EXPENC_BATCH_GROUPED && !grouped)
-      return fail(EXPENC_EUNSUPPORTED, "grouped batch launches need split precision and the solid-harmonic kind "
-                                       "with one column width for every group");
     std::vector<const EncPlan *> plans(NG);
     std::vector<const EncBuffers *> bufs(NG);
     for (int g = 0; g < NG; ++g) {
