@@ -170,3 +170,26 @@ def test_launch_shape_width_and_batch_launch_validation():
     assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) == 0
     opts.batch_launch = b.EXPENC_BATCH_GROUPED
     assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) > 0
+
+
+def test_size_limits_are_reported_by_planning():
+    """The documented size limits reach the caller as status codes before
+    any device work: grids above 2^26 pixels and more than 2^31 samples are
+    invalid, more than 4096 coil columns (ncoils x batch) unsupported, and
+    batch or problem counts out of range invalid."""
+    b, lib = _lib()
+    out = (ctypes.c_int64 * 6)()
+    ok = _op(b)
+    assert lib.expenc_plan_info(ctypes.byref(ok), 1, 0, 1, out) == b.EXPENC_OK
+    big = _op(b, n=8193)                      # 8193^2 > 2^26 pixels
+    assert lib.expenc_plan_info(ctypes.byref(big), 1, 0, 1, out) == b.EXPENC_EINVAL
+    assert b"too large" in lib.expenc_last_error()
+    op = _op(b)
+    op.nsamples = (1 << 31) + 1
+    assert lib.expenc_plan_info(ctypes.byref(op), 1, 0, 1, out) == b.EXPENC_EINVAL
+    wide = _op(b, c=64)
+    assert lib.expenc_plan_info(ctypes.byref(wide), 64, 0, 1, out) == b.EXPENC_OK      # 4096 columns
+    assert lib.expenc_plan_info(ctypes.byref(wide), 65, 0, 1, out) == b.EXPENC_EUNSUPPORTED
+    assert lib.expenc_plan_info(ctypes.byref(ok), 0, 0, 1, out) == b.EXPENC_EINVAL     # batch < 1
+    assert lib.expenc_plan_info(ctypes.byref(ok), 1, 0, 0, out) == b.EXPENC_EINVAL     # no problems
+    assert lib.expenc_plan_info(ctypes.byref(ok), 1, 0, 65536, out) == b.EXPENC_EINVAL

@@ -264,3 +264,25 @@ def test_cg_split_matches_oracle(prec, sh):
     res = np.linalg.norm(op.AH(op.A(x) - y))
     res_ref = np.linalg.norm(op.AH(op.A(ref) - y))
     assert abs(res - res_ref) <= 0.1 * res_ref + 1e-6 * np.linalg.norm(op.AH(y))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_zero_iterations_return_the_start(prec):
+    """K = 0, the degenerate solve: FISTA (single and batched) and CG return
+    their starting image x_0 = 0 exactly, after the prologue (power
+    iteration, lambda rule) has run, and report a healthy status."""
+    import torch
+    ee = _ee()
+    w = synth.TINY
+    case = Case(w, sh=True)
+    y = case.to_dev(c64(_oracle_op(case).A(case.x_noisy)))
+    v0 = case.to_dev(c64(synth.power_start(w.npix, 3)))
+    print(f"[case] zero iterations {prec}", flush=True)
+    r = ee.fista(y, case.op, 0, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0, n_power=5,
+                 lam=-1.0, lambda_factor=1e-3)
+    assert r.x.shape[-2:] == (w.n, w.n) and not torch.any(r.x != 0)
+    xb = ee.fista_batched([y, y], [case.op, case.op], 0, w.levels, w.wavelet, precision=prec, lipschitz=0.0,
+                          power_v0=v0, n_power=5, lam=-1.0, lambda_factor=1e-3, check_status=True)
+    assert all(not torch.any(x != 0) for x in xb)
+    xc = ee.cg(y, case.op, 0, precision=prec, check_status=True)
+    assert not torch.any(xc != 0)
