@@ -31,7 +31,10 @@
  *     validation happens on the host before any HIP call and is reported
  *     synchronously; launch failures are reported as EXPENC_EHIP.
  *   - On a non-OK status, expenc_last_error() returns a thread-local message.
- *   - Calls on distinct workspaces are independent; calls that share a
+ *   - Calls on distinct workspaces are independent, also when issued from
+ *     several host threads at once (the library's graph cache, capture
+ *     stream and fork streams are shared and locked; two first calls that
+ *     both capture a graph capture one after the other); calls that share a
  *     workspace must be ordered by the caller (same stream).
  */
 #ifndef EXPENC_H

@@ -196,6 +196,9 @@ struct GraphEntry {
 };
 static std::mutex g_graph_mu;
 static std::vector<GraphEntry> g_graphs;
+// Held from the start of a capture to its end: the per-device capture stream
+// (and the batched solver's fork streams) serve one capture at a time.
+static std::mutex g_capture_mu;
 static constexpr size_t kGraphCacheMax = 64;
 
 static uint64_t fnv(uint64_t h, const void *p, size_t n) {
@@ -226,20 +229,30 @@ static hipStream_t capture_stream(int device) {
 
 // Runs `body(stream)` either eagerly on s, or captured into a cached graph
 // that is then launched on s.
+// Launches the cached graph of (key, device) on s; false when there is none.
+static bool launch_cached(uint64_t key, int dev, hipStream_t s, int *rc) {
+  std::lock_guard<std::mutex> lk(g_graph_mu);
+  for (auto &e : g_graphs)
+    if (e.key == key && e.device == dev) {
+      e.last_stream = s;
+      const hipError_t err = hipGraphLaunch(e.exec, s);
+      *rc = err == hipSuccess ? EXPENC_OK : fail(EXPENC_EHIP, "graph launch failed: %s", hipGetErrorString(err));
+      return true;
+    }
+  return false;
+}
+
 template <class Body>
 static int run_graph(uint64_t key, hipStream_t s, Body body) {
   if (!graphs_enabled()) return body(s);
   int dev = 0;
   EX_HIP(hipGetDevice(&dev));
-  {
-    std::lock_guard<std::mutex> lk(g_graph_mu);
-    for (auto &e : g_graphs)
-      if (e.key == key && e.device == dev) {
-        e.last_stream = s;
-        EX_HIP(hipGraphLaunch(e.exec, s));
-        return EXPENC_OK;
-      }
-  }
+  int rc = EXPENC_OK;
+  if (launch_cached(key, dev, s, &rc)) return rc;
+  // one capture at a time; a thread that waited here may find the graph
+  // another thread has just captured for the same key
+  std::lock_guard<std::mutex> cap(g_capture_mu);
+  if (launch_cached(key, dev, s, &rc)) return rc;
   hipStream_t cs = capture_stream(dev);
   if (!cs) return fail(EXPENC_EHIP, "could not create the capture stream");
   EX_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
@@ -767,7 +780,8 @@ static int layout_batched(int32_t nprob, const expenc_op *ops, int32_t batch, co
 // plus the fork event, per device.  They are created before a capture
 // begins and kept until the process ends, so that no stream or event is
 // created or destroyed while a stream is being captured (an event recorded
-// into a capture stays referenced by the capture until it ends).
+// into a capture stays referenced by the capture until it ends).  The pool
+// serves one solve at a time: the caller holds *hold while it forks.
 constexpr int kForkStreams = 8;
 struct ForkPool {
   std::vector<hipStream_t> streams;
@@ -775,10 +789,10 @@ struct ForkPool {
 };
 
 static int fork_resources(int device, int ngroups, std::vector<hipStream_t> *streams,
-                          std::vector<hipEvent_t> *events) {
+                          std::vector<hipEvent_t> *events, std::unique_lock<std::mutex> *hold) {
   static std::mutex mu;
   static std::vector<ForkPool> pools;
-  std::lock_guard<std::mutex> lk(mu);
+  *hold = std::unique_lock<std::mutex>(mu);
   if ((int)pools.size() <= device) pools.resize(device + 1);
   ForkPool &fp = pools[device];
   const int ns = std::min(ngroups, kForkStreams);
@@ -884,10 +898,11 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
   if (opts->n_iter > 0) {
     std::vector<hipStream_t> fs;
     std::vector<hipEvent_t> ev;
+    std::unique_lock<std::mutex> pool_hold;
     if (NG > 1) {
       int dev = 0;
       EX_HIP(hipGetDevice(&dev));
-      EX_TRY(fork_resources(dev, NG, &fs, &ev));
+      EX_TRY(fork_resources(dev, NG, &fs, &ev, &pool_hold));
     }
     // Group g's work fn(g, stream) on a stream forked from cs, joined back.
     auto forked = [&](hipStream_t cs, auto &&fn) -> int {

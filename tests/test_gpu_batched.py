@@ -120,6 +120,73 @@ def test_batched_fixed_scalars_and_repeat_is_bitwise():
         assert np.array_equal(a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint32))
 
 
+def test_concurrent_host_threads_match_calls_made_alone():
+    """Four host threads issue batched solves at the same moment, each on its
+    own stream with its own workspace (so each captures a graph of its own):
+    the library's shared state (graph cache, capture stream, fork streams)
+    must keep them apart, so that every result, first call and cached replay,
+    is bitwise the same call made alone."""
+    import ctypes
+    import threading
+    import torch
+    from paper_2211_07532_amd import _binding as b
+    ws_ = _mixed_workloads(n_per=1, n_iter=6)
+    cases = [Case(w, sh=True) for w in ws_]
+    ops = [_oracle_op(c) for c in cases]
+    ys = [c.to_dev(c64(o.A(c.x_noisy))) for o, c in zip(ops, cases)]
+    L = 1.05 * max(solve.power_lipschitz(o, c64(synth.power_start(w.npix, 12)), 20) for o, w in zip(ops, ws_))
+    n = len(cases)
+    carr = (b.ExpencOp * n)(*[c.op._c for c in cases])
+    yp = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+    precs = [b.FP16_SPLIT, b.FP32, b.FP16_SPLIT, b.BF16_SPLIT]
+
+    def solve_once(prec, stream, ws, xs):
+        opts = b.FistaOpts(6, prec, b.DB4, 2, 0, 0, 0, 0, 0, b.EXPENC_BATCH_FORKED, L, 2e-3, 0.0, None, None,
+                           None)
+        xp = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        return b.lib().fista_solve_batched(n, carr, 1, yp, xp, ctypes.byref(opts), ctypes.c_void_p(ws.data_ptr()),
+                                           ws.numel(), ctypes.c_void_p(stream.cuda_stream))
+
+    def resources(prec):
+        opts = b.FistaOpts(6, prec, b.DB4, 2, 0, 0, 0, 0, 0, 0, L, 2e-3, 0.0, None, None, None)
+        need = b.lib().fista_batched_workspace_size(n, carr, 1, ctypes.byref(opts))
+        assert need > 0
+        ws = torch.zeros(need, dtype=torch.uint8, device="cuda")
+        runs = [[torch.zeros((c.w.n, c.w.n), dtype=torch.complex64, device="cuda") for c in cases] for _ in range(2)]
+        return torch.cuda.Stream(), ws, runs
+
+    res = [resources(p) for p in precs]
+    torch.cuda.synchronize()
+    rcs = [[None, None] for _ in precs]
+    gate = threading.Barrier(len(precs))
+
+    def worker(i):
+        stream, ws, runs = res[i]
+        gate.wait()
+        for r in range(2):  # the first call captures, the second replays
+            rcs[i][r] = solve_once(precs[i], stream, ws, runs[r])
+        stream.synchronize()
+
+    print(f"[case] {len(precs)} threads, batched solves of {n} problems each", flush=True)
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(len(precs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=100)
+        assert not t.is_alive()
+    torch.cuda.synchronize()
+    assert rcs == [[b.EXPENC_OK, b.EXPENC_OK]] * len(precs), rcs
+    for i, p in enumerate(precs):
+        stream, _, _ = res[i]
+        ws = torch.zeros_like(res[i][1])
+        alone = [torch.zeros_like(x) for x in res[i][2][0]]
+        assert solve_once(p, stream, ws, alone) == b.EXPENC_OK
+        stream.synchronize()
+        for r in range(2):
+            for a, x in zip(alone, res[i][2][r]):
+                assert torch.equal(a.view(torch.float32), x.view(torch.float32)), (i, r)
+
+
 def test_batched_rejects_bad_arguments():
     import ctypes
     import torch
