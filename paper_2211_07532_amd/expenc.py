@@ -5,6 +5,12 @@ in the library's HIP kernels.  Tensors must live on a ROCm device.
 
 Layouts (see include/expenc.h): images [B][ny][nx] (or [B][R]) complex64,
 k-space [B][T][C] complex64, field arrays float64.
+
+Workspaces are allocated by the binding and kept for reuse, one per operator,
+call kind and current stream (per device and stream for batched solves):
+calls on one stream are ordered by it, calls on different streams get
+different workspaces.  Several host threads that issue calls on ONE stream
+with one operator must take turns, since their launches would interleave.
 """
 from __future__ import annotations
 
@@ -118,7 +124,7 @@ class Operator:
         n = _b.lib().expenc_workspace_size(ctypes.byref(self._c), batch, _prec(precision), what, nx_pad, ny_pad)
         if n == 0:
             raise _b.ExpencError(_b.EXPENC_EINVAL, "expenc_workspace_size")
-        key = (what, batch, _prec(precision), nx_pad, ny_pad)
+        key = (what, batch, _prec(precision), nx_pad, ny_pad, _stream(self.device).value)
         ws = self._ws.get(key)
         if ws is None or ws.numel() < n:
             ws = torch.empty(n, dtype=torch.uint8, device=self.device)
@@ -410,7 +416,7 @@ def fista_balanced(y: torch.Tensor, op: Operator, n_iter: int, levels: int = 1, 
     n = _b.lib().fista_balanced_workspace_size(ctypes.byref(op._c), B, ctypes.byref(opts))
     if n == 0:
         raise _b.ExpencError(_b.EXPENC_EINVAL, "fista_balanced_workspace_size")
-    key = ("balanced", B, _prec(precision), levels)
+    key = ("balanced", B, _prec(precision), levels, _stream(op.device).value)
     ws = op._ws.get(key)
     if ws is None or ws.numel() < n:
         ws = torch.empty(n, dtype=torch.uint8, device=op.device)
@@ -464,11 +470,12 @@ def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: i
     need = _b.lib().fista_batched_workspace_size(n, carr, batch, ctypes.byref(opts))
     if need == 0:
         raise _b.ExpencError(_b.EXPENC_EINVAL, "fista_batched_workspace_size")
-    ws = _batch_ws.get(dev)
+    wkey = (dev, _stream(dev).value)
+    ws = _batch_ws.get(wkey)
     if ws is None or ws.numel() < need:
-        _batch_ws.pop(dev, None)
+        _batch_ws.pop(wkey, None)
         ws = torch.empty(need, dtype=torch.uint8, device=dev)
-        _batch_ws[dev] = ws
+        _batch_ws[wkey] = ws
     check(_b.lib().fista_solve_batched(n, carr, batch, yp, xp, ctypes.byref(opts), _ptr(ws), ws.numel(),
                                        _stream(dev)), "fista_solve_batched")
     if check_status:

@@ -187,6 +187,45 @@ def test_concurrent_host_threads_match_calls_made_alone():
                 assert torch.equal(a.view(torch.float32), x.view(torch.float32)), (i, r)
 
 
+def test_binding_threads_on_own_streams_share_an_operator():
+    """Through the Python binding: threads that solve with ONE operator, each
+    on its own torch stream, get workspaces of their own (the binding keys
+    them by stream) and the result of the call made alone."""
+    import threading
+    import torch
+    ee = _ee()
+    w = _mixed_workloads(n_per=1, n_iter=6)[1]
+    c = Case(w, sh=True)
+    y0 = c64(_oracle_op(c).A(c.x_noisy))
+    L = 1.05 * solve.power_lipschitz(_oracle_op(c), c64(synth.power_start(w.npix, 12)), 20)
+    precs = ["fp16", "fp32", "fp16"]
+    ys = [c.to_dev(y0 * (k + 1)) for k in range(len(precs))]
+    kw = dict(lipschitz=L, lam=2e-3)
+    streams = [torch.cuda.Stream() for _ in precs]
+    out = [None] * len(precs)
+    gate = threading.Barrier(len(precs))
+    torch.cuda.synchronize()
+
+    def worker(i):
+        with torch.cuda.stream(streams[i]):
+            gate.wait()
+            out[i] = [ee.fista(ys[i], c.op, 6, 2, "db4", precision=precs[i], **kw).x for _ in range(2)]
+        streams[i].synchronize()
+
+    print(f"[case] {len(precs)} threads on one operator (n={w.n})", flush=True)
+    threads = [threading.Thread(target=worker, args=(i,)) for i in range(len(precs))]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=100)
+        assert not t.is_alive()
+    torch.cuda.synchronize()
+    for i, p in enumerate(precs):
+        alone = ee.fista(ys[i], c.op, 6, 2, "db4", precision=p, **kw).x
+        for r in range(2):
+            assert torch.equal(alone.view(torch.float32), out[i][r].view(torch.float32)), (i, r)
+
+
 def test_batched_rejects_bad_arguments():
     import ctypes
     import torch
