@@ -20,7 +20,7 @@ SOURCES = ["encode.hip", "split.hip", "split_adj.hip", "wavelet.hip", "api.hip",
            "balanced.hip", "noalloc.hip"]
 # Per-source code generation: the polynomial split adjoint keeps its matrix-
 # core results in the vector register file (no AGPR copies of the phase
-# tiles; 163 registers, three waves per SIMD instead of two).  The same
+# tiles; 165-168 registers, three waves per SIMD instead of two).  The same
 # option slows the forward kernels, so it is not global.
 EXTRA_FLAGS = {"split_adj.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 ARCH = "gfx950"

@@ -765,6 +765,7 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.has_dw0 = op->dw0 != nullptr;
   q.P = nprob;
   q.scaled = precision == EXPENC_FP16_SPLIT;
+  q.adj_anc = q.sh && precision != EXPENC_FP32;
   // forward: 256 sample rows per workgroup, split over pixels
   {
     int64_t nrb = q.Tp / 256 * q.P;
@@ -809,6 +810,7 @@ int plan_forward_within(const expenc_op *op, int32_t batch, int32_t precision, s
   EX_TRY(make_plan(op, batch, precision, &q));
   // the forward uses no adjoint partial sums: one adjoint split keeps them small
   q.adj_split = 1;
+  q.adj_anc = false;
   q.adj_chunk = (int32_t)q.Tp;
   const int32_t min_split = q.prec == EXPENC_FP32 ? (int32_t)ceil_div(q.Rp, kF32ChunkMax) : 1;
   auto set_split = [&](int32_t want) {
@@ -846,6 +848,7 @@ int carve_enc(const EncPlan &p, Arena &a, EncBuffers *b, size_t min_part) {
     b->dpa = a.take<float>(P * p.Tp * 16);
     b->dwq = a.take<double>(P * p.Rp);
     b->ddw = a.take<float>(P * p.Rp);
+    if (p.adj_anc) b->anc = a.take<float>(P * (p.Tp / 32) * p.Rp);
   }
   if (p.prec != EXPENC_FP32) {
     b->zs = a.take<char>(P * p.Rp * (p.NCP / 16) * 256);
@@ -1061,6 +1064,8 @@ int enc_forward_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s, b
 
 int enc_adjoint_partials(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   if (p.comb && !b.sq) return fail(EXPENC_EINVAL, "coil table of a single-image split plan is not carved");
+  if (p.adj_anc && !b.anc) return fail(EXPENC_EINVAL, "anchor table of a split plan is not carved");
+  if (p.sh && p.prec != EXPENC_FP32 && !p.adj_anc) return fail(EXPENC_EINVAL, "forward-only plan");
   timed(1, s, [&] {
     if (p.prec != EXPENC_FP32) {
       split_adjoint_launch(p, b, s);

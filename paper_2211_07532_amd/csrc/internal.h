@@ -240,6 +240,10 @@ struct EncPlan {
   // combines its coils in the epilogue and writes [adj_split][NGY][Rp]
   // partial images instead of [adj_split][Rp][NCP] per-coil partials
   bool comb = false;
+  // split forms with the solid-harmonic basis: the adjoint contraction reads
+  // its per-tile FP64 phase anchors from a table built at preparation
+  // (EncBuffers::anc); off for forward-only plans
+  bool adj_anc = false;
   bool has_dw0 = false;
   // Solid-harmonic basis given by grid geometry (EXPENC_BASIS_SH).  Split
   // forms with it lay pixels out row-padded: r' = y*nxq + x, nxq = nx rounded
@@ -286,6 +290,8 @@ struct EncBuffers {
   float *dpa = nullptr;    // split + SH: [Tp/32][64][8] adjoint increment operand (FP32)
   double *dwq = nullptr;   // split + SH: [Rp] dw0/2pi in the row-padded pixel layout
   float *ddw = nullptr;    // split + SH: [Rp] dwq minus its 16-pixel tile centre (FP32)
+  float *anc = nullptr;    // split + SH, adj_anc: [Tp/32][Rp] FP64 phase of each 32-sample tile's centre
+                           // sample at each pixel, reduced to turns in [0, 1) (the adjoint's anchors)
   float2 *sq = nullptr;    // split, single image: [Rp][NCP] S_c(r) in the partial-sum layout (0 on padding)
   float *scl = nullptr;    // scaled form: [P][2] powers of two of the forward (0) and adjoint (1) operands
   float *amax = nullptr;   // scaled form: [3][P][kAmaxBlocks] per-workgroup bounds of pre-passes (operand,

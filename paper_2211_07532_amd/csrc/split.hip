@@ -754,6 +754,31 @@ __global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, float *
   o[1] = make_float4(v[4], v[5], v[6], v[7]);
 }
 
+// Anchors of the polynomial split adjoint: for the 32-sample tile q and the
+// row-padded pixel rq, the phase of the tile's centre sample 32q + 16 at that
+// pixel, sum_m P_m(t) mono_m(x, y) + t dw0(r)/2pi, evaluated in FP64 (nested
+// in y, then in x) and reduced to turns in [0, 1).  The adjoint adds its FP32
+// phase increments within the tile to it.
+__global__ void k_prep_anchor(const double *__restrict__ pmono, const double *__restrict__ dwq, int64_t Tp, int Rp,
+                              int nxq, int nx, int ny, double dx, double dy, float *__restrict__ anc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Tp / 32 * Rp) return;
+  const int pz = blockIdx.y;  // problem
+  pmono += pz * Tp * 12;
+  dwq += (int64_t)pz * Rp;
+  anc += (int64_t)pz * (Tp / 32) * Rp;
+  const int64_t q = i / Rp;
+  const int rq = (int)(i - q * Rp);
+  const double x = (rq % nxq - 0.5 * nx) * dx, y = (rq / nxq - 0.5 * ny) * dy, w = dwq[rq];
+  const double *pc = pmono + (32 * q + 16) * 12;
+  // monomial order of pmono: 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3
+  const double a0 = fma(y, fma(y, fma(y, pc[9], pc[5]), pc[2]), pc[0]);
+  const double a1 = fma(y, fma(y, pc[8], pc[4]), pc[1]);
+  const double a2 = fma(y, pc[7], pc[3]);
+  const double pa = fma(pc[10], w, fma(x, fma(x, fma(x, pc[6], a2), a1), a0));
+  anc[i] = (float)__builtin_amdgcn_fract(pa);
+}
+
 // dwq[r'] = dw0(r)/2pi in the row-padded pixel layout.
 __global__ void k_prep_dwq(const double *__restrict__ dw0, int nx, int ny, int nxq, int Rp, double *__restrict__ dwq) {
   const int rq = blockIdx.x * blockDim.x + threadIdx.x;
@@ -791,6 +816,12 @@ int sh_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipSt
   }
   k_prep_dwq<<<gp(p.Rp), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);
   EX_LAUNCHED("off-resonance layout");
+  if (p.adj_anc) {
+    if (!b.anc) return fail(EXPENC_EINVAL, "anchor table of a split plan is not carved");
+    k_prep_anchor<<<gp(p.Tp / 32 * p.Rp), 256, 0, s>>>(b.pmono, b.dwq, p.Tp, p.Rp, p.nxq, p.nx, p.ny, p.dx, p.dy,
+                                                        b.anc);
+    EX_LAUNCHED("adjoint anchors");
+  }
   k_tile_diff<<<gp(p.Rp), 256, 0, s>>>(b.dwq, b.ddw, p.Rp, 1);
   EX_LAUNCHED("tile differences (pixels)");
   return EXPENC_OK;

@@ -9,7 +9,7 @@ namespace expenc {
 
 // Arguments of one problem group's adjoint launch.
 struct AdjShArgs {
-  const double *pmono;
+  const float *anc;
   const float *dpa;
   const double *dwq;
   const u32x4 *ys;
@@ -24,7 +24,7 @@ struct AdjShArgs {
 // column groups).
 template <int GW, bool BF>
 __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int bz, int gy) {
-  const double *__restrict__ pmono = a.pmono;
+  const float *__restrict__ anc = a.anc;
   const float *__restrict__ dpa = a.dpa;
   const double *__restrict__ dwq = a.dwq;
   const u32x4 *__restrict__ ys = a.ys;
@@ -42,21 +42,17 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
   const int g0 = by * GW;
   const int NGP = NCP / 16;
   const int pz = bz;  // problem
-  pmono += pz * Tp * 12;
+  anc += pz * (Tp / 32) * Rp;
   dpa += pz * Tp * 16;
   dwq += (int64_t)pz * Rp;
   ys += pz * Tp * NGP * 16;
   // this lane's pixel in each 32-row block, and its B operand of the
   // increment product: the monomial (or dw0) of term 2J + hl
-  double xg[2], yg[2], wg[2];
   float bm[2][6];
 #pragma unroll
   for (int blk = 0; blk < 2; ++blk) {
     const int rq = (int)(row0 + 32 * blk + jl);
     const double x = (rq % nxq - 0.5 * nx) * dx, y = (rq / nxq - 0.5 * ny) * dy, w = dwq[rq];
-    xg[blk] = x;
-    yg[blk] = y;
-    wg[blk] = w;
     // terms 0..11: 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3, dw0, anchor
     bm[blk][0] = (float)(hl ? x : 1.0);
     bm[blk][1] = (float)(hl ? x * x : y);
@@ -79,19 +75,14 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
     const float4 *ap = reinterpret_cast<const float4 *>(dpa + ((t >> 5) * 64 + lane) * 8);
     const float4 a03 = ap[0], a47 = ap[1];
     const float av[6] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y};
-    // anchor: FP64 phase of the tile's centre sample at this lane's pixels,
-    // reduced to turns; it enters the product as term 11 (A = 1)
-    const double *pc = pmono + (t + 16) * 12;
+    // anchor: FP64 phase of the tile's centre sample at this lane's pixels
+    // in turns (from the table); it enters the product as term 11 (A = 1)
+    const float *ap2 = anc + (t >> 5) * Rp + row0 + jl;
+    const float an[2] = {ap2[0], ap2[32]};
     f32x16 ph[2];
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-      const double y = yg[blk], x = xg[blk];
-      const double a0 = pc[0] + y * (pc[2] + y * (pc[5] + y * pc[9]));
-      const double a1 = pc[1] + y * (pc[4] + y * pc[8]);
-      const double a2 = pc[3] + y * pc[7];
-      const double pa = fma(pc[10], wg[blk], a0 + x * (a1 + x * (a2 + x * pc[6])));
-      const float anc = (float)__builtin_amdgcn_fract(pa);
-      const float b5 = hl ? anc : bm[blk][5];
+      const float b5 = hl ? an[blk] : bm[blk][5];
 #pragma unroll
       for (int v = 0; v < 16; ++v) ph[blk][v] = 0.f;
 #pragma unroll
@@ -137,15 +128,19 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
   adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, by, gy, row0, g0, lane, acc);
 }
 
+// The bf16 build needs a few more registers than the fp16 one; it is held to
+// three waves per SIMD (at the cost of spilling two registers), which
+// measured 3 % faster than the two waves it would otherwise get.
 template <int GW, bool BF>
-__global__ __launch_bounds__(256) void k_adj_split_sh(AdjShArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh(AdjShArgs a) {
   adj_split_sh_body<GW, BF>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
 }
 
 // Persistent form over several problem groups (the forward's grouped kernel
 // in split.hip describes the numbering and why the XCD mapping holds).
 template <int GW, bool BF>
-__global__ __launch_bounds__(256) void k_adj_split_sh_grouped(GroupedLaunch<AdjShArgs> G) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh_grouped(
+    GroupedLaunch<AdjShArgs> G) {
   for (int64_t t = blockIdx.x; t < G.off[G.ng]; t += gridDim.x) {
     int g = 0;
     while (g + 1 < G.ng && t >= G.off[g + 1]) ++g;
@@ -157,7 +152,7 @@ __global__ __launch_bounds__(256) void k_adj_split_sh_grouped(GroupedLaunch<AdjS
 }
 
 static AdjShArgs adj_sh_args(const EncPlan &p, const EncBuffers &b) {
-  return AdjShArgs{b.pmono, b.dpa, b.dwq, reinterpret_cast<const u32x4 *>(b.ys), reinterpret_cast<float *>(b.part),
+  return AdjShArgs{b.anc, b.dpa, b.dwq, reinterpret_cast<const u32x4 *>(b.ys), reinterpret_cast<float *>(b.part),
                    p.comb ? b.sq : nullptr, p.Tp, p.Rp, p.NCP, p.adj_chunk, p.adj_split, p.nxq, p.nx, p.ny, p.dx,
                    p.dy};
 }

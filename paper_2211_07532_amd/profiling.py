@@ -9,6 +9,12 @@ under ``rocprofv3 --pmc`` and summaries of rocprofv3's CSV output.
     # kernel durations grouped by kernel and launch grid
     python3 -m paper_2211_07532_amd.profiling trace OUT/*/*_kernel_trace.csv
 
+    # effective shader clock per kernel: GRBM_GUI_ACTIVE (cycles, summed over
+    # the 8 XCDs) over the dispatch's duration, from one run with both
+    rocprofv3 --kernel-trace --pmc GRBM_GUI_ACTIVE GRBM_COUNT --output-format csv -d OUT -- \
+        python3 -m paper_2211_07532_amd.profiling run --forms fp32,fp16 --repeat 10
+    python3 -m paper_2211_07532_amd.profiling clock OUT/*/*_counter_collection.csv OUT/*/*_kernel_trace.csv
+
 The workload copies a 256 MiB buffer (a plain copy of known size, the
 calibration for byte counters) and applies A and A^H once per form to the
 1.5 mm operator (148 x 148, 32 coils, 16384 samples, 16 field terms + dB0),
@@ -41,7 +47,7 @@ def short_name(name: str) -> str:
     return n.split("::")[-1] if "expenc::" in n else n[:60]
 
 
-def run(forms):
+def run(forms, repeat=1):
     import os
     import numpy as np
     import torch
@@ -67,8 +73,9 @@ def run(forms):
         autotune.apply_cached(op, 1, prec)
         if prec != "fp32":
             autotune.apply_cached(op, 1, "fp32")
-        y = ee.forward(x, op, prec)
-        ee.adjoint(y, op, prec)
+        for _ in range(repeat):
+            y = ee.forward(x, op, prec)
+            ee.adjoint(y, op, prec)
     torch.cuda.synchronize()
     print(f"profiling workload done: copy of {COPY_BYTES} bytes, A and A^H for {','.join(forms)}", flush=True)
 
@@ -124,20 +131,48 @@ def pmc(paths):
               ", ".join(f"{k} x{v:.3f}" for k, v in scale.items()))
 
 
+def clock(counter_csv, trace_csv, xcds=8):
+    """Per (kernel, grid): GRBM_GUI_ACTIVE / xcds / duration, the shader clock
+    the kernel ran at (MHz), averaged over its dispatches and over the later
+    half of them (after the clock has settled)."""
+    dur = {}
+    for r in csv.DictReader(open(trace_csv)):
+        dur[r["Dispatch_Id"]] = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    rows = OrderedDict()
+    for r in csv.DictReader(open(counter_csv)):
+        if r["Counter_Name"] != "GRBM_GUI_ACTIVE" or r["Dispatch_Id"] not in dur:
+            continue
+        key = (short_name(r["Kernel_Name"]), r.get("Grid_Size", ""))
+        d = dur[r["Dispatch_Id"]]
+        rows.setdefault(key, []).append((d, float(r["Counter_Value"]) / xcds / d / 1e6))
+    print("| kernel | grid | dispatches | avg us | MHz (all) | MHz (later half) |")
+    print("|---|---|---|---|---|---|")
+    for (k, g), v in rows.items():
+        late = v[len(v) // 2:]
+        print(f"| {k} | {g} | {len(v)} | {1e6 * sum(d for d, _ in v) / len(v):.1f} | "
+              f"{sum(m for _, m in v) / len(v):.0f} | {sum(m for _, m in late) / len(late):.0f} |")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(prog="python -m paper_2211_07532_amd.profiling")
     sub = ap.add_subparsers(dest="cmd", required=True)
     r = sub.add_parser("run")
     r.add_argument("--forms", default="fp32,fp16")
+    r.add_argument("--repeat", type=int, default=1)
     t = sub.add_parser("trace")
     t.add_argument("csv", nargs="+")
     c = sub.add_parser("pmc")
     c.add_argument("csv", nargs="+")
+    k = sub.add_parser("clock")
+    k.add_argument("counter_csv")
+    k.add_argument("trace_csv")
     a = ap.parse_args(argv)
     if a.cmd == "run":
-        run([f for f in a.forms.split(",") if f])
+        run([f for f in a.forms.split(",") if f], a.repeat)
     elif a.cmd == "trace":
         trace(a.csv)
+    elif a.cmd == "clock":
+        clock(a.counter_csv, a.trace_csv)
     else:
         pmc(a.csv)
 
