@@ -42,15 +42,15 @@ N_POWER = 20
 # 256 MiB copy.  Valid only for the kernel source and launch shape they were
 # taken on: `sha` is the SHA-256 of the files the kernel is built from.
 TRAFFIC = {
-    "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290755072,
+    "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290733445,
              "valu_instr": 158732000, "fwd_valu_instr": 121229000,
-             "sha": "6acaf85201e55d0555733c9f1b6641a0cc073090c5dfa7d82e3cc044a29720d1"},
-    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 89606349,
-             "valu_instr": 93196400, "fwd_valu_instr": 106418000,
-             "sha": "6088a9a3bd153b5ed0730aa5e3c3d4db94509c0f7f0cc8bc3247bb0a4e42e12a"},
-    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 89587302,
-             "valu_instr": 74911900, "fwd_valu_instr": 87461900,
-             "sha": "6088a9a3bd153b5ed0730aa5e3c3d4db94509c0f7f0cc8bc3247bb0a4e42e12a"},
+             "sha": "1ed65a2851177be4464908bfd4e8a3c71a0ee1d51e211d17be1192d9d3690979"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 137457664,
+             "valu_instr": 65483900, "fwd_valu_instr": 106418000,
+             "sha": "b0fc440bf902c24a9224727a8a7d2ad4a499c6a4bbc43452a09c06faeb83884d"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 137516237,
+             "valu_instr": 65483900, "fwd_valu_instr": 87461900,
+             "sha": "b0fc440bf902c24a9224727a8a7d2ad4a499c6a4bbc43452a09c06faeb83884d"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],

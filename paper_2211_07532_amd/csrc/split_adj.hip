@@ -18,6 +18,7 @@ struct AdjShArgs {
   int64_t Tp;
   int Rp, NCP, chunk, nsplit, nxq, nx, ny;
   double dx, dy;
+  Bf16Masks mk;
 };
 
 // One workgroup of the adjoint (workgroup bx, by, bz of a grid with gy
@@ -115,8 +116,8 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
             c2[e] = __builtin_amdgcn_cosf(f);
             s2[e] = __builtin_amdgcn_sinf(f);
           }
-          split_pair<BF>(c2[0], c2[1], w[0][m], w[1][m]);
-          split_pair<BF>(s2[0], s2[1], w[2][m], w[3][m]);
+          split_pair<BF>(c2[0], c2[1], w[0][m], w[1][m], a.mk);
+          split_pair<BF>(s2[0], s2[1], w[2][m], w[3][m], a.mk);
         }
         const u32x4 A[4] = {u32x4{w[0][0], w[0][1], w[0][2], w[0][3]}, u32x4{w[1][0], w[1][1], w[1][2], w[1][3]},
                             u32x4{w[2][0], w[2][1], w[2][2], w[2][3]}, u32x4{w[3][0], w[3][1], w[3][2], w[3][3]}};
@@ -128,9 +129,9 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
   adj_epilogue<GW>(part, sq, Rp, NCP, nsplit, split, pz, by, gy, row0, g0, lane, acc);
 }
 
-// The bf16 build needs a few more registers than the fp16 one; it is held to
-// three waves per SIMD (at the cost of spilling two registers), which
-// measured 3 % faster than the two waves it would otherwise get.
+// The bf16 build is held to three waves per SIMD: left to itself the
+// compiler may take a few more registers than that allows, and two waves
+// per SIMD measured 3 % slower.
 template <int GW, bool BF>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh(AdjShArgs a) {
   adj_split_sh_body<GW, BF>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
@@ -154,7 +155,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1)
 static AdjShArgs adj_sh_args(const EncPlan &p, const EncBuffers &b) {
   return AdjShArgs{b.anc, b.dpa, b.dwq, reinterpret_cast<const u32x4 *>(b.ys), reinterpret_cast<float *>(b.part),
                    p.comb ? b.sq : nullptr, p.Tp, p.Rp, p.NCP, p.adj_chunk, p.adj_split, p.nxq, p.nx, p.ny, p.dx,
-                   p.dy};
+                   p.dy, bf16_masks()};
 }
 
 template <bool BF>

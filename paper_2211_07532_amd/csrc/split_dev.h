@@ -40,6 +40,34 @@ __device__ inline void split_pair(float a, float b, uint32_t &hi, uint32_t &lo) 
   }
 }
 
+// Masks of the bf16 remainder below, (-1, 0) and (0, -1) as packed bf16
+// pairs.  They reach the kernels as arguments (scalar registers): written as
+// constants, the compiler encodes (-1, 0) as the inline constant -1.0, which
+// the dot-product instruction reads as the FP32 pattern 0xbf800000, (0, -1).
+struct Bf16Masks {
+  uint32_t lo, hi;
+};
+inline Bf16Masks bf16_masks() { return Bf16Masks{0x0000bf80u, 0xbf800000u}; }
+
+// split_pair with the bf16 remainders v - hi from a two-term bf16 dot
+// product, (hi_a, hi_b) . (-1, 0) + a and (hi_a, hi_b) . (0, -1) + b: one
+// instruction per value instead of widening hi and subtracting (exact: the
+// product is exact and hi is within a factor 2 of v).  Same bits as
+// split_pair<true>; fp16 pairs go to split_pair<false>.
+template <bool BF>
+__device__ inline void split_pair(float a, float b, uint32_t &hi, uint32_t &lo, Bf16Masks mk) {
+  if constexpr (BF) {
+    const bf16x2 h = {(__bf16)a, (__bf16)b};
+    hi = __builtin_bit_cast(uint32_t, h);
+    const float la = __builtin_amdgcn_fdot2_f32_bf16(h, __builtin_bit_cast(bf16x2, mk.lo), a, false);
+    const float lb = __builtin_amdgcn_fdot2_f32_bf16(h, __builtin_bit_cast(bf16x2, mk.hi), b, false);
+    const bf16x2 l = {(__bf16)la, (__bf16)lb};
+    lo = __builtin_bit_cast(uint32_t, l);
+  } else {
+    split_pair<false>(a, b, hi, lo);
+  }
+}
+
 template <bool BF>
 __device__ inline f32x16 mfma16(u32x4 a, u32x4 b, f32x16 c) {
   if constexpr (BF)
