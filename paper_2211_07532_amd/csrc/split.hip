@@ -734,7 +734,16 @@ __global__ void k_prep_pmono(const double *__restrict__ kap, int NT, int L, int6
 // 32-sample tile q, lane l and term pair J, the entry is
 // pmono[t][k] - pmono[32q + 16][k] with t = 32q + l%32, k = 2J + l/32 (k <= 10),
 // and 1 for k = 11 (the term that carries the per-pixel anchor).
-__global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, float *__restrict__ dpa) {
+//
+// Row layout (rows): when every 32-pixel block of the adjoint lies in one
+// image row y, the increment is a cubic in x whose coefficients are
+// polynomials in y, C_0 = d0 + d2 y + d5 y^2 + d9 y^3, C_1 = d1 + d4 y + d8 y^2,
+// C_2 = d3 + d7 y, C_3 = d6 (d_m the differences above, monomials in pmono
+// order), plus d10 dw0 and the anchor: rank 6.  Lane l holds, for its sample
+// and half hl = l/32, the coefficients the kernel evaluates at the block's y:
+// [0..3] the cubic in y of C_hl, [4..5] the linear one of C_{2+hl}, [6] d10
+// (hl = 0, the dw0 term) or 1 (hl = 1, the anchor term).
+__global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, bool rows, float *__restrict__ dpa) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Tp / 32 * 64) return;
   pmono += blockIdx.y * Tp * 12;  // problem
@@ -743,12 +752,22 @@ __global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, float *
   const int l = (int)(i & 63);
   const int64_t t = 32 * q + (l & 31), ta = 32 * q + 16;
   float v[8];
+  if (rows) {
+    double d[11];
+    for (int m = 0; m <= 10; ++m) d[m] = pmono[t * 12 + m] - pmono[ta * 12 + m];
+    const bool hl = (l >> 5) != 0;
+    const double c[7] = {hl ? d[1] : d[0], hl ? d[4] : d[2], hl ? d[8] : d[5], hl ? 0.0 : d[9],
+                         hl ? d[6] : d[3], hl ? 0.0 : d[7], hl ? 1.0 : d[10]};
+    for (int j = 0; j < 7; ++j) v[j] = (float)c[j];
+    v[7] = 0.f;
+  } else {
 #pragma unroll
-  for (int J = 0; J < 6; ++J) {
-    const int k = 2 * J + (l >> 5);
-    v[J] = k <= 10 ? (float)(pmono[t * 12 + k] - pmono[ta * 12 + k]) : 1.0f;
+    for (int J = 0; J < 6; ++J) {
+      const int k = 2 * J + (l >> 5);
+      v[J] = k <= 10 ? (float)(pmono[t * 12 + k] - pmono[ta * 12 + k]) : 1.0f;
+    }
+    v[6] = v[7] = 0.f;
   }
-  v[6] = v[7] = 0.f;
   float4 *o = reinterpret_cast<float4 *>(dpa + i * 8);
   o[0] = make_float4(v[0], v[1], v[2], v[3]);
   o[1] = make_float4(v[4], v[5], v[6], v[7]);
@@ -811,7 +830,7 @@ int sh_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipSt
   k_prep_pmono<<<gp(p.Tp), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), p.z0s, b.pmono);
   EX_LAUNCHED("monomial coefficients");
   if (p.prec != EXPENC_FP32) {
-    k_prep_dpa<<<gp(p.Tp / 32 * 64), 256, 0, s>>>(b.pmono, p.Tp, b.dpa);
+    k_prep_dpa<<<gp(p.Tp / 32 * 64), 256, 0, s>>>(b.pmono, p.Tp, p.adj_rows, b.dpa);
     EX_LAUNCHED("increment table (samples)");
   }
   k_prep_dwq<<<gp(p.Rp), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);

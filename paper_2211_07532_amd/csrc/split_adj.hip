@@ -2,6 +2,8 @@
 // polynomial form (the polynomial forms and the split arithmetic are
 // described in split.hip).  It sits in a translation unit of its own so that
 // it can be built with its own code-generation options.
+#include <vector>
+
 #include "internal.h"
 #include "split_dev.h"
 
@@ -22,8 +24,9 @@ struct AdjShArgs {
 };
 
 // One workgroup of the adjoint (workgroup bx, by, bz of a grid with gy
-// column groups).
-template <int GW, bool BF>
+// column groups).  ROWS: every 32-pixel block lies in one image row and the
+// increment product has rank 6 (the row layout of dpa, see k_prep_dpa).
+template <int GW, bool BF, bool ROWS>
 __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int bz, int gy) {
   const float *__restrict__ anc = a.anc;
   const float *__restrict__ dpa = a.dpa;
@@ -49,18 +52,27 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
   ys += pz * Tp * NGP * 16;
   // this lane's pixel in each 32-row block, and its B operand of the
   // increment product: the monomial (or dw0) of term 2J + hl
-  float bm[2][6];
+  constexpr int NJ = ROWS ? 3 : 6;  // term pairs
+  float bm[2][NJ];
+  float yb[2];  // ROWS: the block's image row y
 #pragma unroll
   for (int blk = 0; blk < 2; ++blk) {
     const int rq = (int)(row0 + 32 * blk + jl);
     const double x = (rq % nxq - 0.5 * nx) * dx, y = (rq / nxq - 0.5 * ny) * dy, w = dwq[rq];
-    // terms 0..11: 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3, dw0, anchor
-    bm[blk][0] = (float)(hl ? x : 1.0);
-    bm[blk][1] = (float)(hl ? x * x : y);
-    bm[blk][2] = (float)(hl ? y * y : x * y);
-    bm[blk][3] = (float)(hl ? x * x * y : x * x * x);
-    bm[blk][4] = (float)(hl ? y * y * y : x * y * y);
-    bm[blk][5] = (float)w;  // lanes 32..63 replace it by the anchor per step
+    yb[blk] = (float)y;
+    if constexpr (ROWS) {
+      // terms 0..5: 1, x, x^2, x^3, dw0, anchor
+      bm[blk][0] = (float)(hl ? x : 1.0);
+      bm[blk][1] = (float)(hl ? x * x * x : x * x);
+    } else {
+      // terms 0..11: 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3, dw0, anchor
+      bm[blk][0] = (float)(hl ? x : 1.0);
+      bm[blk][1] = (float)(hl ? x * x : y);
+      bm[blk][2] = (float)(hl ? y * y : x * y);
+      bm[blk][3] = (float)(hl ? x * x * y : x * x * x);
+      bm[blk][4] = (float)(hl ? y * y * y : x * y * y);
+    }
+    bm[blk][NJ - 1] = (float)w;  // lanes 32..63 replace it by the anchor per step
   }
   f32x16 acc[2][GW];
 #pragma unroll
@@ -75,7 +87,21 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
     // A operand of the increment product (this lane's sample, terms 2J + hl)
     const float4 *ap = reinterpret_cast<const float4 *>(dpa + ((t >> 5) * 64 + lane) * 8);
     const float4 a03 = ap[0], a47 = ap[1];
-    const float av[6] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y};
+    float av[2][NJ];
+#pragma unroll
+    for (int blk = 0; blk < 2; ++blk) {
+      if constexpr (ROWS) {
+        // C_hl and C_{2+hl} at the block's row, then d10 or 1
+        const float y = yb[blk];
+        av[blk][0] = fmaf(y, fmaf(y, fmaf(y, a03.w, a03.z), a03.y), a03.x);
+        av[blk][1] = fmaf(y, a47.y, a47.x);
+        av[blk][2] = a47.z;
+      } else {
+        const float v[6] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y};
+#pragma unroll
+        for (int J = 0; J < 6; ++J) av[blk][J] = v[J];
+      }
+    }
     // anchor: FP64 phase of the tile's centre sample at this lane's pixels
     // in turns (from the table); it enters the product as term 11 (A = 1)
     const float *ap2 = anc + (t >> 5) * Rp + row0 + jl;
@@ -83,12 +109,13 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
     f32x16 ph[2];
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-      const float b5 = hl ? an[blk] : bm[blk][5];
+      const float bl = hl ? an[blk] : bm[blk][NJ - 1];
 #pragma unroll
       for (int v = 0; v < 16; ++v) ph[blk][v] = 0.f;
 #pragma unroll
-      for (int J = 0; J < 5; ++J) ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[J], bm[blk][J], ph[blk], 0, 0, 0);
-      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[5], b5, ph[blk], 0, 0, 0);
+      for (int J = 0; J < NJ - 1; ++J)
+        ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[blk][J], bm[blk][J], ph[blk], 0, 0, 0);
+      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[blk][NJ - 1], bl, ph[blk], 0, 0, 0);
     }
     // two contraction steps of 16 samples; ph[blk][8h + i] is sample
     // 16h + 8(i/4) + 4hl + i%4 of pixel jl, which is K index 8hl + i of
@@ -132,14 +159,14 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
 // The bf16 build is held to three waves per SIMD: left to itself the
 // compiler may take a few more registers than that allows, and two waves
 // per SIMD measured 3 % slower.
-template <int GW, bool BF>
+template <int GW, bool BF, bool ROWS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh(AdjShArgs a) {
-  adj_split_sh_body<GW, BF>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
+  adj_split_sh_body<GW, BF, ROWS>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
 }
 
 // Persistent form over several problem groups (the forward's grouped kernel
 // in split.hip describes the numbering and why the XCD mapping holds).
-template <int GW, bool BF>
+template <int GW, bool BF, bool ROWS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh_grouped(
     GroupedLaunch<AdjShArgs> G) {
   for (int64_t t = blockIdx.x; t < G.off[G.ng]; t += gridDim.x) {
@@ -148,7 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1)
     const int64_t l = t - G.off[g];
     const int gx = G.gx[g], gy = G.gy[g];
     const int64_t q = l / gx;
-    adj_split_sh_body<GW, BF>(G.a[g], (int)(l - q * gx), (int)(q % gy), (int)(q / gy), gy);
+    adj_split_sh_body<GW, BF, ROWS>(G.a[g], (int)(l - q * gx), (int)(q % gy), (int)(q / gy), gy);
   }
 }
 
@@ -158,19 +185,19 @@ static AdjShArgs adj_sh_args(const EncPlan &p, const EncBuffers &b) {
                    p.dy, bf16_masks()};
 }
 
-template <bool BF>
+template <bool BF, bool ROWS>
 static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   const AdjShArgs a = adj_sh_args(p, b);
   if (p.GW == 2)
-    k_adj_split_sh<2, BF><<<grid, 256, 0, s>>>(a);
+    k_adj_split_sh<2, BF, ROWS><<<grid, 256, 0, s>>>(a);
   else
-    k_adj_split_sh<1, BF><<<grid, 256, 0, s>>>(a);
+    k_adj_split_sh<1, BF, ROWS><<<grid, 256, 0, s>>>(a);
 }
 
-template <int GW, bool BF>
+template <int GW, bool BF, bool ROWS>
 static int adj_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
-  const void *kern = reinterpret_cast<const void *>(&k_adj_split_sh_grouped<GW, BF>);
+  const void *kern = reinterpret_cast<const void *>(&k_adj_split_sh_grouped<GW, BF, ROWS>);
   GroupedLaunch<AdjShArgs> G{};
   G.ng = n;
   G.off[0] = 0;
@@ -182,30 +209,49 @@ static int adj_grouped(const EncPlan *const *p, const EncBuffers *const *b, int 
   }
   unsigned grid = 0;
   EX_TRY(persistent_grid(kern, G.off[n], &grid));
-  k_adj_split_sh_grouped<GW, BF><<<grid, 256, 0, s>>>(G);
+  k_adj_split_sh_grouped<GW, BF, ROWS><<<grid, 256, 0, s>>>(G);
   EX_LAUNCHED("grouped adjoint contraction");
   return EXPENC_OK;
 }
 
-int split_adjoint_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
+// Grouped adjoint launches (chunks of kMaxGrouped) of plans that share the
+// row layout flag.
+static int adj_grouped_class(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
   for (int i = 0; i < n; i += kMaxGrouped) {
     const int m = std::min(kMaxGrouped, n - i);
-    for (int g = i; g < i + m; ++g)
-      if (!split_groupable(*p[i], *p[g])) return fail(EXPENC_EINVAL, "plans of a grouped launch differ in shape");
-    const bool bf = p[i]->prec == EXPENC_BF16_SPLIT;
+    const bool bf = p[i]->prec == EXPENC_BF16_SPLIT, rows = p[i]->adj_rows;
     int rc;
-    if (p[i]->GW == 2) rc = bf ? adj_grouped<2, true>(p + i, b + i, m, s) : adj_grouped<2, false>(p + i, b + i, m, s);
-    else rc = bf ? adj_grouped<1, true>(p + i, b + i, m, s) : adj_grouped<1, false>(p + i, b + i, m, s);
+    if (p[i]->GW == 2) {
+      if (rows) rc = bf ? adj_grouped<2, true, true>(p + i, b + i, m, s) : adj_grouped<2, false, true>(p + i, b + i, m, s);
+      else rc = bf ? adj_grouped<2, true, false>(p + i, b + i, m, s) : adj_grouped<2, false, false>(p + i, b + i, m, s);
+    } else {
+      if (rows) rc = bf ? adj_grouped<1, true, true>(p + i, b + i, m, s) : adj_grouped<1, false, true>(p + i, b + i, m, s);
+      else rc = bf ? adj_grouped<1, true, false>(p + i, b + i, m, s) : adj_grouped<1, false, false>(p + i, b + i, m, s);
+    }
     EX_TRY(rc);
   }
   return EXPENC_OK;
 }
 
+int split_adjoint_grouped(const EncPlan *const *pall, const EncBuffers *const *ball, int nall, hipStream_t s) {
+  // the row-layout groups and the others take kernels of their own
+  std::vector<const EncPlan *> pv[2];
+  std::vector<const EncBuffers *> bv[2];
+  for (int g = 0; g < nall; ++g) {
+    if (!split_groupable(*pall[0], *pall[g])) return fail(EXPENC_EINVAL, "plans of a grouped launch differ in shape");
+    pv[pall[g]->adj_rows].push_back(pall[g]);
+    bv[pall[g]->adj_rows].push_back(ball[g]);
+  }
+  for (int cls = 0; cls < 2; ++cls) EX_TRY(adj_grouped_class(pv[cls].data(), bv[cls].data(), (int)pv[cls].size(), s));
+  return EXPENC_OK;
+}
+
 void split_adjoint_sh_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
-  if (p.prec == EXPENC_BF16_SPLIT)
-    adj_split_sh<true>(p, b, s);
+  const bool bf = p.prec == EXPENC_BF16_SPLIT;
+  if (p.adj_rows)
+    bf ? adj_split_sh<true, true>(p, b, s) : adj_split_sh<false, true>(p, b, s);
   else
-    adj_split_sh<false>(p, b, s);
+    bf ? adj_split_sh<true, false>(p, b, s) : adj_split_sh<false, false>(p, b, s);
 }
 
 }  // namespace expenc
