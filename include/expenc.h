@@ -473,11 +473,8 @@ int expenc_set_launch_shape(const expenc_op *op, int32_t batch, int32_t precisio
                             int32_t adj_target, int32_t col_groups);
 
 /*
- * expenc_plan_info writing min(n_out, 8) values: out[0..5] as there,
- * out[6] = the column width in 16-column groups per wave and out[7] = 1 when
- * the split adjoint of the solid-harmonic kind runs in its row layout (every
- * 32-pixel block inside one image row, i.e. nx rounded up to 16 is a
- * multiple of 32: rank-6 phase increments), else 0.
+ * expenc_plan_info writing min(n_out, 7) values: out[0..5] as there and
+ * out[6] = the column width in 16-column groups per wave.
  */
 int expenc_plan_info_ex(const expenc_op *op, int32_t batch, int32_t precision, int32_t nprob, int64_t *out,
                         int32_t n_out);

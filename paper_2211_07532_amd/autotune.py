@@ -85,11 +85,11 @@ def set_targets(op: _e.Operator, batch: int, precision, fwd_target: int, adj_tar
 
 
 def plan_info(op: _e.Operator, batch: int = 1, precision="fp32", nprob: int = 1) -> dict:
-    out = (ctypes.c_int64 * 8)()
-    _b.check(_b.lib().expenc_plan_info_ex(ctypes.byref(op._c), batch, _e._prec(precision), nprob, out, 8),
+    out = (ctypes.c_int64 * 7)()
+    _b.check(_b.lib().expenc_plan_info_ex(ctypes.byref(op._c), batch, _e._prec(precision), nprob, out, 7),
              "expenc_plan_info_ex")
     return {"fwd_split": out[0], "adj_split": out[1], "fwd_workgroups": out[2], "adj_workgroups": out[3],
-            "fwd_split_max": out[4], "adj_split_max": out[5], "col_groups": out[6], "adj_rows": out[7]}
+            "fwd_split_max": out[4], "adj_split_max": out[5], "col_groups": out[6]}
 
 
 @dataclasses.dataclass

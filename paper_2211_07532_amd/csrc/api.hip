@@ -394,15 +394,14 @@ extern "C" int expenc_plan_info_ex(const expenc_op *op, int32_t batch, int32_t p
   if (n_out < 0) return fail(EXPENC_EINVAL, "n_out must be >= 0");
   EncPlan p;
   EX_TRY(make_plan(op, batch, precision, &p, nprob));
-  const int64_t v[8] = {p.fwd_split,
+  const int64_t v[7] = {p.fwd_split,
                         p.adj_split,
                         (int64_t)p.Tp / 256 * p.fwd_split * p.NGY * p.P,  // forward workgroups per launch
                         (int64_t)p.Rp / 256 * p.adj_split * p.NGY * p.P,  // adjoint workgroups per launch
                         p.Rp / 16,                                        // largest forward split
                         p.Tp / 16,                                        // largest adjoint split
-                        p.GW,                                             // 16-column groups per wave
-                        p.adj_rows ? 1 : 0};                              // row-layout split adjoint
-  for (int i = 0; i < n_out && i < 8; ++i) out[i] = v[i];
+                        p.GW};                                            // 16-column groups per wave
+  for (int i = 0; i < n_out && i < 7; ++i) out[i] = v[i];
   return EXPENC_OK;
 }
 

@@ -766,7 +766,6 @@ int make_plan(const expenc_op *op, int32_t batch, int32_t precision, EncPlan *p,
   q.P = nprob;
   q.scaled = precision == EXPENC_FP16_SPLIT;
   q.adj_anc = q.sh && precision != EXPENC_FP32;
-  q.adj_rows = q.adj_anc && q.nxq % 32 == 0;
   // forward: 256 sample rows per workgroup, split over pixels
   {
     int64_t nrb = q.Tp / 256 * q.P;
@@ -812,7 +811,6 @@ int plan_forward_within(const expenc_op *op, int32_t batch, int32_t precision, s
   // the forward uses no adjoint partial sums: one adjoint split keeps them small
   q.adj_split = 1;
   q.adj_anc = false;
-  q.adj_rows = false;
   q.adj_chunk = (int32_t)q.Tp;
   const int32_t min_split = q.prec == EXPENC_FP32 ? (int32_t)ceil_div(q.Rp, kF32ChunkMax) : 1;
   auto set_split = [&](int32_t want) {

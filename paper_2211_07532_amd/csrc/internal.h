@@ -244,10 +244,6 @@ struct EncPlan {
   // its per-tile FP64 phase anchors from a table built at preparation
   // (EncBuffers::anc); off for forward-only plans
   bool adj_anc = false;
-  // ... and when every 32-pixel block of the adjoint lies in one image row
-  // (nxq a multiple of 32), it forms the phase increments from per-row
-  // polynomial coefficients (rank 6 instead of 12; dpa in the row layout)
-  bool adj_rows = false;
   bool has_dw0 = false;
   // Solid-harmonic basis given by grid geometry (EXPENC_BASIS_SH).  Split
   // forms with it lay pixels out row-padded: r' = y*nxq + x, nxq = nx rounded
@@ -291,7 +287,7 @@ struct EncBuffers {
   float *dbet = nullptr;   // split forms: [Rp][NT] bet minus its 16-row tile centre (FP32)
   float *dkap = nullptr;   // split forms: [Tp][NT] kap minus its 16-row tile centre (FP32)
   double *pmono = nullptr; // split + SH: [Tp][12] cubic-monomial phase coefficients (turns) and t
-  float *dpa = nullptr;    // split + SH: [Tp/32][64][8] adjoint increment operand (FP32; row layout with adj_rows)
+  float *dpa = nullptr;    // split + SH: [Tp/32][64][8] adjoint increment coefficients (FP32, per lane)
   double *dwq = nullptr;   // split + SH: [Rp] dw0/2pi in the row-padded pixel layout
   float *ddw = nullptr;    // split + SH: [Rp] dwq minus its 16-pixel tile centre (FP32)
   float *anc = nullptr;    // split + SH, adj_anc: [Tp/32][Rp] FP64 phase of each 32-sample tile's centre

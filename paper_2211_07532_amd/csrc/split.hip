@@ -248,13 +248,16 @@ __global__ __launch_bounds__(256) void k_adj_split(const double *__restrict__ ka
 // one for the off-resonance difference t (dw0(r) - dw0(r_c)) / 2pi.
 //
 // Adjoint (32 samples x 64 pixels per wave and step): the phase is the
-// FP64 anchor of the tile's centre sample t_c at each pixel plus the
-// increment sum_m (P_m(t) - P_m(t_c)) mono_m(r) + (t - t_c) dw0(r)/2pi, a
-// rank-11 product of a [32 samples x 12] table with a [12 x 32 pixels]
-// operand.  The increments therefore run on the matrix cores as six
-// v_mfma_f32_32x32x2_f32 per 32-pixel block (term 11 carries the anchor
-// with a unit A entry), instead of eleven FP32 FMAs per entry on the vector
-// unit.  The product's output layout gives each lane 16 samples of ONE
+// FP64 anchor of the tile's centre sample t_c at each pixel (a table written
+// at preparation) plus the increment sum_m (P_m(t) - P_m(t_c)) mono_m(r) +
+// (t - t_c) dw0(r)/2pi.  Inside one image row the increment is a cubic in x
+// whose four coefficients are polynomials in the row's y, so for a block of
+// 32 pixels of one row it is a rank-6 product (the cubic, dw0 and the
+// anchor with a unit A entry) of a [32 samples x 6] operand, evaluated per
+// block from per-sample coefficients, with a [6 x 32 pixels] operand: three
+// v_mfma_f32_32x32x2_f32 per block (five for a block that continues into
+// the next row), instead of eleven FP32 FMAs per entry on the vector unit.
+// The product's output layout gives each lane 16 samples of ONE
 // pixel, which is the A-operand layout of the contraction up to a fixed
 // permutation of the samples inside each group of 16; the adjoint records
 // are packed in that order, so no exchange between lanes is needed.
@@ -730,20 +733,17 @@ __global__ void k_prep_pmono(const double *__restrict__ kap, int NT, int L, int6
   for (int m = 0; m < 12; ++m) pmono[t * 12 + m] = out[m];
 }
 
-// A operand of the adjoint's phase-increment product, in lane order: for the
-// 32-sample tile q, lane l and term pair J, the entry is
-// pmono[t][k] - pmono[32q + 16][k] with t = 32q + l%32, k = 2J + l/32 (k <= 10),
-// and 1 for k = 11 (the term that carries the per-pixel anchor).
-//
-// Row layout (rows): when every 32-pixel block of the adjoint lies in one
-// image row y, the increment is a cubic in x whose coefficients are
-// polynomials in y, C_0 = d0 + d2 y + d5 y^2 + d9 y^3, C_1 = d1 + d4 y + d8 y^2,
-// C_2 = d3 + d7 y, C_3 = d6 (d_m the differences above, monomials in pmono
-// order), plus d10 dw0 and the anchor: rank 6.  Lane l holds, for its sample
-// and half hl = l/32, the coefficients the kernel evaluates at the block's y:
+// A operand of the adjoint's phase-increment product, in lane order.  For the
+// 32-sample tile q and lane l (sample t = 32q + l%32, half hl = l/32), with
+// d_m = pmono[t][m] - pmono[32q + 16][m] (monomials in pmono order), the
+// increment at a pixel of image row y is the cubic in x
+//   C_0 + C_1 x + C_2 x^2 + C_3 x^3 + d10 dw0,
+//   C_0 = d0 + d2 y + d5 y^2 + d9 y^3,  C_1 = d1 + d4 y + d8 y^2,
+//   C_2 = d3 + d7 y,                    C_3 = d6,
+// and lane l holds the coefficients the adjoint evaluates at a block's row:
 // [0..3] the cubic in y of C_hl, [4..5] the linear one of C_{2+hl}, [6] d10
 // (hl = 0, the dw0 term) or 1 (hl = 1, the anchor term).
-__global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, bool rows, float *__restrict__ dpa) {
+__global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, float *__restrict__ dpa) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= Tp / 32 * 64) return;
   pmono += blockIdx.y * Tp * 12;  // problem
@@ -751,23 +751,14 @@ __global__ void k_prep_dpa(const double *__restrict__ pmono, int64_t Tp, bool ro
   const int64_t q = i >> 6;
   const int l = (int)(i & 63);
   const int64_t t = 32 * q + (l & 31), ta = 32 * q + 16;
+  double d[11];
+  for (int m = 0; m <= 10; ++m) d[m] = pmono[t * 12 + m] - pmono[ta * 12 + m];
+  const bool hl = (l >> 5) != 0;
+  const double c[7] = {hl ? d[1] : d[0], hl ? d[4] : d[2], hl ? d[8] : d[5], hl ? 0.0 : d[9],
+                       hl ? d[6] : d[3], hl ? 0.0 : d[7], hl ? 1.0 : d[10]};
   float v[8];
-  if (rows) {
-    double d[11];
-    for (int m = 0; m <= 10; ++m) d[m] = pmono[t * 12 + m] - pmono[ta * 12 + m];
-    const bool hl = (l >> 5) != 0;
-    const double c[7] = {hl ? d[1] : d[0], hl ? d[4] : d[2], hl ? d[8] : d[5], hl ? 0.0 : d[9],
-                         hl ? d[6] : d[3], hl ? 0.0 : d[7], hl ? 1.0 : d[10]};
-    for (int j = 0; j < 7; ++j) v[j] = (float)c[j];
-    v[7] = 0.f;
-  } else {
-#pragma unroll
-    for (int J = 0; J < 6; ++J) {
-      const int k = 2 * J + (l >> 5);
-      v[J] = k <= 10 ? (float)(pmono[t * 12 + k] - pmono[ta * 12 + k]) : 1.0f;
-    }
-    v[6] = v[7] = 0.f;
-  }
+  for (int j = 0; j < 7; ++j) v[j] = (float)c[j];
+  v[7] = 0.f;
   float4 *o = reinterpret_cast<float4 *>(dpa + i * 8);
   o[0] = make_float4(v[0], v[1], v[2], v[3]);
   o[1] = make_float4(v[4], v[5], v[6], v[7]);
@@ -830,7 +821,7 @@ int sh_prepare(const EncPlan &p, const expenc_op *op, const EncBuffers &b, hipSt
   k_prep_pmono<<<gp(p.Tp), 256, 0, s>>>(b.kap, p.NT, p.L, p.Tp, mono_matrix(p.z0), p.z0s, b.pmono);
   EX_LAUNCHED("monomial coefficients");
   if (p.prec != EXPENC_FP32) {
-    k_prep_dpa<<<gp(p.Tp / 32 * 64), 256, 0, s>>>(b.pmono, p.Tp, p.adj_rows, b.dpa);
+    k_prep_dpa<<<gp(p.Tp / 32 * 64), 256, 0, s>>>(b.pmono, p.Tp, b.dpa);
     EX_LAUNCHED("increment table (samples)");
   }
   k_prep_dwq<<<gp(p.Rp), 256, 0, s>>>(op->dw0, p.nx, p.ny, p.nxq, p.Rp, b.dwq);

@@ -24,9 +24,21 @@ struct AdjShArgs {
 };
 
 // One workgroup of the adjoint (workgroup bx, by, bz of a grid with gy
-// column groups).  ROWS: every 32-pixel block lies in one image row and the
-// increment product has rank 6 (the row layout of dpa, see k_prep_dpa).
-template <int GW, bool BF, bool ROWS>
+// column groups).
+//
+// Phase of a 32-sample x 32-pixel block: the FP64 anchor of the tile's centre
+// sample at each pixel (table anc) plus the increment over the tile.  With
+// the pixels of the block in one image row y the increment is a cubic in x,
+// sum_k C_k(t, y) x^k + d10(t) dw0, whose coefficients are polynomials in y
+// (k_prep_dpa): a rank-6 product, three v_mfma_f32_32x32x2_f32 with terms
+// (1 | x), (x^2 | x^3), (dw0 | anchor) against (C_0 | C_1), (C_2 | C_3),
+// (d10 | 1) evaluated at the block's row.  A block that continues into the
+// next row (when the padded row length nxq is not a multiple of 32) adds,
+// for its pixels in that row only, the change of the coefficients between
+// the two rows: E_k = C_k(t, y1) - C_k(t, y0) against (1 | x), (x^2 | 0) on
+// those pixels and 0 on the others (E_3 = 0: C_3 does not depend on y), two
+// more products; CROSS instantiates that case (nxq not a multiple of 32).
+template <int GW, bool BF, bool CROSS>
 __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int bz, int gy) {
   const float *__restrict__ anc = a.anc;
   const float *__restrict__ dpa = a.dpa;
@@ -50,29 +62,25 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
   dpa += pz * Tp * 16;
   dwq += (int64_t)pz * Rp;
   ys += pz * Tp * NGP * 16;
-  // this lane's pixel in each 32-row block, and its B operand of the
-  // increment product: the monomial (or dw0) of term 2J + hl
-  constexpr int NJ = ROWS ? 3 : 6;  // term pairs
-  float bm[2][NJ];
-  float yb[2];  // ROWS: the block's image row y
+  // this lane's pixel in each 32-pixel block and its B operands: terms
+  // 2J + hl of the row product, and of the next-row correction
+  float bm[2][3], bd[2][2];
+  float y0[2], y1[2];  // image rows of the block's first and last pixel
+  bool two[2];         // the block continues into the next row (uniform)
 #pragma unroll
   for (int blk = 0; blk < 2; ++blk) {
-    const int rq = (int)(row0 + 32 * blk + jl);
-    const double x = (rq % nxq - 0.5 * nx) * dx, y = (rq / nxq - 0.5 * ny) * dy, w = dwq[rq];
-    yb[blk] = (float)y;
-    if constexpr (ROWS) {
-      // terms 0..5: 1, x, x^2, x^3, dw0, anchor
-      bm[blk][0] = (float)(hl ? x : 1.0);
-      bm[blk][1] = (float)(hl ? x * x * x : x * x);
-    } else {
-      // terms 0..11: 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3, dw0, anchor
-      bm[blk][0] = (float)(hl ? x : 1.0);
-      bm[blk][1] = (float)(hl ? x * x : y);
-      bm[blk][2] = (float)(hl ? y * y : x * y);
-      bm[blk][3] = (float)(hl ? x * x * y : x * x * x);
-      bm[blk][4] = (float)(hl ? y * y * y : x * y * y);
-    }
-    bm[blk][NJ - 1] = (float)w;  // lanes 32..63 replace it by the anchor per step
+    const int rs = (int)(row0 + 32 * blk), rq = rs + jl;
+    const int r0 = rs / nxq, r1 = (rs + 31) / nxq;
+    const double x = (rq % nxq - 0.5 * nx) * dx, w = dwq[rq];
+    y0[blk] = (float)((r0 - 0.5 * ny) * dy);
+    y1[blk] = (float)((r1 - 0.5 * ny) * dy);
+    two[blk] = r1 != r0;
+    const bool next = rq / nxq != r0;
+    bm[blk][0] = (float)(hl ? x : 1.0);
+    bm[blk][1] = (float)(hl ? x * x * x : x * x);
+    bm[blk][2] = (float)w;  // lanes 32..63 replace it by the anchor per step
+    bd[blk][0] = next ? bm[blk][0] : 0.f;
+    bd[blk][1] = next && !hl ? bm[blk][1] : 0.f;
   }
   f32x16 acc[2][GW];
 #pragma unroll
@@ -84,38 +92,32 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
   const int64_t t0 = (int64_t)split * chunk;
   const int64_t t1 = min(Tp, t0 + chunk);
   for (int64_t t = t0; t < t1; t += 32) {
-    // A operand of the increment product (this lane's sample, terms 2J + hl)
+    // this lane's sample: the coefficients of C_hl(y) (cubic) and
+    // C_{2+hl}(y) (linear), then d10 or 1
     const float4 *ap = reinterpret_cast<const float4 *>(dpa + ((t >> 5) * 64 + lane) * 8);
     const float4 a03 = ap[0], a47 = ap[1];
-    float av[2][NJ];
-#pragma unroll
-    for (int blk = 0; blk < 2; ++blk) {
-      if constexpr (ROWS) {
-        // C_hl and C_{2+hl} at the block's row, then d10 or 1
-        const float y = yb[blk];
-        av[blk][0] = fmaf(y, fmaf(y, fmaf(y, a03.w, a03.z), a03.y), a03.x);
-        av[blk][1] = fmaf(y, a47.y, a47.x);
-        av[blk][2] = a47.z;
-      } else {
-        const float v[6] = {a03.x, a03.y, a03.z, a03.w, a47.x, a47.y};
-#pragma unroll
-        for (int J = 0; J < 6; ++J) av[blk][J] = v[J];
-      }
-    }
     // anchor: FP64 phase of the tile's centre sample at this lane's pixels
-    // in turns (from the table); it enters the product as term 11 (A = 1)
+    // in turns (from the table); it enters the product with A = 1
     const float *ap2 = anc + (t >> 5) * Rp + row0 + jl;
     const float an[2] = {ap2[0], ap2[32]};
     f32x16 ph[2];
 #pragma unroll
     for (int blk = 0; blk < 2; ++blk) {
-      const float bl = hl ? an[blk] : bm[blk][NJ - 1];
+      const float ya = y0[blk];
+      const float c0 = fmaf(ya, fmaf(ya, fmaf(ya, a03.w, a03.z), a03.y), a03.x);
+      const float c1 = fmaf(ya, a47.y, a47.x);
 #pragma unroll
       for (int v = 0; v < 16; ++v) ph[blk][v] = 0.f;
-#pragma unroll
-      for (int J = 0; J < NJ - 1; ++J)
-        ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[blk][J], bm[blk][J], ph[blk], 0, 0, 0);
-      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[blk][NJ - 1], bl, ph[blk], 0, 0, 0);
+      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(c0, bm[blk][0], ph[blk], 0, 0, 0);
+      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(c1, bm[blk][1], ph[blk], 0, 0, 0);
+      ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(a47.z, hl ? an[blk] : bm[blk][2], ph[blk], 0, 0, 0);
+      if (CROSS && two[blk]) {
+        const float yb = y1[blk];
+        const float e0 = fmaf(yb, fmaf(yb, fmaf(yb, a03.w, a03.z), a03.y), a03.x) - c0;
+        const float e1 = fmaf(yb, a47.y, a47.x) - c1;
+        ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(e0, bd[blk][0], ph[blk], 0, 0, 0);
+        ph[blk] = __builtin_amdgcn_mfma_f32_32x32x2f32(e1, bd[blk][1], ph[blk], 0, 0, 0);
+      }
     }
     // two contraction steps of 16 samples; ph[blk][8h + i] is sample
     // 16h + 8(i/4) + 4hl + i%4 of pixel jl, which is K index 8hl + i of
@@ -159,14 +161,14 @@ __device__ inline void adj_split_sh_body(const AdjShArgs &a, int bx, int by, int
 // The bf16 build is held to three waves per SIMD: left to itself the
 // compiler may take a few more registers than that allows, and two waves
 // per SIMD measured 3 % slower.
-template <int GW, bool BF, bool ROWS>
+template <int GW, bool BF, bool CROSS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh(AdjShArgs a) {
-  adj_split_sh_body<GW, BF, ROWS>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
+  adj_split_sh_body<GW, BF, CROSS>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
 }
 
 // Persistent form over several problem groups (the forward's grouped kernel
 // in split.hip describes the numbering and why the XCD mapping holds).
-template <int GW, bool BF, bool ROWS>
+template <int GW, bool BF, bool CROSS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh_grouped(
     GroupedLaunch<AdjShArgs> G) {
   for (int64_t t = blockIdx.x; t < G.off[G.ng]; t += gridDim.x) {
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1)
     const int64_t l = t - G.off[g];
     const int gx = G.gx[g], gy = G.gy[g];
     const int64_t q = l / gx;
-    adj_split_sh_body<GW, BF, ROWS>(G.a[g], (int)(l - q * gx), (int)(q % gy), (int)(q / gy), gy);
+    adj_split_sh_body<GW, BF, CROSS>(G.a[g], (int)(l - q * gx), (int)(q % gy), (int)(q / gy), gy);
   }
 }
 
@@ -185,19 +187,23 @@ static AdjShArgs adj_sh_args(const EncPlan &p, const EncBuffers &b) {
                    p.dy, bf16_masks()};
 }
 
-template <bool BF, bool ROWS>
+// Blocks of 32 pixels continue into the next image row unless the padded row
+// length is a multiple of 32.
+static bool adj_cross(const EncPlan &p) { return p.nxq % 32 != 0; }
+
+template <bool BF, bool CROSS>
 static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   dim3 grid(split_grid((int64_t)p.Rp / 256 * p.adj_split), (unsigned)p.NGY, (unsigned)p.P);
   const AdjShArgs a = adj_sh_args(p, b);
   if (p.GW == 2)
-    k_adj_split_sh<2, BF, ROWS><<<grid, 256, 0, s>>>(a);
+    k_adj_split_sh<2, BF, CROSS><<<grid, 256, 0, s>>>(a);
   else
-    k_adj_split_sh<1, BF, ROWS><<<grid, 256, 0, s>>>(a);
+    k_adj_split_sh<1, BF, CROSS><<<grid, 256, 0, s>>>(a);
 }
 
-template <int GW, bool BF, bool ROWS>
+template <int GW, bool BF, bool CROSS>
 static int adj_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
-  const void *kern = reinterpret_cast<const void *>(&k_adj_split_sh_grouped<GW, BF, ROWS>);
+  const void *kern = reinterpret_cast<const void *>(&k_adj_split_sh_grouped<GW, BF, CROSS>);
   GroupedLaunch<AdjShArgs> G{};
   G.ng = n;
   G.off[0] = 0;
@@ -209,46 +215,44 @@ static int adj_grouped(const EncPlan *const *p, const EncBuffers *const *b, int 
   }
   unsigned grid = 0;
   EX_TRY(persistent_grid(kern, G.off[n], &grid));
-  k_adj_split_sh_grouped<GW, BF, ROWS><<<grid, 256, 0, s>>>(G);
+  k_adj_split_sh_grouped<GW, BF, CROSS><<<grid, 256, 0, s>>>(G);
   EX_LAUNCHED("grouped adjoint contraction");
   return EXPENC_OK;
 }
 
-// Grouped adjoint launches (chunks of kMaxGrouped) of plans that share the
-// row layout flag.
+// Grouped launches (chunks of kMaxGrouped) of plans of one kernel variant.
+template <bool CROSS>
 static int adj_grouped_class(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
   for (int i = 0; i < n; i += kMaxGrouped) {
     const int m = std::min(kMaxGrouped, n - i);
-    const bool bf = p[i]->prec == EXPENC_BF16_SPLIT, rows = p[i]->adj_rows;
+    const bool bf = p[i]->prec == EXPENC_BF16_SPLIT;
     int rc;
-    if (p[i]->GW == 2) {
-      if (rows) rc = bf ? adj_grouped<2, true, true>(p + i, b + i, m, s) : adj_grouped<2, false, true>(p + i, b + i, m, s);
-      else rc = bf ? adj_grouped<2, true, false>(p + i, b + i, m, s) : adj_grouped<2, false, false>(p + i, b + i, m, s);
-    } else {
-      if (rows) rc = bf ? adj_grouped<1, true, true>(p + i, b + i, m, s) : adj_grouped<1, false, true>(p + i, b + i, m, s);
-      else rc = bf ? adj_grouped<1, true, false>(p + i, b + i, m, s) : adj_grouped<1, false, false>(p + i, b + i, m, s);
-    }
+    if (p[i]->GW == 2)
+      rc = bf ? adj_grouped<2, true, CROSS>(p + i, b + i, m, s) : adj_grouped<2, false, CROSS>(p + i, b + i, m, s);
+    else
+      rc = bf ? adj_grouped<1, true, CROSS>(p + i, b + i, m, s) : adj_grouped<1, false, CROSS>(p + i, b + i, m, s);
     EX_TRY(rc);
   }
   return EXPENC_OK;
 }
 
-int split_adjoint_grouped(const EncPlan *const *pall, const EncBuffers *const *ball, int nall, hipStream_t s) {
-  // the row-layout groups and the others take kernels of their own
+int split_adjoint_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
+  // groups whose pixel blocks stay inside image rows and the others take
+  // kernel variants of their own
   std::vector<const EncPlan *> pv[2];
   std::vector<const EncBuffers *> bv[2];
-  for (int g = 0; g < nall; ++g) {
-    if (!split_groupable(*pall[0], *pall[g])) return fail(EXPENC_EINVAL, "plans of a grouped launch differ in shape");
-    pv[pall[g]->adj_rows].push_back(pall[g]);
-    bv[pall[g]->adj_rows].push_back(ball[g]);
+  for (int g = 0; g < n; ++g) {
+    if (!split_groupable(*p[0], *p[g])) return fail(EXPENC_EINVAL, "plans of a grouped launch differ in shape");
+    pv[adj_cross(*p[g])].push_back(p[g]);
+    bv[adj_cross(*p[g])].push_back(b[g]);
   }
-  for (int cls = 0; cls < 2; ++cls) EX_TRY(adj_grouped_class(pv[cls].data(), bv[cls].data(), (int)pv[cls].size(), s));
-  return EXPENC_OK;
+  EX_TRY(adj_grouped_class<false>(pv[0].data(), bv[0].data(), (int)pv[0].size(), s));
+  return adj_grouped_class<true>(pv[1].data(), bv[1].data(), (int)pv[1].size(), s);
 }
 
 void split_adjoint_sh_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
   const bool bf = p.prec == EXPENC_BF16_SPLIT;
-  if (p.adj_rows)
+  if (adj_cross(p))
     bf ? adj_split_sh<true, true>(p, b, s) : adj_split_sh<false, true>(p, b, s);
   else
     bf ? adj_split_sh<true, false>(p, b, s) : adj_split_sh<false, false>(p, b, s);

@@ -172,29 +172,6 @@ def test_launch_shape_width_and_batch_launch_validation():
     assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) > 0
 
 
-def test_row_layout_of_the_split_adjoint_is_planned_from_the_grid():
-    """The split adjoint of the solid-harmonic kind uses its rank-6 row
-    layout exactly when every 32-pixel block lies in one image row (nx
-    rounded up to 16 a multiple of 32); never in FP32 or for basis maps.
-    The GPU parity tests run both layouts (tiny / c40 grids: rows; ragged,
-    1.1 mm grids: the rank-12 layout)."""
-    b, lib = _lib()
-    out = (ctypes.c_int64 * 8)()
-
-    def rows(n, prec=b.FP16_SPLIT, kind=None):
-        op = _op(b, n=n)
-        if kind is not None:
-            op.basis_kind = kind
-            op.basis = 0x1000
-        assert lib.expenc_plan_info_ex(ctypes.byref(op), 1, prec, 1, out, 8) == b.EXPENC_OK
-        return out[7]
-
-    assert [rows(n) for n in (13, 20, 32, 36, 148, 170, 200, 208, 224)] == [0, 1, 1, 0, 1, 0, 0, 0, 1]
-    assert rows(148, prec=b.BF16_SPLIT) == 1
-    assert rows(148, prec=b.FP32) == 0
-    assert rows(148, kind=b.BASIS_MAPS) == 0
-
-
 def test_size_limits_are_reported_by_planning():
     """The documented size limits reach the caller as status codes before
     any device work: grids above 2^26 pixels and more than 2^31 samples are

@@ -6,7 +6,10 @@ split operators before refinement), and, in both directions, no worse than
 5x the error level the RNE split emulation predicts for the same arithmetic
 (plus 2e-6 for the FP32 phase increments); image NRMSE after a split-form
 solve with FP32 anchors <= 1e-4.  Whole-output full-size parity is in
-test_gpu_fullsize.py."""
+test_gpu_fullsize.py.  The solid-harmonic adjoint forms its phase row by row
+over 32-pixel blocks: the 13 px grid (rows padded to 16) has every block
+continue into the next row, the 20 and 32 px grids (rows padded to 32) none,
+and the 1.1 mm grid of the full-size tests some."""
 import numpy as np
 import pytest
 
