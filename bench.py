@@ -42,15 +42,15 @@ N_POWER = 20
 # 256 MiB copy.  Valid only for the kernel source and launch shape they were
 # taken on: `sha` is the SHA-256 of the files the kernel is built from.
 TRAFFIC = {
-    "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290733445,
+    "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290744832,
              "valu_instr": 158732000, "fwd_valu_instr": 121229000,
-             "sha": "1ed65a2851177be4464908bfd4e8a3c71a0ee1d51e211d17be1192d9d3690979"},
-    "bf16": {"kernel": "k_adj_split_sh<2, true>", "adj_split": 32, "bytes": 137457664,
-             "valu_instr": 65483900, "fwd_valu_instr": 106418000,
-             "sha": "b0fc440bf902c24a9224727a8a7d2ad4a499c6a4bbc43452a09c06faeb83884d"},
-    "fp16": {"kernel": "k_adj_split_sh<2, false>", "adj_split": 32, "bytes": 137516237,
-             "valu_instr": 65483900, "fwd_valu_instr": 87461900,
-             "sha": "b0fc440bf902c24a9224727a8a7d2ad4a499c6a4bbc43452a09c06faeb83884d"},
+             "sha": "e23f23a8c5d8888071b00b532203a02ef3c7fb02b255038e3ee89e782ce1d9d0"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true, false>", "adj_split": 32, "bytes": 137442099,
+             "valu_instr": 65876700, "fwd_valu_instr": 106418000,
+             "sha": "09398e91d134e9d61ade0780456e84d3f60d08de32d4443bf4f0fdcec112279b"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false, false>", "adj_split": 32, "bytes": 137481011,
+             "valu_instr": 65876700, "fwd_valu_instr": 87461900,
+             "sha": "09398e91d134e9d61ade0780456e84d3f60d08de32d4443bf4f0fdcec112279b"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],
@@ -81,6 +81,17 @@ def traffic_for(form, adj_split, key="bytes"):
     if not e or e["sha"] != source_sha(form) or e["adj_split"] != adj_split:
         return None
     return e.get(key)
+
+
+def adjoint_phase_rank(n):
+    """Average rank of the split adjoint's FP32 phase product on an n x n
+    grid: rows padded to a multiple of 16, 32-pixel blocks of the padded
+    row-major index; a block inside one row takes rank 6, one that continues
+    into the next row rank 10."""
+    nxq = -(-n // 16) * 16
+    blocks = -(-nxq * n // 32)
+    cross = sum(1 for k in range(blocks) if (32 * k) // nxq != (32 * k + 31) // nxq)
+    return 6 + 4 * cross / blocks
 
 
 # VALU issue time of a launch: each wave64 vector instruction occupies its
@@ -475,9 +486,11 @@ def main():
         vi_adj, vi_fwd = traffic_for(prec, adj_split, "valu_instr"), traffic_for(prec, adj_split, "fwd_valu_instr")
         if vi_adj and vi_fwd:
             tv_a, tv_f = vi_adj / VALU_ISSUE_PER_S * 1e3, vi_fwd / VALU_ISSUE_PER_S * 1e3
-            # the split adjoint also forms its phase on the matrix cores: a
-            # rank-12 FP32 product per entry
-            t_phase = 0.0 if prec == "fp32" else 12 * w.nsamples * w.npix / (PEAK_TFLOPS["fp32"] / 2 * 1e12) * 1e3
+            # the split adjoint also forms its phase on the matrix cores: an
+            # FP32 product of rank 6 per entry (10 for 32-pixel blocks that
+            # continue into the next image row)
+            t_phase = 0.0 if prec == "fp32" else (adjoint_phase_rank(w.n) * w.nsamples * w.npix
+                                                  / (PEAK_TFLOPS["fp32"] / 2 * 1e12) * 1e3)
             out[prec]["roofline_valu"] = {
                 "valu_instr_per_entry_adjoint": round(vi_adj * 64 / (w.nsamples * w.npix), 2),
                 "valu_instr_per_entry_forward": round(vi_fwd * 64 / (w.nsamples * w.npix), 2),
