@@ -352,7 +352,7 @@ def run_batch(args, prec, ee, torch):
     tb, xb = timed(batched)
     grp = {}
     if prec != "fp32":
-        print("[bench] batch, grouped persistent contractions", file=sys.stderr, flush=True)
+        print("[bench] batch, grouped contractions", file=sys.stderr, flush=True)
         tg, xg = timed(grouped)
         grp = {"recon_per_s_grouped": round(len(ws) / tg, 3), "s_per_batch_grouped": round(tg, 3),
                "grouped_equals_forked": all(bool(torch.equal(a, b)) for a, b in zip(xg, xb))}

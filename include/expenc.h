@@ -312,8 +312,8 @@ int fista_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
  * FORKED: every group runs its own iteration loop (one launch per pass for
  * the group's problems) on a stream forked inside the captured graph.
  * GROUPED: the groups advance in lock step and each split-difference
- * iteration's forward and adjoint contractions run as one persistent launch
- * whose workgroups walk the (problem, row block, split) tiles of every group
+ * iteration's forward and adjoint contractions run as one launch each over
+ * the (problem, row block, split) tiles of every group, one workgroup per tile
  * (split precisions with EXPENC_BASIS_SH and one column width for every
  * group, else EXPENC_EUNSUPPORTED).  Both give bit-identical results. */
 enum { EXPENC_BATCH_FORKED = 0, EXPENC_BATCH_GROUPED = 1 };

@@ -932,7 +932,7 @@ extern "C" int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t 
     EX_TRY(run_graph(key, s, [&](hipStream_t cs) -> int {
       if (!grouped) return forked(cs, [&](int g, hipStream_t gs) { return bp.groups[g].body(gs); });
       // lock-step groups: each iteration's two split contractions run as one
-      // persistent launch over every group's tiles
+      // launch over every group's tiles
       constexpr int kAll = FistaGroup::kStageAll;
       for (int k = 0; k < opts->n_iter; ++k) {
         if (!bp.groups[0].split_difference(k)) {

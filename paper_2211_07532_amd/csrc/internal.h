@@ -78,8 +78,8 @@ __device__ inline void flag_nonfinite(unsigned *status, float2 v) {
 // contiguous range of reduction chunks and the slice of the streamed operand
 // it needs stays in its L2.  The grid has 8Q >= N workgroups; the at most 7
 // surplus ones return at once.
-// (b: the workgroup's index in the launch's x dimension; a persistent
-// launch passes the index of the tile it is working on.)
+// (b: the workgroup's index in the launch's x dimension; a grouped launch
+// passes the tile's index within its group.)
 __device__ inline bool split_tile(int b, int nrb, int nsplit, int *split, int *rb) {
   const int n = nrb * nsplit;
   const int q = (n + 7) >> 3;
@@ -386,9 +386,6 @@ bool split_groupable(const EncPlan &a, const EncPlan &b);
 // kMaxGrouped groups each.
 int split_forward_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s);
 int split_adjoint_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s);
-// Grid of a persistent launch: the workgroups resident at once (occupancy x
-// compute units), at most the virtual ones, a multiple of 8.
-int persistent_grid(const void *kernel, int64_t nvirtual, unsigned *grid);
 int split_build_z(const EncPlan &p, const float *smaps, const float2 *x, const float2 *xsub, int64_t x_stride,
                   int32_t x_row_stride, const EncBuffers &b, hipStream_t s, int64_t x_pstride);
 int split_pack_y(const EncPlan &p, const float2 *y_abi, bool from_partials, const float2 *y_meas,

@@ -368,15 +368,18 @@ __global__ __launch_bounds__(256) void k_fwd_split_sh(FwdShArgs a) {
   fwd_split_sh_body<GW, BF>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y);
 }
 
-// Persistent form for several problem groups of one shape class (same GW
-// and number format): the virtual workgroups of every group's grid are
-// numbered group by group (x fastest), and each resident workgroup walks
-// them with the launch's stride.  Every group's x extent is a multiple of
-// eight, as is the stride, so a virtual workgroup runs on the XCD its index
-// assigns it and split_tile's L2 locality holds.
+// One launch for several problem groups of one shape class (same GW and
+// number format): the workgroups of every group's grid are numbered group by
+// group (x fastest) and the launch has one workgroup per tile.  Every group's
+// x extent is a multiple of eight, so a tile runs on the XCD its index
+// assigns it and split_tile's L2 locality holds.  (A persistent form, a
+// grid of the resident workgroups walking the tiles with its stride, was
+// slower: its loop raised the adjoint's registers to two waves per SIMD.)
 template <int GW, bool BF>
 __global__ __launch_bounds__(256) void k_fwd_split_sh_grouped(GroupedLaunch<FwdShArgs> G) {
-  for (int64_t t = blockIdx.x; t < G.off[G.ng]; t += gridDim.x) {
+  {
+    const int64_t t = blockIdx.x;
+    if (t >= G.off[G.ng]) return;
     int g = 0;
     while (g + 1 < G.ng && t >= G.off[g + 1]) ++g;
     const int64_t l = t - G.off[g];
@@ -930,19 +933,8 @@ bool split_groupable(const EncPlan &a, const EncPlan &b) {
          a.scaled == b.scaled;
 }
 
-int persistent_grid(const void *kernel, int64_t nvirtual, unsigned *grid) {
-  int dev = 0, ncu = 0, per_cu = 0;
-  EX_HIP(hipGetDevice(&dev));
-  EX_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
-  EX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0));
-  const int64_t resident = (int64_t)std::max(per_cu, 1) * ncu;
-  *grid = (unsigned)((std::min(resident, nvirtual) + 7) / 8 * 8);
-  return EXPENC_OK;
-}
-
 template <int GW, bool BF>
 static int fwd_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
-  const void *kern = reinterpret_cast<const void *>(&k_fwd_split_sh_grouped<GW, BF>);
   GroupedLaunch<FwdShArgs> G{};
   G.ng = n;
   G.off[0] = 0;
@@ -952,9 +944,8 @@ static int fwd_grouped(const EncPlan *const *p, const EncBuffers *const *b, int 
     G.gy[g] = p[g]->NGY;
     G.off[g + 1] = G.off[g] + (int64_t)G.gx[g] * G.gy[g] * p[g]->P;
   }
-  unsigned grid = 0;
-  EX_TRY(persistent_grid(kern, G.off[n], &grid));
-  k_fwd_split_sh_grouped<GW, BF><<<grid, 256, 0, s>>>(G);
+  if (G.off[n] > INT32_MAX) return fail(EXPENC_EUNSUPPORTED, "grouped launch larger than 2^31 workgroups");
+  k_fwd_split_sh_grouped<GW, BF><<<(unsigned)G.off[n], 256, 0, s>>>(G);
   EX_LAUNCHED("grouped forward contraction");
   return EXPENC_OK;
 }

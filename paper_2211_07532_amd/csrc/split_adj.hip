@@ -166,12 +166,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1)
   adj_split_sh_body<GW, BF, CROSS>(a, blockIdx.x, blockIdx.y, blockIdx.z, gridDim.y);
 }
 
-// Persistent form over several problem groups (the forward's grouped kernel
-// in split.hip describes the numbering and why the XCD mapping holds).
+// One launch over several problem groups, one workgroup per tile (the
+// forward's grouped kernel in split.hip describes the numbering and why the
+// XCD mapping holds).
 template <int GW, bool BF, bool CROSS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(BF ? 3 : 1))) void k_adj_split_sh_grouped(
     GroupedLaunch<AdjShArgs> G) {
-  for (int64_t t = blockIdx.x; t < G.off[G.ng]; t += gridDim.x) {
+  {
+    const int64_t t = blockIdx.x;
+    if (t >= G.off[G.ng]) return;
     int g = 0;
     while (g + 1 < G.ng && t >= G.off[g + 1]) ++g;
     const int64_t l = t - G.off[g];
@@ -203,7 +206,6 @@ static void adj_split_sh(const EncPlan &p, const EncBuffers &b, hipStream_t s) {
 
 template <int GW, bool BF, bool CROSS>
 static int adj_grouped(const EncPlan *const *p, const EncBuffers *const *b, int n, hipStream_t s) {
-  const void *kern = reinterpret_cast<const void *>(&k_adj_split_sh_grouped<GW, BF, CROSS>);
   GroupedLaunch<AdjShArgs> G{};
   G.ng = n;
   G.off[0] = 0;
@@ -213,9 +215,8 @@ static int adj_grouped(const EncPlan *const *p, const EncBuffers *const *b, int 
     G.gy[g] = p[g]->NGY;
     G.off[g + 1] = G.off[g] + (int64_t)G.gx[g] * G.gy[g] * p[g]->P;
   }
-  unsigned grid = 0;
-  EX_TRY(persistent_grid(kern, G.off[n], &grid));
-  k_adj_split_sh_grouped<GW, BF, CROSS><<<grid, 256, 0, s>>>(G);
+  if (G.off[n] > INT32_MAX) return fail(EXPENC_EUNSUPPORTED, "grouped launch larger than 2^31 workgroups");
+  k_adj_split_sh_grouped<GW, BF, CROSS><<<(unsigned)G.off[n], 256, 0, s>>>(G);
   EX_LAUNCHED("grouped adjoint contraction");
   return EXPENC_OK;
 }

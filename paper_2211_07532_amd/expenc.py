@@ -441,7 +441,7 @@ def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: i
     check_status the call waits for the solves and raises ExpencError if any
     iterate turned non-finite (otherwise it returns without waiting).
     launch: "forked" (each group's own launches on forked streams) or
-    "grouped" (lock-step groups sharing one persistent launch per split
+    "grouped" (lock-step groups sharing one launch per split
     contraction; split precisions, solid-harmonic operators)."""
     launches = {"forked": _b.EXPENC_BATCH_FORKED, "grouped": _b.EXPENC_BATCH_GROUPED}
     if launch not in launches:

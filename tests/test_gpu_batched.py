@@ -318,7 +318,7 @@ def _many_groups(n_groups, n_iter, levels=2):
 
 @pytest.mark.parametrize("prec,n_groups", [("fp16", 3), ("bf16", 3), ("fp16", 10)])
 def test_grouped_launch_is_bitwise_equal_to_forked(prec, n_groups):
-    """The persistent grouped contractions (every group's tiles in one launch
+    """The grouped contractions (every group's tiles in one launch
     per pass, groups in lock step) against each group's own launches on
     forked streams: the same tiles with the same arithmetic, so the results
     are bit-identical.  30 iterations cover the first gradient from the
