@@ -42,15 +42,15 @@ N_POWER = 20
 # 256 MiB copy.  Valid only for the kernel source and launch shape they were
 # taken on: `sha` is the SHA-256 of the files the kernel is built from.
 TRAFFIC = {
-    "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290744832,
+    "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290732933,
              "valu_instr": 158732000, "fwd_valu_instr": 121229000,
-             "sha": "e23f23a8c5d8888071b00b532203a02ef3c7fb02b255038e3ee89e782ce1d9d0"},
-    "bf16": {"kernel": "k_adj_split_sh<2, true, false>", "adj_split": 32, "bytes": 137442099,
+             "sha": "59168bf013a2ee07b091f13a6e62e70179e0e9838b2ad0dc91c816f7c0521c65"},
+    "bf16": {"kernel": "k_adj_split_sh<2, true, false>", "adj_split": 32, "bytes": 137413018,
              "valu_instr": 65876700, "fwd_valu_instr": 106418000,
-             "sha": "09398e91d134e9d61ade0780456e84d3f60d08de32d4443bf4f0fdcec112279b"},
-    "fp16": {"kernel": "k_adj_split_sh<2, false, false>", "adj_split": 32, "bytes": 137481011,
+             "sha": "f4a676adc9f85538d8c9391f36d285854136e0e6aebf7131512a285bd6a031fc"},
+    "fp16": {"kernel": "k_adj_split_sh<2, false, false>", "adj_split": 32, "bytes": 137499034,
              "valu_instr": 65876700, "fwd_valu_instr": 87461900,
-             "sha": "09398e91d134e9d61ade0780456e84d3f60d08de32d4443bf4f0fdcec112279b"},
+             "sha": "f4a676adc9f85538d8c9391f36d285854136e0e6aebf7131512a285bd6a031fc"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],
