@@ -44,13 +44,13 @@ N_POWER = 20
 TRAFFIC = {
     "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290732933,
              "valu_instr": 158732000, "fwd_valu_instr": 121229000,
-             "sha": "59168bf013a2ee07b091f13a6e62e70179e0e9838b2ad0dc91c816f7c0521c65"},
+             "sha": "b425cca87a4a6285ed52169fb82cf8fc08c9ebb80af90fb529e7782ba4a253b2"},
     "bf16": {"kernel": "k_adj_split_sh<2, true, false>", "adj_split": 32, "bytes": 137413018,
              "valu_instr": 65876700, "fwd_valu_instr": 106418000,
-             "sha": "f4a676adc9f85538d8c9391f36d285854136e0e6aebf7131512a285bd6a031fc"},
+             "sha": "3e41fa37bddfa321d5ff012ba9b942d7b1415db7196cc04588d821501b3be52c"},
     "fp16": {"kernel": "k_adj_split_sh<2, false, false>", "adj_split": 32, "bytes": 137499034,
              "valu_instr": 65876700, "fwd_valu_instr": 87461900,
-             "sha": "f4a676adc9f85538d8c9391f36d285854136e0e6aebf7131512a285bd6a031fc"},
+             "sha": "3e41fa37bddfa321d5ff012ba9b942d7b1415db7196cc04588d821501b3be52c"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],

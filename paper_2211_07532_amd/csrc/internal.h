@@ -367,11 +367,11 @@ void split_adjoint_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 // the polynomial (solid-harmonic) split adjoint, built in split_adj.hip
 void split_adjoint_sh_launch(const EncPlan &p, const EncBuffers &b, hipStream_t s);
 
-// Persistent launch of one split contraction over several problem groups
-// (plans of one shape class: solid-harmonic kind, same number format and
-// column width GW).  Virtual workgroup t runs workgroup (x, y, z) of group
+// One launch of a split contraction over several problem groups (plans of
+// one shape class: solid-harmonic kind, same number format and column width
+// GW).  Workgroup t of the launch runs workgroup (x, y, z) of group
 // g's own grid, where off[g] <= t < off[g+1] and t - off[g] numbers that grid
-// x fastest; resident workgroups walk t with the launch's stride.
+// x fastest; the launch has one workgroup per t.
 constexpr int kMaxGrouped = 8;
 template <class Args>
 struct GroupedLaunch {
