@@ -141,3 +141,37 @@ def test_split_fista_on_scaled_data(prec):
         e = solve.nrmse(res.x.cpu().numpy().reshape(-1) / s, ref)
         print(f"split FISTA {prec} data scale {s:.1e}: NRMSE {e:.2e}", flush=True)
         assert e <= 1e-4, s
+
+
+@pytest.mark.parametrize("n", [32, 13], ids=["rows-aligned", "rows-crossing"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp16"])
+def test_strong_field_operators(prec, n):
+    """Fields far beyond the paper's (every field term x30 and the off-
+    resonance map x10: up to 63 (13 px) and 357 (32 px) turns of phase
+    within one 32-sample tile, 14-16 turns between neighbouring pixels)
+    stay accurate: the phase is reduced to turns before every sine and
+    cosine, and the FP32 increments of the split forms stay small against
+    their tiles.  Measured: split forms 0.4-2.2e-5 (held to 1e-4, a tenth of
+    the split operators' bar), FP32 1.2e-7 (held to 1e-6; its phase is FP64
+    per entry).  Grids of 32 px and 13 px take the adjoint's
+    two kernel variants (32-pixel blocks inside image rows / continuing into
+    the next row)."""
+    import torch
+    ee = _ee()
+    w = synth.Workload("strong", n, 0.1, 6, 700, 3e-6, 2.0, 16, 100.0, 20.0, 5, "haar", 1, 71)
+    case = Case(w, sh=True)
+    coef, dw0 = case.coef * 30.0, case.dw0 * 10.0
+    dev = torch.device("cuda")
+    op = ee.Operator(n, n, case.t_smaps, torch.from_numpy(coef).to(dev), case.t_time, None,
+                     torch.from_numpy(dw0).to(dev), sh_grid=(w.fov, w.fov, case.z0))
+    args = (case.smaps, coef, case.time, case.basis_np, dw0)
+    phi = encoding.phase(coef, case.time, case.basis_np, dw0) / (2 * np.pi)
+    print(f"[case] strong field {prec} n={n}: phase spans {np.ptp(phi):.0f} turns, "
+          f"{np.abs(np.diff(phi, axis=0)).max():.2f} turns per sample", flush=True)
+    x = c64(synth.random_complex((2, w.npix), 72))
+    g = c64(synth.random_complex((2, w.nsamples, w.ncoils), 73))
+    e_f = rel(ee.forward(case.to_dev(x), op, precision=prec).cpu().numpy(), encoding.forward(x, *args))
+    e_a = rel(ee.adjoint(case.to_dev(g), op, precision=prec).cpu().numpy(), encoding.adjoint(g, *args))
+    print(f"strong field {prec} n={n}: forward {e_f:.2e}, adjoint {e_a:.2e}", flush=True)
+    bar = 1e-6 if prec == "fp32" else 1e-4
+    assert e_f <= bar and e_a <= bar
