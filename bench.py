@@ -44,13 +44,13 @@ N_POWER = 20
 TRAFFIC = {
     "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290732933,
              "valu_instr": 158732000, "fwd_valu_instr": 121229000,
-             "sha": "b425cca87a4a6285ed52169fb82cf8fc08c9ebb80af90fb529e7782ba4a253b2"},
+             "sha": "35ffc78e8771a4aa35de99ed43d5bae54a7f05566e41254f1843957be03b05f3"},
     "bf16": {"kernel": "k_adj_split_sh<2, true, false>", "adj_split": 32, "bytes": 137413018,
              "valu_instr": 65876700, "fwd_valu_instr": 106418000,
-             "sha": "3e41fa37bddfa321d5ff012ba9b942d7b1415db7196cc04588d821501b3be52c"},
+             "sha": "c6bb0738b88f46c561b4bdf62844c0b3f1c29f208088c3e6508946c2fe08aa40"},
     "fp16": {"kernel": "k_adj_split_sh<2, false, false>", "adj_split": 32, "bytes": 137499034,
              "valu_instr": 65876700, "fwd_valu_instr": 87461900,
-             "sha": "3e41fa37bddfa321d5ff012ba9b942d7b1415db7196cc04588d821501b3be52c"},
+             "sha": "c6bb0738b88f46c561b4bdf62844c0b3f1c29f208088c3e6508946c2fe08aa40"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],
@@ -254,6 +254,33 @@ def run_ls_vs_cs(forms, ee, torch, y, op, fista_rates):
     return {"ls_iters": n_ls, "cs_iters": n_cs, "forms": out}
 
 
+def run_anchor_modes(prec, ee, torch, w, op, y, v0, golden, reps):
+    """The split form's FISTA loop (L and lambda given) under each anchor
+    mode: FISTA iterations per second and the image's NRMSE against the FP64
+    solve.  The anchors are where the gradient is recomputed in full; the
+    other iterations update it from the split products."""
+    sc = ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=0.0, power_v0=v0, n_power=N_POWER)
+    L, lam = sc.lipschitz, sc.lam[0]
+    res = {}
+    for mode in ee.ANCHORS:
+        def loop():
+            return ee.fista(y, op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam,
+                            sync_scalars=False, anchor=mode)
+        r = loop()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            loop()
+        torch.cuda.synchronize()
+        it_s = w.n_iter * reps / (time.perf_counter() - t0)
+        e = None
+        if golden is not None:
+            xr = r.x.cpu().numpy().reshape(-1).astype(np.complex128)
+            e = float(f"{np.linalg.norm(xr - golden.reshape(-1)) / np.linalg.norm(golden):.3e}")
+        res[mode] = {"fista_iter_per_s": round(it_s, 2), "nrmse_vs_fp64": e}
+    return {"form": prec, **res}
+
+
 def run_mm11(forms, ee, torch, no_tune, retune):
     """The 1.1 mm configuration (200 x 200, 32 coils, T = 40000, 3rd-order
     field + dB0, 100 FISTA iterations, db4 J = 4): FISTA iter/s per form with
@@ -411,7 +438,7 @@ def main():
         tuning = None
         if not args.no_tune:
             # launch shapes from the project autotuner (cached per device and geometry);
-            # the split forms' FP32 anchors use the FP32 plan
+            # the split forms' FP32 anchors (first and last iteration) use the FP32 plan
             from paper_2211_07532_amd import autotune
             for f in (["fp32"] if prec != "fp32" else []) + [prec]:
                 r = autotune.tune(op, 1, f, use_cache=not args.retune)
@@ -538,6 +565,9 @@ def main():
                               "nrmse_vs_fp64": out["bf16"]["nrmse_vs_fp64"],
                               "vs_fp32_fista_iter_ratio": round(out["bf16"]["fista_iter_per_s"] /
                                                                 out["fp32"]["fista_iter_per_s"], 3)}
+    if head != "fp32":
+        print(f"[bench] anchor modes ({head})", file=sys.stderr, flush=True)
+        line["anchor_modes"] = run_anchor_modes(head, ee, torch, w, op, y, v0, golden, max(2, args.steps))
     print("[bench] balanced FISTA with the undecimated wavelet", file=sys.stderr, flush=True)
     line["balanced_fista"] = run_balanced(sorted({"fp32", head}), ee, torch, w, op, y, v0)
     print("[bench] least squares (CG) against CS", file=sys.stderr, flush=True)

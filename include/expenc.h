@@ -259,7 +259,7 @@ typedef struct expenc_fista_opts {
   int32_t levels;          /* J >= 1                                                 */
   int32_t nx_pad, ny_pad;  /* wavelet grid (>= nx, ny, multiples of 2^J); 0 = round up */
   int32_t ista;            /* 1: momentum off (t_k = 1), monotone ISTA               */
-  int32_t refine_every;    /* split forms: exact FP32 gradient every m iterations (0 = 25 fp16, 17 bf16) */
+  int32_t refine_every;    /* split forms: anchor cadence m (0 = the anchor mode's default) */
   int32_t n_power;         /* power steps when lipschitz <= 0 (in the solve's
                               precision when batch == 1, else FP32)                  */
   int32_t batch_launch;    /* fista_solve_batched: EXPENC_BATCH_FORKED or
@@ -272,7 +272,21 @@ typedef struct expenc_fista_opts {
   const float *power_v0;   /* device [R] complex64 power-iteration start (lipschitz <= 0) */
   double *objective;       /* device [B][n_iter] float64 objective trace, or NULL    */
   double *scalars;         /* device [2 + 2B] float64: L, tau(b=0), lambda[B], ..., or NULL */
+  int32_t anchor;          /* split forms: precision of the anchors, EXPENC_ANCHOR_*  */
+  int32_t reserved;        /* must be 0                                              */
 } expenc_fista_opts;
+
+/* Anchors of the split forms' gradient (expenc_fista_opts.anchor and
+ * expenc_balanced_opts.anchor).  Every refine_every-th iteration, and the
+ * last, recomputes the gradient at z_ref = z_k and later iterations add the
+ * split operators' A^H A (z_k - z_ref) to it.
+ *   ENDS (default, cadence 5): the anchors of the first and the last
+ *     iteration in FP32, the others in the iteration's split form;
+ *   FP32 (cadence 25 fp16, 17 bf16): every anchor in FP32;
+ *   SPLIT (cadence 5): every anchor but the first in the split form.
+ * The first iteration's gradient is FP32 in every mode (z_0 = 0, so it is
+ * -A^H y, which the lambda rule also uses). */
+enum { EXPENC_ANCHOR_ENDS = 0, EXPENC_ANCHOR_FP32 = 1, EXPENC_ANCHOR_SPLIT = 2 };
 
 /*
  * CS reconstruction: FISTA on eq. 1 exactly as written (no 1/2 on the data
@@ -285,9 +299,9 @@ typedef struct expenc_fista_opts {
  * whose top-left nx x ny block is encoded.  y: [B][T][C]; x: [B][ny][nx]
  * (crop of x_K, overwritten).  The iteration loop is captured once into a
  * HIP graph and replayed on `stream`; L, lambda and tau stay on the device.
- * Split precisions use an anchored gradient: an FP32 gradient at z_ref is
- * refreshed every refine_every iterations and the split operators only
- * apply A^H A to z_k - z_ref.
+ * Split precisions use an anchored gradient: the gradient at z_ref is
+ * recomputed every refine_every iterations (in FP32 or the split form, see
+ * EXPENC_ANCHOR_*) and the split operators only apply A^H A to z_k - z_ref.
  */
 int fista_solve(const expenc_op *op, int32_t batch, const float *y, float *x,
                 const expenc_fista_opts *opts, void *ws, size_t ws_bytes, void *stream);
@@ -365,11 +379,11 @@ typedef struct expenc_balanced_opts {
   int32_t precision;     /* EXPENC_FP32 / EXPENC_BF16_SPLIT / EXPENC_FP16_SPLIT    */
   int32_t wavelet;       /* EXPENC_HAAR / EXPENC_DB4                               */
   int32_t levels;        /* J in [1, 8] (the paper: 1)                             */
-  int32_t refine_every;  /* split forms: FP32 anchor cadence (0 = 25 fp16, 17 bf16) */
+  int32_t refine_every;  /* split forms: anchor cadence (0 = the anchor mode's default) */
   int32_t n_power;       /* power steps when lipschitz <= 0 (solve's precision at
                             batch 1, else FP32)                                      */
   int32_t ista;          /* 1: momentum off                                        */
-  int32_t reserved;      /* must be 0                                              */
+  int32_t anchor;        /* split forms: precision of the anchors, EXPENC_ANCHOR_*  */
   double lipschitz;      /* > 0: L_A to use; <= 0: power iteration from power_v0   */
   double kappa;          /* >= 0: balance weight; < 0: kappa = L_A                 */
   double lambda_scale;   /* factor on the sigma/2 rule (1 = the paper's)           */

@@ -9,5 +9,5 @@ Python binding; it loads the in-tree library and raises if it is missing.
 from .expenc import (Operator, sh_basis, forward, adjoint, lipschitz, wavelet_fwd, wavelet_inv,  # noqa: F401
                      wavelet_prox, soft_threshold, fista, fista_batched, cg, prewhiten, coil_compress, swt_fwd, swt_inv,
                      sigma_weights, fista_balanced, BalancedResult, FistaResult, axpby,
-                     PRECISIONS, WAVELETS)
+                     PRECISIONS, WAVELETS, ANCHORS)
 from ._binding import lib, path as library_path, ExpencError, LibraryMissing  # noqa: F401

@@ -20,6 +20,7 @@ EXPENC_ENONFINITE = -5
 EXPENC_EDIVERGED = -6
 EXPENC_BATCH_FORKED = 0
 EXPENC_BATCH_GROUPED = 1
+EXPENC_ANCHOR_ENDS, EXPENC_ANCHOR_FP32, EXPENC_ANCHOR_SPLIT = 0, 1, 2
 
 FP32, BF16_SPLIT, FP16_SPLIT = 0, 1, 2
 HAAR, DB4 = 0, 1
@@ -52,6 +53,7 @@ class FistaOpts(ctypes.Structure):
         ("lipschitz", ctypes.c_double), ("lambda_", ctypes.c_double),
         ("lambda_factor", ctypes.c_double),
         ("power_v0", _vp), ("objective", _vp), ("scalars", _vp),
+        ("anchor", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -60,7 +62,7 @@ class BalancedOpts(ctypes.Structure):
         ("n_iter", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("wavelet", ctypes.c_int32), ("levels", ctypes.c_int32),
         ("refine_every", ctypes.c_int32), ("n_power", ctypes.c_int32),
-        ("ista", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("ista", ctypes.c_int32), ("anchor", ctypes.c_int32),
         ("lipschitz", ctypes.c_double), ("kappa", ctypes.c_double), ("lambda_scale", ctypes.c_double),
         ("power_v0", _vp), ("lambda_", _vp), ("scalars", _vp),
     ]

@@ -378,8 +378,9 @@ int check_bal(const expenc_balanced_opts *o, int *refine) {
   if (o->lipschitz <= 0 && (!o->power_v0 || o->n_power < 1))
     return fail(EXPENC_EINVAL, "lipschitz <= 0 requires power_v0 and n_power >= 1");
   if (!o->lambda && !(o->lambda_scale > 0)) return fail(EXPENC_EINVAL, "lambda_scale must be > 0");
-  if (o->reserved != 0) return fail(EXPENC_EINVAL, "reserved field must be 0");
-  *refine = o->refine_every > 0 ? o->refine_every : default_refine(o->precision);
+  if (o->anchor != EXPENC_ANCHOR_ENDS && o->anchor != EXPENC_ANCHOR_FP32 && o->anchor != EXPENC_ANCHOR_SPLIT)
+    return fail(EXPENC_EINVAL, "unknown anchor mode %d", o->anchor);
+  *refine = o->refine_every > 0 ? o->refine_every : default_refine(o->precision, o->anchor);
   return EXPENC_OK;
 }
 
@@ -525,9 +526,10 @@ extern "C" int fista_balanced_solve(const expenc_op *op, int32_t batch, const fl
         EX_TRY(enc_adjoint_partials(p, L.eb, cs));
         EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.r, N, op->nx, nullptr, nullptr, cs));
       } else if (k % refine == 0 || k == K - 1) {
-        EX_TRY(residual_fp32(pf));
-        EX_TRY(enc_adjoint_partials(pf, L.eb, cs));
-        EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.rref, N, op->nx, nullptr, nullptr, cs));
+        const EncPlan &pa = anchor_in_fp32(opts->anchor, k, K) ? pf : p;
+        EX_TRY(residual_fp32(pa));
+        EX_TRY(enc_adjoint_partials(pa, L.eb, cs));
+        EX_TRY(enc_adjoint_reduce_out(pa, L.eb, op->smaps, L.rref, N, op->nx, nullptr, nullptr, cs));
         EX_TRY(copy_f2(L.rref, L.r, img, cs));
         EX_TRY(copy_f2(L.xb, L.xref, img, cs));
       } else {

@@ -379,7 +379,10 @@ static int check_fista_opts(const expenc_fista_opts *o, int *eff_refine) {
   if (o->lipschitz <= 0 && (!o->power_v0 || o->n_power < 1))
     return fail(EXPENC_EINVAL, "lipschitz <= 0 requires power_v0 and n_power >= 1");
   if (o->lambda < 0 && !(o->lambda_factor > 0)) return fail(EXPENC_EINVAL, "lambda < 0 requires lambda_factor > 0");
-  *eff_refine = o->refine_every > 0 ? o->refine_every : default_refine(o->precision);
+  if (o->anchor != EXPENC_ANCHOR_ENDS && o->anchor != EXPENC_ANCHOR_FP32 && o->anchor != EXPENC_ANCHOR_SPLIT)
+    return fail(EXPENC_EINVAL, "unknown anchor mode %d", o->anchor);
+  if (o->reserved != 0) return fail(EXPENC_EINVAL, "reserved option field must be 0");
+  *eff_refine = o->refine_every > 0 ? o->refine_every : default_refine(o->precision, o->anchor);
   return EXPENC_OK;
 }
 
@@ -502,10 +505,11 @@ struct FistaGroup {
         EX_TRY(enc_adjoint_partials(p, L.eb, cs));
         EX_TRY(enc_adjoint_reduce_out(p, L.eb, op->smaps, L.v, img, nxp, alpha, L.z, cs, nullptr, pimg, pnx, pny));
       } else if (k % refine == 0 || k == K - 1) {
-        // anchor: exact FP32 gradient at z_ref = z
-        EX_TRY(residual_fp32(pf));
-        EX_TRY(enc_adjoint_partials(pf, L.eb, cs));
-        EX_TRY(enc_adjoint_reduce_out(pf, L.eb, op->smaps, L.gref, img, nxp, nullptr, nullptr, cs, nullptr, pimg));
+        // anchor: the gradient at z_ref = z, in FP32 or in the split form
+        const EncPlan &pa = anchor_in_fp32(opts->anchor, k, K) ? pf : p;
+        EX_TRY(residual_fp32(pa));
+        EX_TRY(enc_adjoint_partials(pa, L.eb, cs));
+        EX_TRY(enc_adjoint_reduce_out(pa, L.eb, op->smaps, L.gref, img, nxp, nullptr, nullptr, cs, nullptr, pimg));
         k_grad_step<<<(unsigned)ceil_div(all, 256), 256, 0, cs>>>(L.v, L.z, L.gref, alpha, nxp, nyp, p.nx, p.ny, all, B);
         EX_LAUNCHED("gradient step");
         EX_TRY(copy_f2(L.z, L.zref, all, cs));

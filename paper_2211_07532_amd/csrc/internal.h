@@ -311,14 +311,22 @@ size_t enc_part_elems(const EncPlan &p);
 int run_captured(uint64_t key, hipStream_t s, const std::function<int(hipStream_t)> &body);
 uint64_t hash_bytes(uint64_t h, const void *p, size_t n);
 
-// Autotuner overrides of the contraction workgroup targets (0 = default).
-// Default FP32 anchor cadence of the split forms' anchored gradient: the
-// error of a split step scales with the form's product precision (fp16
-// halves: 22 bits, bf16 halves: 16 bits) times ||z - z_ref||, so the fp16
-// form refreshes its anchor less often.  The cadences hold the final image
-// within 1e-5 of the FP64 solve on the 1.5 mm reconstruction (50 iterations:
-// 4.9e-6 fp16, 6.9e-6 bf16).
-inline int default_refine(int32_t precision) { return precision == EXPENC_FP16_SPLIT ? 25 : 17; }
+// Default anchor cadence of the split forms' anchored gradient.  The error of
+// a split difference step scales with the form's product precision times
+// ||z - z_ref||, so frequent anchors help, and an anchor formed in the split
+// form costs no more than a difference iteration: the split-anchored modes
+// refresh every 5 iterations (1.5 mm, 50 iterations: final image 2.8e-6
+// fp16, 3.3e-6 bf16 against the FP64 solve).  Anchors all in FP32 cost a
+// full FP32 A and A^H each and keep the earlier cadences, which held the
+// image within 1e-5 (4.9e-6 fp16 at 25, 6.9e-6 bf16 at 17).
+inline int default_refine(int32_t precision, int32_t anchor) {
+  if (anchor != EXPENC_ANCHOR_FP32) return 5;
+  return precision == EXPENC_FP16_SPLIT ? 25 : 17;
+}
+// Whether the anchor of iteration k (of K) is formed in FP32.
+inline bool anchor_in_fp32(int32_t anchor, int k, int K) {
+  return k == 0 || anchor == EXPENC_ANCHOR_FP32 || (anchor == EXPENC_ANCHOR_ENDS && k == K - 1);
+}
 int set_tuning(const expenc_op *op, int32_t batch, int32_t precision, int32_t fwd_target, int32_t adj_target,
                int32_t col_groups);
 uint64_t tuning_generation();

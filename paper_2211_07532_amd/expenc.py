@@ -26,6 +26,8 @@ from ._binding import FP32, BF16_SPLIT, FP16_SPLIT, HAAR, DB4, check
 PRECISIONS = {"fp32": FP32, "bf16": BF16_SPLIT, "bf16_split": BF16_SPLIT, "fp16": FP16_SPLIT,
               "fp16_split": FP16_SPLIT}
 WAVELETS = {"haar": HAAR, "db4": DB4}
+# anchors of the split forms' gradient (see EXPENC_ANCHOR_* in include/expenc.h)
+ANCHORS = {"ends": _b.EXPENC_ANCHOR_ENDS, "fp32": _b.EXPENC_ANCHOR_FP32, "split": _b.EXPENC_ANCHOR_SPLIT}
 
 
 def _prec(p) -> int:
@@ -34,6 +36,10 @@ def _prec(p) -> int:
 
 def _wav(w) -> int:
     return WAVELETS[w] if isinstance(w, str) else int(w)
+
+
+def _anchor(a) -> int:
+    return ANCHORS[a] if isinstance(a, str) else int(a)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -253,8 +259,10 @@ class FistaResult:
 def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4", precision="fp32",
           lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3, power_v0=None,
           n_power: int = 30, nx_pad: int = 0, ny_pad: int = 0, ista: bool = False, refine_every: int = 0,
-          trace: bool = False, sync_scalars: bool = True, check_status: bool = True):
+          trace: bool = False, sync_scalars: bool = True, check_status: bool = True, anchor="ends"):
     """FISTA on eq. 1 (see fista_solve in include/expenc.h).  Returns a FistaResult.
+    anchor: precision of the split forms' gradient anchors, "ends" (FP32 at
+    the first and last iteration, split in between), "fp32" or "split".
     With sync_scalars the call waits for the solve and reads its status word:
     a non-finite iterate (or, with trace=True, an objective above F(0))
     raises ExpencError when check_status, else is returned in .status."""
@@ -274,7 +282,7 @@ def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4"
                         n_power, 0, float(lipschitz), float(lam), float(lambda_factor),
                         None if power_v0 is None else _need(power_v0, torch.complex64, "power_v0",
                                                             op.device).data_ptr(),
-                        None if obj is None else obj.data_ptr(), sc.data_ptr())
+                        None if obj is None else obj.data_ptr(), sc.data_ptr(), _anchor(anchor))
     ws = op.workspace(_b.WS_FISTA, batch, precision, nxp, nyp)
     check(_b.lib().fista_solve(ctypes.byref(op._c), batch, _ptr(yb), _ptr(x), ctypes.byref(opts), _ptr(ws),
                                ws.numel(), _stream(op.device)), "fista_solve")
@@ -395,7 +403,7 @@ class BalancedResult:
 def fista_balanced(y: torch.Tensor, op: Operator, n_iter: int, levels: int = 1, wavelet="db4", precision="fp32",
                    lipschitz: float = 0.0, kappa: float = -1.0, lam: Optional[torch.Tensor] = None,
                    lambda_scale: float = 1.0, power_v0=None, n_power: int = 30, ista: bool = False,
-                   refine_every: int = 0) -> BalancedResult:
+                   refine_every: int = 0, anchor="ends") -> BalancedResult:
     """Balanced FISTA with the undecimated wavelet (see fista_balanced_solve in include/expenc.h)."""
     single = y.dim() == 2
     yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
@@ -408,7 +416,8 @@ def fista_balanced(y: torch.Tensor, op: Operator, n_iter: int, levels: int = 1, 
     sc = torch.zeros(3 + 2 * B * nb, dtype=torch.float64, device=op.device)
     if lam is not None:
         lam = _need(lam.reshape(B, nb).contiguous(), torch.float64, "lam", op.device)
-    opts = _b.BalancedOpts(n_iter, _prec(precision), _wav(wavelet), levels, refine_every, n_power, int(ista), 0,
+    opts = _b.BalancedOpts(n_iter, _prec(precision), _wav(wavelet), levels, refine_every, n_power, int(ista),
+                           _anchor(anchor),
                            float(lipschitz), float(kappa), float(lambda_scale),
                            None if power_v0 is None else _need(power_v0, torch.complex64, "power_v0",
                                                                op.device).data_ptr(),
@@ -434,7 +443,7 @@ _batch_ws = {}
 def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: int, levels: int, wavelet="db4",
                   precision="fp32", lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3,
                   power_v0=None, n_power: int = 30, ista: bool = False, refine_every: int = 0,
-                  check_status: bool = False, launch: str = "forked"):
+                  check_status: bool = False, launch: str = "forked", anchor="ends"):
     """Independent FISTA solves of problems (ys[i], ops[i]) in one call (see
     fista_solve_batched in include/expenc.h).  Every ys[i] is [T_i][C_i] (or
     [B][T_i][C_i] with one B for all).  Returns the list of x_i.  With
@@ -462,7 +471,7 @@ def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: i
     opts = _b.FistaOpts(n_iter, _prec(precision), _wav(wavelet), levels, 0, 0, int(ista), refine_every,
                         n_power, launches[launch], float(lipschitz), float(lam), float(lambda_factor),
                         None if power_v0 is None else _need(power_v0, torch.complex64, "power_v0", dev).data_ptr(),
-                        None, None)
+                        None, None, _anchor(anchor))
     n = len(ops)
     carr = (_b.ExpencOp * n)(*[op._c for op in ops])
     yp = (ctypes.c_void_p * n)(*[t.data_ptr() for t in ybs])

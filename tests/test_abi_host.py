@@ -172,6 +172,24 @@ def test_launch_shape_width_and_batch_launch_validation():
     assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) > 0
 
 
+def test_anchor_mode_is_validated():
+    """The split forms' anchor mode (ENDS, FP32, SPLIT) and the reserved
+    option field are checked on the host before any launch."""
+    b, lib = _lib()
+    op = _op(b)
+    arr = (b.ExpencOp * 1)(op)
+    opts = b.FistaOpts(2, b.FP16_SPLIT, 1, 2, 0, 0, 0, 0, 0, 0, 1.0, 1.0, 0.0, None, None, None)
+    assert opts.anchor == b.EXPENC_ANCHOR_ENDS      # the default of a zero-filled struct
+    for mode in (b.EXPENC_ANCHOR_ENDS, b.EXPENC_ANCHOR_FP32, b.EXPENC_ANCHOR_SPLIT):
+        opts.anchor = mode
+        assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) > 0
+    opts.anchor = 3
+    assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) == 0
+    opts.anchor = 0
+    opts.reserved = 1
+    assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) == 0
+
+
 def test_size_limits_are_reported_by_planning():
     """The documented size limits reach the caller as status codes before
     any device work: grids above 2^26 pixels and more than 2^31 samples are

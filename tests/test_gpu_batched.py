@@ -322,7 +322,8 @@ def test_grouped_launch_is_bitwise_equal_to_forked(prec, n_groups):
     per pass, groups in lock step) against each group's own launches on
     forked streams: the same tiles with the same arithmetic, so the results
     are bit-identical.  30 iterations cover the first gradient from the
-    lambda rule, split-difference iterations and FP32 anchors; 10 groups take
+    lambda rule, split-difference iterations, split anchors and the last
+    iteration's FP32 anchor; 10 groups take
     two grouped launches per pass (at most 8 groups each)."""
     ee = _ee()
     ws = _many_groups(n_groups, 30) if n_groups > 3 else _mixed_workloads(n_per=2, n_iter=30)

@@ -47,6 +47,21 @@ def test_full_size_fista_matches_golden(mm15, prec):
     assert e <= 1e-5
 
 
+@pytest.mark.parametrize("anchor", ["fp32", "split"])
+def test_full_size_fista_anchor_modes_match_golden(mm15, anchor):
+    """The other two anchor modes of the split forms (every anchor in FP32
+    at its cadence of 25, every anchor but the first in fp16 split at 5) on
+    the full-size solve: both within 1e-5 of the FP64 solve."""
+    import paper_2211_07532_amd as ee
+    w, case, y, g = mm15
+    v0 = case.to_dev(c64(synth.power_start(w.npix, int(g["power_seed"]))))
+    res = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision="fp16", lipschitz=0.0,
+                   power_v0=v0, n_power=int(g["n_power"]), lam=-1.0, lambda_factor=1e-3, anchor=anchor)
+    e = solve.nrmse(res.x.cpu().numpy().reshape(-1), g["x_hat"])
+    print(f"golden fp16 anchor={anchor}: NRMSE {e:.2e}", flush=True)
+    assert e <= 1e-5
+
+
 BALANCED = os.path.join(os.path.dirname(__file__), "golden", "mm15_balanced.npz")
 
 

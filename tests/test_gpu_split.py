@@ -5,7 +5,8 @@ Bars: relative l2 error of A / A^H <= 1e-3 in split form (the target for the
 split operators before refinement), and, in both directions, no worse than
 5x the error level the RNE split emulation predicts for the same arithmetic
 (plus 2e-6 for the FP32 phase increments); image NRMSE after a split-form
-solve with FP32 anchors <= 1e-4.  Whole-output full-size parity is in
+solve <= 1e-4 under each anchor mode (FP32 at the ends and split
+between, all FP32, all split after the first).  Whole-output full-size parity is in
 test_gpu_fullsize.py.  The solid-harmonic adjoint forms its phase row by row
 over 32-pixel blocks: the 13 px grid (rows padded to 16) has every block
 continue into the next row, the 20 and 32 px grids (rows padded to 32) none,
@@ -62,10 +63,11 @@ def test_split_operators(prec, name, sh):
     assert e_adj0 <= 5 * emu_a + 2e-6
 
 
+@pytest.mark.parametrize("anchor", ["ends", "fp32", "split"])
 @pytest.mark.parametrize("sh", [False, True], ids=["maps", "sh"])
 @pytest.mark.parametrize("prec", ["bf16", "fp16"])
 @pytest.mark.parametrize("variant", ["tiny", "padded-db4"])
-def test_split_fista_with_anchors(prec, variant, sh):
+def test_split_fista_with_anchors(prec, variant, sh, anchor):
     ee = _ee()
     if variant == "tiny":
         w = synth.TINY
@@ -78,14 +80,14 @@ def test_split_fista_with_anchors(prec, variant, sh):
     lam = solve.lambda_rule(op, y)
     ref = solve.fista(op, y, L, lam, w.n_iter, w.levels, w.wavelet, w.n_pad)
     res = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam,
-                   refine_every=10)
+                   refine_every=10, anchor=anchor)
     e = solve.nrmse(res.x.cpu().numpy().reshape(-1), ref)
     # without intermediate anchors (only the first and the last iteration are exact)
     res0 = ee.fista(case.to_dev(y), case.op, w.n_iter, w.levels, w.wavelet, precision=prec, lipschitz=L, lam=lam,
-                    refine_every=10 ** 6)
+                    refine_every=10 ** 6, anchor=anchor)
     e0 = solve.nrmse(res0.x.cpu().numpy().reshape(-1), ref)
-    print(f"split FISTA {prec} {variant} sh={sh}: NRMSE {e:.2e} (anchored every 10), {e0:.2e} (no intermediate anchor)",
-          flush=True)
+    print(f"split FISTA {prec} {variant} sh={sh} anchor={anchor}: NRMSE {e:.2e} (anchored every 10), "
+          f"{e0:.2e} (no intermediate anchor)", flush=True)
     assert e <= 1e-4
 
 
