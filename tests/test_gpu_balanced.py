@@ -91,3 +91,23 @@ def test_balanced_fista_matches_oracle(prec, name, levels):
     assert abs(res.kappa - L_A) <= 1e-12 * L_A and abs(res.lipschitz_a - L_A) <= 1e-12 * L_A
     assert el <= 1.0 + 1e-6
     assert e <= (1e-5 if prec == "fp32" else 1e-4)
+
+
+@pytest.mark.parametrize("anchor", ["ends", "fp32", "split"])
+def test_balanced_fista_anchor_modes_match_oracle(anchor):
+    """The balanced solver's split form (fp16) under each anchor mode against
+    the FP64 oracle's balanced FISTA, with the oracle's weights passed in."""
+    import paper_2211_07532_amd as ee
+    import torch
+    w = synth.Workload("bal", 20, 0.2, 6, 900, 3e-6, 2.0, 16, 80.0, 20.0, 12, "db4", 1, 71)
+    case = Case(w, sh=True)
+    op = solve.Operator(case.smaps, case.coef, case.time, case.basis_np, case.dw0, w.n)
+    y = c64(op.A(case.x_noisy))
+    L_A = solve.power_lipschitz(op, c64(synth.power_start(w.npix, 3)), 30)
+    lam = bal.sigma_weights(bal.swt2(op.AH(y).reshape(w.n, w.n), 1, "db4"), 1)
+    ref = bal.fista(op, y, L_A, L_A, lam, w.n_iter, 1, "db4")
+    res = ee.fista_balanced(case.to_dev(y), case.op, w.n_iter, 1, "db4", precision="fp16", lipschitz=L_A,
+                            lam=torch.from_numpy(lam).cuda(), refine_every=4, anchor=anchor)
+    e = solve.nrmse(res.x.cpu().numpy().reshape(-1), ref.reshape(-1))
+    print(f"[case] balanced fp16 anchor={anchor}: NRMSE {e:.2e}", flush=True)
+    assert e <= 1e-4

@@ -76,6 +76,40 @@ def test_mixed_batch_matches_oracle_and_single_solves(prec):
         assert e <= bar
 
 
+@pytest.mark.parametrize("anchor", ["fp32", "split"])
+def test_batched_anchor_modes_match_oracle_and_single_solves(anchor):
+    """The batched solver under the two other anchor modes (all anchors in
+    FP32 at cadence 17; all anchors after the first in the split form at
+    cadence 5), bf16: each size class against the FP64 oracle and every
+    problem against its single solve with the same mode."""
+    ee = _ee()
+    ws = _mixed_workloads()
+    cases = [Case(w, sh=True) for w in ws]
+    ops = [_oracle_op(c) for c in cases]
+    ys = [c64(o.A(c.x_noisy)) for o, c in zip(ops, cases)]
+    rmax = max(w.npix for w in ws)
+    v0 = c64(synth.power_start(rmax, 11))
+    n_power = 25
+    print(f"[case] batched bf16 anchor={anchor}: {len(ws)} problems", flush=True)
+    xs = ee.fista_batched([c.to_dev(y) for c, y in zip(cases, ys)], [c.op for c in cases], ws[0].n_iter,
+                          ws[0].levels, "db4", precision="bf16", lipschitz=0.0, power_v0=cases[0].to_dev(v0),
+                          n_power=n_power, lam=-1.0, lambda_factor=1e-3, anchor=anchor)
+    for k in range(3):
+        w, op, y = ws[k], ops[k], ys[k]
+        L = solve.power_lipschitz(op, v0[:w.npix], n_power)
+        ref = solve.fista(op, y, L, solve.lambda_rule(op, y), w.n_iter, w.levels, w.wavelet, w.n_pad)
+        e = solve.nrmse(xs[k].cpu().numpy().reshape(-1), ref)
+        print(f"  problem {k} (n={w.n}): NRMSE vs oracle {e:.2e}", flush=True)
+        assert e <= 1e-4
+    for k, (c, y) in enumerate(zip(cases, ys)):
+        single = ee.fista(c.to_dev(y), c.op, ws[k].n_iter, ws[k].levels, "db4", precision="bf16", lipschitz=0.0,
+                          power_v0=c.to_dev(v0[:ws[k].npix]), n_power=n_power, lam=-1.0, lambda_factor=1e-3,
+                          anchor=anchor)
+        e = rel(xs[k].cpu().numpy(), single.x.cpu().numpy())
+        print(f"  problem {k}: batched vs single {e:.2e}", flush=True)
+        assert e <= 1e-4
+
+
 def test_batched_fp16_scales_per_problem():
     """The fp16 form's operand scales are per problem: the problems of one
     launch (two per size class here) get data scaled by very different powers
