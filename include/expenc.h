@@ -280,13 +280,15 @@ typedef struct expenc_fista_opts {
  * expenc_balanced_opts.anchor).  Every refine_every-th iteration, and the
  * last, recomputes the gradient at z_ref = z_k and later iterations add the
  * split operators' A^H A (z_k - z_ref) to it.
- *   ENDS (default, cadence 5): the anchors of the first and the last
- *     iteration in FP32, the others in the iteration's split form;
- *   FP32 (cadence 25 fp16, 17 bf16): every anchor in FP32;
- *   SPLIT (cadence 5): every anchor but the first in the split form.
+ *   SPLIT (default, 0; cadence 5): every anchor but the first in the
+ *     iteration's split form;
+ *   FP32 (cadence 25 fp16, 17 bf16): every anchor in FP32, so the solve
+ *     converges to the FP32 operator's solution (the choice for problems
+ *     whose solution is sensitive to the operator's last digits);
+ *   ENDS (cadence 5): as SPLIT, with the last iteration's anchor in FP32.
  * The first iteration's gradient is FP32 in every mode (z_0 = 0, so it is
  * -A^H y, which the lambda rule also uses). */
-enum { EXPENC_ANCHOR_ENDS = 0, EXPENC_ANCHOR_FP32 = 1, EXPENC_ANCHOR_SPLIT = 2 };
+enum { EXPENC_ANCHOR_SPLIT = 0, EXPENC_ANCHOR_FP32 = 1, EXPENC_ANCHOR_ENDS = 2 };
 
 /*
  * CS reconstruction: FISTA on eq. 1 exactly as written (no 1/2 on the data
@@ -370,8 +372,8 @@ int fista_solve_batched(int32_t nprob, const expenc_op *ops, int32_t batch, cons
  * threshold tau_b = lambda_b / L and the FISTA momentum; x = W^H alpha_K
  * ([B][ny][nx]).  Weights: opts->lambda ([B][3J+1] device) or, when NULL,
  * lambda_scale * sigma/2 from W A^H y (FP32 operators).  Split precisions use
- * the anchored gradient of fista_solve (every refine_every-th and the last
- * iteration exact in FP32).  The loop is captured into a cached HIP graph.
+ * the anchored gradient of fista_solve (the gradient recomputed every
+ * refine_every-th and at the last iteration, see EXPENC_ANCHOR_*).  The loop is captured into a cached HIP graph.
  * scalars (device, optional): [L_A, kappa, L, lambda[B][3J+1], tau[B][3J+1]].
  */
 typedef struct expenc_balanced_opts {

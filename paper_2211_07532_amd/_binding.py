@@ -20,7 +20,7 @@ EXPENC_ENONFINITE = -5
 EXPENC_EDIVERGED = -6
 EXPENC_BATCH_FORKED = 0
 EXPENC_BATCH_GROUPED = 1
-EXPENC_ANCHOR_ENDS, EXPENC_ANCHOR_FP32, EXPENC_ANCHOR_SPLIT = 0, 1, 2
+EXPENC_ANCHOR_SPLIT, EXPENC_ANCHOR_FP32, EXPENC_ANCHOR_ENDS = 0, 1, 2
 
 FP32, BF16_SPLIT, FP16_SPLIT = 0, 1, 2
 HAAR, DB4 = 0, 1

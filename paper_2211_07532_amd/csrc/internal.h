@@ -316,7 +316,8 @@ uint64_t hash_bytes(uint64_t h, const void *p, size_t n);
 // ||z - z_ref||, so frequent anchors help, and an anchor formed in the split
 // form costs no more than a difference iteration: the split-anchored modes
 // refresh every 5 iterations (1.5 mm, 50 iterations: final image 2.8e-6
-// fp16, 3.3e-6 bf16 against the FP64 solve).  Anchors all in FP32 cost a
+// fp16, 3.3e-6 bf16 against the FP64 solve, the same with the last anchor
+// in FP32).  Anchors all in FP32 cost a
 // full FP32 A and A^H each and keep the earlier cadences, which held the
 // image within 1e-5 (4.9e-6 fp16 at 25, 6.9e-6 bf16 at 17).
 inline int default_refine(int32_t precision, int32_t anchor) {

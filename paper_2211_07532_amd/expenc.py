@@ -27,7 +27,7 @@ PRECISIONS = {"fp32": FP32, "bf16": BF16_SPLIT, "bf16_split": BF16_SPLIT, "fp16"
               "fp16_split": FP16_SPLIT}
 WAVELETS = {"haar": HAAR, "db4": DB4}
 # anchors of the split forms' gradient (see EXPENC_ANCHOR_* in include/expenc.h)
-ANCHORS = {"ends": _b.EXPENC_ANCHOR_ENDS, "fp32": _b.EXPENC_ANCHOR_FP32, "split": _b.EXPENC_ANCHOR_SPLIT}
+ANCHORS = {"split": _b.EXPENC_ANCHOR_SPLIT, "fp32": _b.EXPENC_ANCHOR_FP32, "ends": _b.EXPENC_ANCHOR_ENDS}
 
 
 def _prec(p) -> int:
@@ -259,10 +259,11 @@ class FistaResult:
 def fista(y: torch.Tensor, op: Operator, n_iter: int, levels: int, wavelet="db4", precision="fp32",
           lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3, power_v0=None,
           n_power: int = 30, nx_pad: int = 0, ny_pad: int = 0, ista: bool = False, refine_every: int = 0,
-          trace: bool = False, sync_scalars: bool = True, check_status: bool = True, anchor="ends"):
+          trace: bool = False, sync_scalars: bool = True, check_status: bool = True, anchor="split"):
     """FISTA on eq. 1 (see fista_solve in include/expenc.h).  Returns a FistaResult.
-    anchor: precision of the split forms' gradient anchors, "ends" (FP32 at
-    the first and last iteration, split in between), "fp32" or "split".
+    anchor: precision of the split forms' gradient anchors, "split" (every
+    anchor after the first in the split form), "fp32" (every anchor in FP32)
+    or "ends" (as "split" with the last one in FP32).
     With sync_scalars the call waits for the solve and reads its status word:
     a non-finite iterate (or, with trace=True, an objective above F(0))
     raises ExpencError when check_status, else is returned in .status."""
@@ -403,7 +404,7 @@ class BalancedResult:
 def fista_balanced(y: torch.Tensor, op: Operator, n_iter: int, levels: int = 1, wavelet="db4", precision="fp32",
                    lipschitz: float = 0.0, kappa: float = -1.0, lam: Optional[torch.Tensor] = None,
                    lambda_scale: float = 1.0, power_v0=None, n_power: int = 30, ista: bool = False,
-                   refine_every: int = 0, anchor="ends") -> BalancedResult:
+                   refine_every: int = 0, anchor="split") -> BalancedResult:
     """Balanced FISTA with the undecimated wavelet (see fista_balanced_solve in include/expenc.h)."""
     single = y.dim() == 2
     yb = y.reshape(1 if single else y.shape[0], op.nsamples, op.ncoils)
@@ -443,7 +444,7 @@ _batch_ws = {}
 def fista_batched(ys: Sequence[torch.Tensor], ops: Sequence[Operator], n_iter: int, levels: int, wavelet="db4",
                   precision="fp32", lipschitz: float = 0.0, lam: float = -1.0, lambda_factor: float = 1e-3,
                   power_v0=None, n_power: int = 30, ista: bool = False, refine_every: int = 0,
-                  check_status: bool = False, launch: str = "forked", anchor="ends"):
+                  check_status: bool = False, launch: str = "forked", anchor="split"):
     """Independent FISTA solves of problems (ys[i], ops[i]) in one call (see
     fista_solve_batched in include/expenc.h).  Every ys[i] is [T_i][C_i] (or
     [B][T_i][C_i] with one B for all).  Returns the list of x_i.  With

@@ -173,14 +173,14 @@ def test_launch_shape_width_and_batch_launch_validation():
 
 
 def test_anchor_mode_is_validated():
-    """The split forms' anchor mode (ENDS, FP32, SPLIT) and the reserved
+    """The split forms' anchor mode (SPLIT, FP32, ENDS) and the reserved
     option field are checked on the host before any launch."""
     b, lib = _lib()
     op = _op(b)
     arr = (b.ExpencOp * 1)(op)
     opts = b.FistaOpts(2, b.FP16_SPLIT, 1, 2, 0, 0, 0, 0, 0, 0, 1.0, 1.0, 0.0, None, None, None)
-    assert opts.anchor == b.EXPENC_ANCHOR_ENDS      # the default of a zero-filled struct
-    for mode in (b.EXPENC_ANCHOR_ENDS, b.EXPENC_ANCHOR_FP32, b.EXPENC_ANCHOR_SPLIT):
+    assert opts.anchor == b.EXPENC_ANCHOR_SPLIT     # the default of a zero-filled struct
+    for mode in (b.EXPENC_ANCHOR_SPLIT, b.EXPENC_ANCHOR_FP32, b.EXPENC_ANCHOR_ENDS):
         opts.anchor = mode
         assert lib.fista_batched_workspace_size(1, arr, 1, ctypes.byref(opts)) > 0
     opts.anchor = 3

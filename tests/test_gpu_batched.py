@@ -76,12 +76,12 @@ def test_mixed_batch_matches_oracle_and_single_solves(prec):
         assert e <= bar
 
 
-@pytest.mark.parametrize("anchor", ["fp32", "split"])
+@pytest.mark.parametrize("anchor", ["fp32", "ends"])
 def test_batched_anchor_modes_match_oracle_and_single_solves(anchor):
     """The batched solver under the two other anchor modes (all anchors in
-    FP32 at cadence 17; all anchors after the first in the split form at
-    cadence 5), bf16: each size class against the FP64 oracle and every
-    problem against its single solve with the same mode."""
+    FP32 at cadence 17; split anchors at cadence 5 with the last one in
+    FP32), bf16: each size class against the FP64 oracle and every problem
+    against its single solve with the same mode."""
     ee = _ee()
     ws = _mixed_workloads()
     cases = [Case(w, sh=True) for w in ws]

@@ -47,11 +47,11 @@ def test_full_size_fista_matches_golden(mm15, prec):
     assert e <= 1e-5
 
 
-@pytest.mark.parametrize("anchor", ["fp32", "split"])
+@pytest.mark.parametrize("anchor", ["fp32", "ends"])
 def test_full_size_fista_anchor_modes_match_golden(mm15, anchor):
     """The other two anchor modes of the split forms (every anchor in FP32
-    at its cadence of 25, every anchor but the first in fp16 split at 5) on
-    the full-size solve: both within 1e-5 of the FP64 solve."""
+    at its cadence of 25; split anchors at 5 with the last one in FP32) on
+    the full-size fp16 solve: both within 1e-5 of the FP64 solve."""
     import paper_2211_07532_amd as ee
     w, case, y, g = mm15
     v0 = case.to_dev(c64(synth.power_start(w.npix, int(g["power_seed"]))))
