@@ -288,7 +288,70 @@ __device__ inline int wrap(int i, int n) {
   return i;
 }
 
+// wrap for an index known to lie in [-n, 2n) (FAST: two selects, no
+// branch), else the general form
+template <bool FAST>
+__device__ inline int wrap_in(int i, int n) {
+  if constexpr (FAST) {
+    i += i < 0 ? n : 0;
+    i -= i >= n ? n : 0;
+    return i;
+  } else {
+    return wrap(i, n);
+  }
+}
+
 __device__ inline double2 widen(float2 v) { return make_double2(v.x, v.y); }
+
+// Staging of a level's input footprint (RY x RX from row 2 ty0, column
+// 2 tx0, periodic) into LDS: every load is issued before the first LDS store
+// and none sits under a branch, so a thread waits for memory once.  The tail
+// index is clamped (a repeated load, not stored).
+template <int RY, int RX, bool FAST>
+__device__ inline void stage_analysis(const float2 *__restrict__ in, int istride, int tx0, int ty0, int mx, int my,
+                                      float2 (*dst)[RX]) {
+  constexpr int NIN = RY * RX, NLD = (NIN + 255) / 256;
+  float2 ld[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = min((int)threadIdx.x + 256 * k, NIN - 1);
+    const int r = i / RX, c = i - r * RX;
+    ld[k] = in[(int64_t)wrap_in<FAST>(2 * ty0 + r, my) * istride + wrap_in<FAST>(2 * tx0 + c, mx)];
+  }
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < NIN) dst[i / RX][i % RX] = ld[k];
+  }
+}
+
+// Staging of a synthesis tile's coefficients: NY x NX of each quarter (LL
+// from ll, the detail bands from w's level block) into sc [2 NY][2 NX] in
+// FP64, loads first as above.
+template <int NY, int NX, bool FAST>
+__device__ inline void stage_synthesis(const float2 *__restrict__ llb, int lstride, const float2 *__restrict__ wb,
+                                       int nx, int i0, int j0, int hx, int hy, double2 (*sc)[2 * NX]) {
+  constexpr int NIN = 4 * NY * NX, NLD = (NIN + 255) / 256;
+  float2 ld[NLD];
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = min((int)threadIdx.x + 256 * k, NIN - 1);
+    const int r = i / (2 * NX), c = i - r * (2 * NX);
+    const bool rh = r >= NY, ch = c >= NX;
+    const int gy = wrap_in<FAST>(i0 + (rh ? r - NY : r), hy), gx = wrap_in<FAST>(j0 + (ch ? c - NX : c), hx);
+    const float2 *src = (!rh && !ch) ? llb + (int64_t)gy * lstride + gx
+                                     : wb + (int64_t)(rh ? hy + gy : gy) * nx + (ch ? hx + gx : gx);
+    ld[k] = *src;
+  }
+#pragma unroll
+  for (int k = 0; k < NLD; ++k) {
+    const int i = threadIdx.x + 256 * k;
+    if (i < NIN) {
+      const int r = i / (2 * NX), c = i - r * (2 * NX);
+      sc[r][c] = widen(ld[k]);
+    }
+  }
+}
 // FP32 rounding of an intermediate pass result, kept in FP64 form
 __device__ inline double2 round32(double x, double y) { return make_double2((float)x, (float)y); }
 
@@ -313,10 +376,12 @@ __global__ __launch_bounds__(256) void k_dwt2_level(const float2 *__restrict__ i
   const int hx = mx >> 1, hy = my >> 1;
   const int tx0 = blockIdx.x * kFwdTX, ty0 = blockIdx.y * kFwdTY;
   in += b * ipitch;
-  for (int i = threadIdx.x; i < RY * RX; i += blockDim.x) {
-    const int r = i / RX, c = i % RX;
-    sin_[r][c] = in[(int64_t)wrap(2 * ty0 + r, my) * istride + wrap(2 * tx0 + c, mx)];
-  }
+  // footprint rows 2 ty0 .. 2 ty0 + RY - 1 < 2 my (and columns) when the
+  // level is at least as large as the footprint
+  if (RY <= my && RX <= mx)
+    stage_analysis<RY, RX, true>(in, istride, tx0, ty0, mx, my, sin_);
+  else
+    stage_analysis<RY, RX, false>(in, istride, tx0, ty0, mx, my, sin_);
   __syncthreads();
   // rows: low and high outputs at tile column x for every staged row
   for (int i = threadIdx.x; i < RY * kFwdTX; i += blockDim.x) {
@@ -402,13 +467,12 @@ __global__ __launch_bounds__(256) void k_idwt2_level(const float2 *__restrict__ 
   const int m0 = blockIdx.y * kInvTY, n0 = blockIdx.x * kInvTX;
   const int i0 = m0 / 2 - H + 1, j0 = n0 / 2 - H + 1;
   const float2 *wb = w + b * wpitch;
-  for (int i = threadIdx.x; i < 4 * NY * NX; i += blockDim.x) {
-    const int r = i / (2 * NX), c = i - r * (2 * NX);
-    const bool rh = r >= NY, ch = c >= NX;
-    const int gy = wrap(i0 + (rh ? r - NY : r), hy), gx = wrap(j0 + (ch ? c - NX : c), hx);
-    sc[r][c] = widen((!rh && !ch) ? ll[b * lpitch + (int64_t)gy * lstride + gx]
-                                  : wb[(int64_t)(rh ? hy + gy : gy) * nx + (ch ? hx + gx : gx)]);
-  }
+  // coefficient rows i0 .. i0 + NY - 1 lie in [-hy, 2 hy) (and columns)
+  // when the level is at least as large as the footprint (i0 >= 1 - H)
+  if (NY <= hy && NX <= hx)
+    stage_synthesis<NY, NX, true>(ll + b * lpitch, lstride, wb, nx, i0, j0, hx, hy, sc);
+  else
+    stage_synthesis<NY, NX, false>(ll + b * lpitch, lstride, wb, nx, i0, j0, hx, hy, sc);
   __syncthreads();
   // columns: output rows 2p, 2p + 1 at every staged column
   for (int i = threadIdx.x; i < (kInvTY / 2) * 2 * NX; i += blockDim.x) {
