@@ -539,8 +539,23 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
     for (int c = sub; c < C; c += 32) {
       const int col = b * C + c;
       double ux = 0.0, uy = 0.0;
-      for (int k = 0; k < nsplit; ++k) {
-        float2 v = part[((int64_t)k * Rp + rq) * NCP + col];
+      const float2 *pk = part + rq * NCP + col;
+      const int64_t step = (int64_t)Rp * NCP;
+      int k = 0;
+      // eight splits per step with their loads in flight together, summed in
+      // split order; then the rest one by one
+      for (; k + 8 <= nsplit; k += 8) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pk[(k + u) * step];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          ux += v[u].x;
+          uy += v[u].y;
+        }
+      }
+      for (; k < nsplit; ++k) {
+        const float2 v = pk[k * step];
         ux += v.x;
         uy += v.y;
       }
@@ -606,7 +621,20 @@ __global__ __launch_bounds__(256) void k_adj_reduce_comb(const float2 *__restric
   }
   const int64_t rq = (int64_t)yy * nxq + xx;
   double sx = 0.0, sy = 0.0;
-  for (int k0 = j; k0 < nslice; k0 += 32) {
+  int k0 = j;
+  // steps whose eight slices exist for all four lanes: unconditional loads,
+  // all in flight before the first add
+  for (; k0 - j + 31 < nslice; k0 += 32) {
+    float2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(int64_t)(k0 + 4 * u) * Rp + rq];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sx += v[u].x;
+      sy += v[u].y;
+    }
+  }
+  if (k0 < nslice) {
     float2 v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u)

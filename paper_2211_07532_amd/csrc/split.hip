@@ -541,26 +541,39 @@ __global__ __launch_bounds__(256) void k_build_z_split(const float2 *__restrict_
   const int64_t q = (id >> 6) / NGP;
   const int col = 16 * g + (lane & 15);
   const int im = (lane >> 4) & 1;
+  // the 8 pixels of this lane: every load is issued before the arithmetic
+  // (outside pixels and columns read an in-bounds element and give 0)
+  const int rq0 = (int)(16 * q + 8 * (lane >> 5));
+  int yy = rq0 / nxq, xx = rq0 - yy * nxq;
+  const bool colok = col < NC;
+  const int b = colok ? col / C : 0, c = colok ? col % C : 0;
+  float2 u[8], w[8], sv[8];
+  bool ok[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    ok[i] = yy < ny && xx < nx && colok;
+    const int yc = ok[i] ? yy : 0, xc = ok[i] ? xx : 0;
+    const int64_t o = b * x_stride + (int64_t)yc * x_row_stride + xc;
+    u[i] = x[o];
+    w[i] = xsub ? xsub[o] : make_float2(0.f, 0.f);
+    // (the S table, when given, holds the same value in row-major order)
+    sv[i] = sq ? sq[(int64_t)(rq0 + i) * NGP * 16 + col] : smaps[(int64_t)c * R + yc * nx + xc];
+    if (++xx == nxq) {
+      xx = 0;
+      ++yy;
+    }
+  }
   float b1[8], b2[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
-    const int rq = (int)(16 * q + 8 * (lane >> 5) + i);
-    const int yy = rq / nxq, xx = rq % nxq;
-    float2 z = make_float2(0.f, 0.f);
-    if (yy < ny && xx < nx && col < NC) {
-      const int b = col / C, c = col % C;
-      const int r = yy * nx + xx;
-      const int64_t o = b * x_stride + (int64_t)yy * x_row_stride + xx;
-      float2 u = x[o];
-      if (xsub) {
-        const float2 w = xsub[o];
-        u.x -= w.x;
-        u.y -= w.y;
-      }
-      // (the S table, when given, holds the same value in row-major order)
-      const float2 s = sq ? sq[(int64_t)rq * NGP * 16 + col] : smaps[(int64_t)c * R + r];
-      z = make_float2((s.x * u.x - s.y * u.y) * sc, (s.x * u.y + s.y * u.x) * sc);
+    float2 uu = u[i];
+    if (xsub) {
+      uu.x -= w[i].x;
+      uu.y -= w[i].y;
     }
+    const float2 s = sv[i];
+    const float2 z = ok[i] ? make_float2((s.x * uu.x - s.y * uu.y) * sc, (s.x * uu.y + s.y * uu.x) * sc)
+                           : make_float2(0.f, 0.f);
     b1[i] = im ? z.y : z.x;
     b2[i] = im ? z.x : -z.y;
   }
