@@ -44,13 +44,13 @@ N_POWER = 20
 TRAFFIC = {
     "fp32": {"kernel": "k_adj_f32_sh<2, false>", "adj_split": 45, "bytes": 290732933,
              "valu_instr": 158732000, "fwd_valu_instr": 121229000,
-             "sha": "3595930babf329e24a0f2c71317771f224fbd22d7bfdcd079c81c1363a013891"},
+             "sha": "7fa5f7b971fa7122a4a604e28a063374c30d25ee0e3a2a846b8bd5236d2f19e5"},
     "bf16": {"kernel": "k_adj_split_sh<2, true, false>", "adj_split": 32, "bytes": 137413018,
              "valu_instr": 65876700, "fwd_valu_instr": 106418000,
-             "sha": "ef7e2c902d5e4d5576219405bf64754d0cc8552bed7c6f8c329ed6c2d4fe2986"},
+             "sha": "b0bac08117197211999e145b3dde291d8fbcbc7f7a345ffe3981196b4e092529"},
     "fp16": {"kernel": "k_adj_split_sh<2, false, false>", "adj_split": 32, "bytes": 137499034,
              "valu_instr": 65876700, "fwd_valu_instr": 87461900,
-             "sha": "ef7e2c902d5e4d5576219405bf64754d0cc8552bed7c6f8c329ed6c2d4fe2986"},
+             "sha": "b0bac08117197211999e145b3dde291d8fbcbc7f7a345ffe3981196b4e092529"},
 }
 TRAFFIC_SOURCES = {"fp32": ["encode.hip", "internal.h", "../build.py"],
                    "bf16": ["split_adj.hip", "split.hip", "split_dev.h", "internal.h", "../build.py"],

@@ -442,6 +442,28 @@ __global__ __launch_bounds__(256) void k_adj_f32_sh(const double *__restrict__ p
 // Split-K reductions (fixed summation order)
 // ---------------------------------------------------------------------------
 
+// Sum of n float2 values p[k * step], k = 0 .. n - 1, in FP64 and in k
+// order, eight loads in flight per step (a loop that loads and adds one at a
+// time waits for memory once per value).
+__device__ inline void sum_strided(const float2 *__restrict__ p, int64_t step, int n, double &sx, double &sy) {
+  int k = 0;
+  for (; k + 8 <= n; k += 8) {
+    float2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(k + u) * step];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sx += v[u].x;
+      sy += v[u].y;
+    }
+  }
+  for (; k < n; ++k) {
+    const float2 v = p[k * step];
+    sx += v.x;
+    sy += v.y;
+  }
+}
+
 // scl: the scaled form's operand powers of two ([P][2]), or NULL.
 __global__ void k_fwd_reduce_out(const float2 *__restrict__ part, int nsplit, int64_t T,
                                  int64_t Tp, int C, int NC, int NCP, float2 *__restrict__ y,
@@ -454,11 +476,7 @@ __global__ void k_fwd_reduce_out(const float2 *__restrict__ part, int nsplit, in
   int64_t t = i / NC;
   int col = (int)(i % NC);
   double sx = 0.0, sy = 0.0;
-  for (int k = 0; k < nsplit; ++k) {
-    float2 v = part[((int64_t)k * Tp + t) * NCP + col];
-    sx += v.x;
-    sy += v.y;
-  }
+  sum_strided(part + t * NCP + col, Tp * NCP, nsplit, sx, sy);
   if (scl) {
     const double inv = 1.0 / scl[2 * pz];
     sx *= inv;
@@ -483,11 +501,7 @@ __global__ void k_fwd_residual(const float2 *__restrict__ part, int nsplit, int6
   int col = (int)(i % NCP);
   double sx = 0.0, sy = 0.0;
   if (t < T && col < NC) {
-    for (int k = 0; k < nsplit; ++k) {
-      float2 v = part[((int64_t)k * Tp + t) * NCP + col];
-      sx += v.x;
-      sy += v.y;
-    }
+    sum_strided(part + t * NCP + col, Tp * NCP, nsplit, sx, sy);
     if (y_meas) {
       const int b = col / C, c = col % C;
       const float2 m = y_meas[((int64_t)b * T + t) * C + c];
@@ -539,26 +553,7 @@ __global__ __launch_bounds__(256) void k_adj_reduce_out(const float2 *__restrict
     for (int c = sub; c < C; c += 32) {
       const int col = b * C + c;
       double ux = 0.0, uy = 0.0;
-      const float2 *pk = part + rq * NCP + col;
-      const int64_t step = (int64_t)Rp * NCP;
-      int k = 0;
-      // eight splits per step with their loads in flight together, summed in
-      // split order; then the rest one by one
-      for (; k + 8 <= nsplit; k += 8) {
-        float2 v[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = pk[(k + u) * step];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          ux += v[u].x;
-          uy += v[u].y;
-        }
-      }
-      for (; k < nsplit; ++k) {
-        const float2 v = pk[k * step];
-        ux += v.x;
-        uy += v.y;
-      }
+      sum_strided(part + rq * NCP + col, (int64_t)Rp * NCP, nsplit, ux, uy);
       float2 s = smaps[(int64_t)c * R + r];
       sx += s.x * ux + s.y * uy;  // conj(s) * u
       sy += s.x * uy - s.y * ux;
